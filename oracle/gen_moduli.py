@@ -1,0 +1,50 @@
+"""Write oracle/moduli.txt: the conventional modulus of each degree used by
+the tests, found by the oracle's own search (orc_find_modulus).
+
+Usage:  python -m oracle.gen_moduli [q ...]
+
+Each line holds the exponents of P in decreasing order (q first, 0 last).
+Calls only code under oracle/.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import oracle
+
+DEFAULT_DEGREES = (
+    list(range(2, 65))
+    + [80, 96, 128, 160, 192, 224]
+    + list(range(256, 1025, 64))
+    + [1536, 2048, 3072, 4096, 8192, 16384]
+)
+
+
+def main(argv):
+    degrees = [int(a) for a in argv] if argv else DEFAULT_DEGREES
+    table = dict(oracle._read_table())
+    for q in degrees:
+        if q in table:
+            continue
+        t0 = time.time()
+        table[q] = oracle.find_modulus(q)
+        print("q=%d %r  %.1fs" % (q, table[q], time.time() - t0), flush=True)
+        _write(table)
+    _write(table)
+
+
+def _write(table):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "moduli.txt")
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write("# exponents of the conventional modulus P of degree q (q first, 0 last):\n")
+        f.write("# lowest weight, then lexicographically smallest; written by oracle/gen_moduli.py\n")
+        for q in sorted(table):
+            f.write(" ".join(str(v) for v in table[q]) + "\n")
+    os.replace(tmp, path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
