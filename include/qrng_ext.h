@@ -1,0 +1,186 @@
+/*
+ * qrng_ext.h -- C ABI of the MI355X (gfx950) block-wise two-source extractor.
+ *
+ * Operation (Li & Zhou, "Real-Time Seedless Post-Processing for Quantum
+ * Random Number Generators"):
+ *
+ *   Two independent raw sample streams X and Y (b bits per sample, Sec. 3)
+ *   are cut into consecutive blocks of n bits (Algorithm 1, equal blocks).
+ *   Block l of X and block l of Y are each read as n_e = n/m elements of
+ *   F_{2^m}, and the pair is mapped to the m-bit inner product
+ *       Z^(l) = sum_{i<n_e} x_i * y_i          (Def. 3.2, Ext_IP^{n_e, m})
+ *   in F_{2^m} (addition = bitwise XOR, Sec. 3.2).  The output stream is
+ *   Z^(0) Z^(1) Z^(2) ... in block order (Thm. 3.6, Thm. 3.7).
+ *
+ * Conventions (the paper leaves them open; fixed here, identical for every
+ * entry point):
+ *   - F_{2^m} = GF(2)[t]/(P), polynomial basis: bit j of an element is the
+ *     coefficient of t^j.  P is the lowest-weight irreducible polynomial of
+ *     degree m, ties broken by the lexicographically smallest exponent tuple
+ *     (trinomial t^m+t^a+1 with least a, else pentanomial
+ *     t^m+t^a+t^b+t^c+1 with least a, then b, then c), unless the caller
+ *     supplies other taps in ext_params.
+ *   - bit r of a block is bit (r mod 8) of byte r/8 of the block (LSB first;
+ *     for 8-bit samples a block is exactly n/8 consecutive samples, and the
+ *     bytes are used as they are);
+ *   - element i of a block is block bits [i*m, (i+1)*m);
+ *   - block l of a stream is stream bytes [l*n/8, (l+1)*n/8);
+ *   - output coefficient j of Z^(l) is output bit l*m + j, bytes LSB first
+ *     (m/8 bytes per block pair, little-endian 32-bit words).
+ *
+ * Supported shapes on the GPU path: m a multiple of 32 whose odd part
+ * (m/32 with all factors 2 removed) is at most 15, n a multiple of m,
+ * and every non-leading exponent of P below m/2.  Everything else returns
+ * EXT_ENOTSUP.
+ *
+ * Errors: every call returns EXT_OK (0) or a negative ext_status; no call
+ * aborts or throws.  A HIP failure is reported as EXT_EDEVICE and is sticky:
+ * every later call on that context returns EXT_EDEVICE.
+ *
+ * Threading: one thread at a time per context (and per stream); distinct
+ * contexts may be used concurrently.
+ */
+#ifndef QRNG_EXT_H
+#define QRNG_EXT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ext_ctx ext_ctx;       /* opaque: shape, modulus, device buffers */
+typedef struct ext_stream ext_stream; /* opaque: one (X, Y) channel pair */
+
+enum ext_status {
+    EXT_OK = 0,
+    EXT_EINVAL = -1,  /* bad argument */
+    EXT_ENOTSUP = -2, /* shape or modulus outside what the GPU path supports */
+    EXT_ENOMEM = -3,  /* host or device allocation failed */
+    EXT_EAGAIN = -4,  /* admission: the stream's device buffer is full, poll and retry */
+    EXT_EDEVICE = -5, /* HIP runtime error (sticky on the context) */
+    EXT_ECLOSED = -6  /* stream already closed */
+};
+
+enum ext_mem_kind {
+    EXT_MEM_HOST = 0,  /* pointers passed to ext_extract/ext_submit/ext_poll are host memory */
+    EXT_MEM_DEVICE = 1 /* they are device memory of the context's device */
+};
+
+typedef struct {
+    uint32_t sample_bits;       /* b, bits per raw sample; 0 means 8.  m % b must be 0
+                                   (the paper makes m a multiple of b, Algorithm 1). */
+    uint32_t n_taps;            /* 0: conventional modulus; 1: trinomial; 3: pentanomial */
+    uint32_t taps[3];           /* non-leading nonzero exponents of P, any order
+                                   (P = t^m + sum t^taps[k] + 1); checked irreducible */
+    uint32_t mem_kind;          /* enum ext_mem_kind */
+    void *hip_stream;           /* hipStream_t to run on (NULL is the null stream) */
+    uint32_t use_hip_stream;    /* 1: run on hip_stream; 0: the library creates a stream */
+    uint64_t device_bytes_cap;  /* per stream: cap on pending input bytes held on the
+                                   device (admission); 0 means 256 MiB */
+    int32_t device;             /* HIP device ordinal; -1 means the current device */
+    uint32_t reserved[4];
+} ext_params;
+
+/* Fill *p with defaults (b = 8, conventional modulus, host memory, a stream
+ * of the library's own, 256 MiB cap, current device). */
+void ext_params_init(ext_params *p);
+
+/*
+ * Create a context for blocks of n_bits bits and m_bits output bits per
+ * block pair (n_e = n_bits / m_bits elements of F_{2^m}, Def. 3.2).
+ * *out is owned by the caller and released by ext_destroy.
+ * EXT_EINVAL: n_bits or m_bits zero, n_bits % m_bits, m % b, bad taps or a
+ *             reducible P.  EXT_ENOTSUP: see "Supported shapes" above.
+ */
+int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params *p, ext_ctx **out);
+
+/* Release the context and every stream still open on it (waits for queued
+ * GPU work first).  NULL is accepted. */
+int ext_destroy(ext_ctx *c);
+
+/* Exponents of the context's modulus P in decreasing order (m first, 0
+ * last).  cap >= 5 always suffices; *n receives the count. */
+int ext_get_modulus(const ext_ctx *c, uint32_t *exps, uint32_t cap, uint32_t *n);
+
+/* The conventional modulus of degree m (see Conventions) without creating a
+ * context: same output format as ext_get_modulus.  EXT_ENOTSUP if m is
+ * outside the library's table and too large to search quickly (> 4096). */
+int ext_default_modulus(uint32_t m_bits, uint32_t *exps, uint32_t cap, uint32_t *n);
+
+/* 1 if t^m + sum t^taps + 1 is irreducible over GF(2), 0 if not, <0 on a
+ * bad argument.  Rabin's test. */
+int ext_is_irreducible(uint32_t m_bits, const uint32_t *taps, uint32_t n_taps);
+
+/*
+ * Plain form (Algorithm 1 over n_pairs whole block pairs).
+ *   x, y : n_pairs * n/8 bytes each (block l at byte offset l*n/8),
+ *          4-byte aligned; 16-byte aligned device memory when m is 128
+ *          or 256 (those shapes read their operands with 16-byte loads)
+ *   out  : n_pairs * m/8 bytes, 4-byte aligned
+ * EXT_MEM_DEVICE: x, y, out are device pointers; the work is queued on the
+ *   context's stream and the call returns at once (synchronize the stream,
+ *   or call ext_sync, before reading out).  The buffers are borrowed until
+ *   that work completes.
+ * EXT_MEM_HOST: the call copies x and y to the device, runs, copies the
+ *   result to out and returns when out is complete.
+ * n_pairs == 0 is a no-op.
+ */
+int ext_extract(ext_ctx *c, const void *x, const void *y, uint64_t n_pairs, void *out);
+
+/* Wait for every piece of work queued by this context. */
+int ext_sync(ext_ctx *c);
+
+/*
+ * Streaming form.  A stream is one (X, Y) channel pair fed in arbitrary
+ * chunks; the partial block still waiting for data is kept on the device.
+ * Block l is computed as soon as both sides hold (l+1)*n/8 bytes; outputs
+ * come back from ext_poll strictly in block order, each exactly once.
+ */
+int ext_stream_open(ext_ctx *c, ext_stream **out);
+
+/*
+ * Append x_len bytes to X and y_len bytes to Y (either may be 0).  The data
+ * are copied before the call returns (host memory) or read in stream order on
+ * the context's stream (device memory, borrowed until that work is done).
+ * Launches the extraction of every block pair completed by this chunk.
+ * EXT_EAGAIN: the bytes held on the device would exceed device_bytes_cap;
+ * nothing was consumed -- poll, then submit again.
+ * *seq_out (may be NULL) receives the number of block pairs launched so far.
+ */
+int ext_submit(ext_stream *s, const void *x, size_t x_len, const void *y, size_t y_len,
+               uint64_t *seq_out);
+
+/*
+ * Non-blocking: copy finished outputs, in block order, into out (host or
+ * device memory per mem_kind), at most out_cap bytes and only whole blocks
+ * (m/8 bytes each).  *out_len receives the bytes written; *blocks_done (may
+ * be NULL) the number of blocks returned so far over the stream's life.
+ */
+int ext_poll(ext_stream *s, void *out, size_t out_cap, size_t *out_len, uint64_t *blocks_done);
+
+/* Blocking variant of ext_poll: waits until every launched block is done,
+ * then copies as ext_poll does. */
+int ext_drain(ext_stream *s, void *out, size_t out_cap, size_t *out_len, uint64_t *blocks_done);
+
+/*
+ * Close the stream: the trailing partial block (fewer than n bits on either
+ * side) is dropped and its size, max over the two sides, is reported in
+ * *dropped_bits (may be NULL).  Outputs not yet polled are discarded.  The
+ * handle is freed; using it afterwards is undefined.
+ */
+int ext_stream_close(ext_stream *s, uint64_t *dropped_bits);
+
+/* Write a one-line JSON description of the context's launch plan (base
+ * product size, Karatsuba levels, work-group shape) into buf. */
+int ext_describe(const ext_ctx *c, char *buf, size_t cap);
+
+/* Static description of a status code. */
+const char *ext_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRNG_EXT_H */

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libqrngext.so (include/qrng_ext.h).
+
+Argument marshalling only: every step of the extraction runs in the HIP
+library.  PyTorch supplies device memory (tensors) and streams
+(``torch.cuda.current_stream()``).  If the library is not built, loading
+fails with an error -- there is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqrngext.so")
+
+EXT_OK = 0
+EXT_EINVAL = -1
+EXT_ENOTSUP = -2
+EXT_ENOMEM = -3
+EXT_EAGAIN = -4
+EXT_EDEVICE = -5
+EXT_ECLOSED = -6
+
+EXT_MEM_HOST = 0
+EXT_MEM_DEVICE = 1
+
+EXPORTED = (
+    "ext_params_init", "ext_create", "ext_destroy", "ext_get_modulus", "ext_default_modulus",
+    "ext_is_irreducible", "ext_extract", "ext_sync", "ext_stream_open", "ext_submit",
+    "ext_poll", "ext_drain", "ext_stream_close", "ext_describe", "ext_strerror",
+)
+
+
+class ExtError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+
+
+class ExtParams(ctypes.Structure):
+    _fields_ = [
+        ("sample_bits", ctypes.c_uint32),
+        ("n_taps", ctypes.c_uint32),
+        ("taps", ctypes.c_uint32 * 3),
+        ("mem_kind", ctypes.c_uint32),
+        ("hip_stream", ctypes.c_void_p),
+        ("use_hip_stream", ctypes.c_uint32),
+        ("device_bytes_cap", ctypes.c_uint64),
+        ("device", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32 * 4),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libqrngext.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqrngext.so is not built; run __graft_entry__.build() "
+                          "or python -m paper_2402_14607_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    u32p = ctypes.POINTER(u32)
+    u64p = ctypes.POINTER(u64)
+    szp = ctypes.POINTER(sz)
+    sig = {
+        "ext_params_init": (None, [ctypes.POINTER(ExtParams)]),
+        "ext_create": (ctypes.c_int, [u64, u32, ctypes.POINTER(ExtParams), ctypes.POINTER(vp)]),
+        "ext_destroy": (ctypes.c_int, [vp]),
+        "ext_get_modulus": (ctypes.c_int, [vp, u32p, u32, u32p]),
+        "ext_default_modulus": (ctypes.c_int, [u32, u32p, u32, u32p]),
+        "ext_is_irreducible": (ctypes.c_int, [u32, u32p, u32]),
+        "ext_extract": (ctypes.c_int, [vp, vp, vp, u64, vp]),
+        "ext_sync": (ctypes.c_int, [vp]),
+        "ext_stream_open": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
+        "ext_submit": (ctypes.c_int, [vp, vp, sz, vp, sz, u64p]),
+        "ext_poll": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
+        "ext_drain": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
+        "ext_stream_close": (ctypes.c_int, [vp, u64p]),
+        "ext_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
+        "ext_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().ext_strerror(code).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise ExtError(rc, what)
+    return rc
+
+
+def default_modulus(m_bits: int) -> tuple:
+    lib = load()
+    exps = (ctypes.c_uint32 * 8)()
+    n = ctypes.c_uint32()
+    _check(lib.ext_default_modulus(m_bits, exps, 8, ctypes.byref(n)), "ext_default_modulus")
+    return tuple(int(exps[i]) for i in range(n.value))
+
+
+def is_irreducible(m_bits: int, taps) -> bool:
+    lib = load()
+    arr = (ctypes.c_uint32 * 3)(*taps)
+    return bool(_check(lib.ext_is_irreducible(m_bits, arr, len(taps)), "ext_is_irreducible"))
+
+
+def _ptr(buf) -> int:
+    """Raw address of a torch tensor or numpy array."""
+    if hasattr(buf, "data_ptr"):
+        return buf.data_ptr()
+    if isinstance(buf, np.ndarray):
+        return buf.ctypes.data
+    raise TypeError("expected a torch tensor or numpy array, got %r" % type(buf))
+
+
+class Extractor:
+    """One ext_ctx: block length n_bits, m_bits output bits per block pair."""
+
+    def __init__(self, n_bits: int, m_bits: int, *, device_memory: bool = True, stream=None,
+                 taps=None, sample_bits: int = 8, device_bytes_cap: int = 0, device: int = -1):
+        self.lib = load()
+        p = ExtParams()
+        self.lib.ext_params_init(ctypes.byref(p))
+        p.sample_bits = sample_bits
+        p.mem_kind = EXT_MEM_DEVICE if device_memory else EXT_MEM_HOST
+        if taps:
+            p.n_taps = len(taps)
+            for i, t in enumerate(taps):
+                p.taps[i] = int(t)
+        if stream is not None:
+            p.hip_stream = ctypes.c_void_p(int(stream))
+            p.use_hip_stream = 1
+        if device_bytes_cap:
+            p.device_bytes_cap = device_bytes_cap
+        p.device = device
+        self.n_bits = n_bits
+        self.m_bits = m_bits
+        self.device_memory = device_memory
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_create(n_bits, m_bits, ctypes.byref(p), ctypes.byref(self.handle)),
+               "ext_create")
+
+    def close(self):
+        if self.handle:
+            self.lib.ext_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def modulus(self) -> tuple:
+        exps = (ctypes.c_uint32 * 8)()
+        n = ctypes.c_uint32()
+        _check(self.lib.ext_get_modulus(self.handle, exps, 8, ctypes.byref(n)), "ext_get_modulus")
+        return tuple(int(exps[i]) for i in range(n.value))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(self.lib.ext_describe(self.handle, buf, 512), "ext_describe")
+        return buf.value.decode()
+
+    def extract(self, x, y, out, n_pairs: int) -> None:
+        """Queue (device memory) or run (host memory) the plain form."""
+        _check(self.lib.ext_extract(self.handle, _ptr(x), _ptr(y), n_pairs, _ptr(out)),
+               "ext_extract")
+
+    def sync(self) -> None:
+        _check(self.lib.ext_sync(self.handle), "ext_sync")
+
+    def open_stream(self) -> "Stream":
+        return Stream(self)
+
+
+class Stream:
+    """One ext_stream (an (X, Y) channel pair) of an Extractor."""
+
+    def __init__(self, ex: Extractor):
+        self.ex = ex
+        self.lib = ex.lib
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_stream_open(ex.handle, ctypes.byref(self.handle)), "ext_stream_open")
+
+    def submit(self, x, x_len: int, y, y_len: int) -> int:
+        """Returns EXT_OK or EXT_EAGAIN; raises on other errors."""
+        seq = ctypes.c_uint64()
+        xp = _ptr(x) if x_len else None
+        yp = _ptr(y) if y_len else None
+        rc = self.lib.ext_submit(self.handle, xp, x_len, yp, y_len, ctypes.byref(seq))
+        if rc == EXT_EAGAIN:
+            return rc
+        _check(rc, "ext_submit")
+        return rc
+
+    def poll(self, out, out_cap: int, wait: bool = False):
+        """(bytes written, blocks returned so far)."""
+        n = ctypes.c_size_t()
+        done = ctypes.c_uint64()
+        f = self.lib.ext_drain if wait else self.lib.ext_poll
+        _check(f(self.handle, _ptr(out) if out_cap else None, out_cap, ctypes.byref(n),
+                 ctypes.byref(done)), "ext_poll")
+        return n.value, done.value
+
+    def close(self) -> int:
+        """Closes the stream; returns the dropped tail in bits."""
+        if not self.handle:
+            return 0
+        dropped = ctypes.c_uint64()
+        _check(self.lib.ext_stream_close(self.handle, ctypes.byref(dropped)), "ext_stream_close")
+        self.handle = ctypes.c_void_p()
+        return dropped.value

@@ -1,0 +1,646 @@
+// ext_api.cpp -- the C ABI (include/qrng_ext.h): contexts, the plain form,
+// the streaming form (pending partial blocks kept on the device) and the
+// launch planning of the extraction kernel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qrng_ext.h"
+#include "ext_internal.h"
+#include "gf2_modulus.h"
+
+namespace qext {
+
+bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
+                uint32_t base_words_target, ExtShape* s) {
+    if (q == 0 || q % 32 || n_e == 0 || (n_taps != 1 && n_taps != 3)) return false;
+    const uint32_t target = base_words_target ? base_words_target : 8u;
+    const uint32_t qw = q / 32;
+    const uint32_t v = (uint32_t)__builtin_ctz(qw);
+    const uint32_t odd = qw >> v;
+    if (odd > 15) return false;
+    uint32_t bw, levels;
+    if (odd <= target) {
+        uint32_t k = 0;
+        while (k < v && (odd << (k + 1)) <= target) ++k;
+        bw = odd << k;
+        levels = v - k;
+    } else {
+        bw = odd;
+        levels = v;
+    }
+    if (levels > 10) return false;
+    uint32_t max_tap = 0;
+    for (uint32_t t = 0; t < n_taps; ++t) {
+        if (taps[t] == 0 || taps[t] >= q) return false;
+        max_tap = std::max(max_tap, taps[t]);
+    }
+    if (2 * max_tap > q) return false;  // two folding passes suffice only below q/2
+
+    ExtShape r{};
+    r.q = q;
+    r.qw = qw;
+    r.n_e = n_e;
+    r.nw = qw * n_e;
+    r.bw = bw;
+    r.levels = levels;
+    r.np = 1;
+    for (uint32_t l = 0; l < levels; ++l) r.np *= 3;
+    r.n_taps = n_taps;
+    for (uint32_t t = 0; t < 3; ++t) r.taps[t] = t < n_taps ? taps[t] : 0;
+    r.dn = max_tap >= 2 ? (max_tap - 1 + 31) / 32 : 0;
+
+    // Pick the element grouping and pairs per work-group that keep the most
+    // lanes busy, with the LDS footprint under kMaxLdsBytes.
+    double best_util = -1.0;
+    for (uint32_t stage_try = levels > 0 ? 1u : 0u;; stage_try = 0) {
+        for (uint32_t g = 1; g <= n_e; ++g) {
+            if (n_e % g) continue;
+            const uint32_t per_pair = r.np * g;
+            uint32_t ppw = per_pair >= (uint32_t)kThreads ? 1u : (uint32_t)kThreads / per_pair;
+            auto lds_words = [&](uint32_t pp) {
+                return pp * ((stage_try ? 2 * r.nw : 0) + 2 * qw + r.dn);
+            };
+            while (ppw > 1 && lds_words(ppw) * 4 > kMaxLdsBytes) --ppw;
+            if (lds_words(ppw) * 4 > 65536) continue;
+            const uint64_t items = (uint64_t)ppw * per_pair;
+            const uint64_t rounds = (items + kThreads - 1) / kThreads;
+            const double util = (double)items / (double)(rounds * kThreads);
+            if (util > best_util + 1e-9) {
+                best_util = util;
+                r.groups = g;
+                r.epg = n_e / g;
+                r.ppw = ppw;
+                r.stage = stage_try;
+                r.lds_words = lds_words(ppw);
+            }
+        }
+        if (best_util >= 0 || stage_try == 0) break;
+    }
+    if (best_util < 0) return false;
+    r.align = (!r.stage && bw % 4 == 0) ? 16u : 4u;
+    *s = r;
+    return true;
+}
+
+}  // namespace qext
+
+using qext::ExtShape;
+
+// ---------------------------------------------------------------------------
+// context and stream objects
+// ---------------------------------------------------------------------------
+struct ext_ctx {
+    uint64_t n_bits = 0;
+    uint32_t m_bits = 0;
+    uint32_t b = 8;
+    std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
+    ExtShape shape{};
+    uint32_t mem_kind = EXT_MEM_HOST;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t copy_stream = nullptr;  // D2H copies of finished outputs
+    int device = 0;
+    uint64_t cap = 0;
+    int sticky = EXT_OK;
+    // device scratch for host-memory ext_extract
+    uint8_t* dx = nullptr;
+    uint8_t* dy = nullptr;
+    uint8_t* dout = nullptr;
+    uint64_t scratch_pairs = 0;
+    std::vector<ext_stream*> streams;
+};
+
+namespace {
+
+struct Launch {
+    uint64_t ring_pos;  // first output slot in the stream's output ring
+    uint64_t n;         // block pairs
+    uint64_t consumed;  // pairs already handed out by ext_poll
+    hipEvent_t done;
+};
+
+}  // namespace
+
+struct ext_stream {
+    ext_ctx* ctx = nullptr;
+    bool closed = false;
+    uint64_t nb = 0;  // bytes per block
+    uint64_t qb = 0;  // output bytes per block
+    // pending input on the device: double buffers, live bytes [head, tail)
+    uint8_t* xbuf[2] = {nullptr, nullptr};
+    uint8_t* ybuf[2] = {nullptr, nullptr};
+    int xcur = 0, ycur = 0;
+    uint64_t buf_bytes = 0;
+    uint64_t xhead = 0, xtail = 0, yhead = 0, ytail = 0;
+    // outputs: ring of out_slots block outputs
+    uint8_t* oring = nullptr;
+    uint64_t out_slots = 0;
+    uint64_t ring_write = 0;  // next slot to fill (monotonic, mod out_slots)
+    uint64_t ring_used = 0;   // slots launched but not yet polled
+    std::deque<Launch> inflight;
+    uint64_t launched = 0;
+    uint64_t returned = 0;
+    // pinned staging for host submissions
+    uint8_t* stage = nullptr;
+    uint64_t stage_bytes = 0;
+    hipEvent_t stage_free = nullptr;
+};
+
+namespace {
+
+int fail(ext_ctx* c, hipError_t e) {
+    if (e == hipSuccess) return EXT_OK;
+    if (c) c->sticky = EXT_EDEVICE;
+    return EXT_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr)                          \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return fail(ctx, _e); \
+    } while (0)
+
+int enter(ext_ctx* c) {
+    if (!c) return EXT_EINVAL;
+    if (c->sticky) return c->sticky;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(c, hipErrorInvalidDevice);
+    if (cur != c->device && hipSetDevice(c->device) != hipSuccess)
+        return fail(c, hipErrorInvalidDevice);
+    return EXT_OK;
+}
+
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
+    HIP_TRY(c, qext::launch_extract(c->shape, (const uint32_t*)x, (const uint32_t*)y,
+                                    (uint32_t*)out, n_pairs, c->stream));
+    return EXT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void ext_params_init(ext_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->sample_bits = 8;
+    p->mem_kind = EXT_MEM_HOST;
+    p->device_bytes_cap = 256ull << 20;
+    p->device = -1;
+}
+
+const char* ext_strerror(int code) {
+    switch (code) {
+        case EXT_OK: return "ok";
+        case EXT_EINVAL: return "invalid argument";
+        case EXT_ENOTSUP: return "shape or modulus not supported by the GPU path";
+        case EXT_ENOMEM: return "out of memory";
+        case EXT_EAGAIN: return "device buffer full (admission): poll and retry";
+        case EXT_EDEVICE: return "HIP device error";
+        case EXT_ECLOSED: return "stream closed";
+        default: return "unknown status";
+    }
+}
+
+int ext_is_irreducible(uint32_t m_bits, const uint32_t* taps, uint32_t n_taps) {
+    if (m_bits < 2 || (n_taps && !taps) || n_taps > 3) return EXT_EINVAL;
+    for (uint32_t k = 0; k < n_taps; ++k)
+        if (taps[k] == 0 || taps[k] >= m_bits) return EXT_EINVAL;
+    return qext::modulus_is_irreducible(m_bits, taps, n_taps) ? 1 : 0;
+}
+
+int ext_default_modulus(uint32_t m_bits, uint32_t* exps, uint32_t cap, uint32_t* n) {
+    if (!exps || !n || m_bits < 2) return EXT_EINVAL;
+    std::vector<uint32_t> taps;
+    try {
+        if (!qext::default_modulus(m_bits, &taps)) return EXT_ENOTSUP;
+    } catch (const std::bad_alloc&) {
+        return EXT_ENOMEM;
+    }
+    if (cap < taps.size() + 2) return EXT_EINVAL;
+    uint32_t k = 0;
+    exps[k++] = m_bits;
+    for (uint32_t t : taps) exps[k++] = t;
+    exps[k++] = 0;
+    *n = k;
+    return EXT_OK;
+}
+
+int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** out) {
+    if (!out) return EXT_EINVAL;
+    *out = nullptr;
+    ext_params def;
+    ext_params_init(&def);
+    if (!p) p = &def;
+    const uint32_t b = p->sample_bits ? p->sample_bits : 8;
+    if (n_bits == 0 || m_bits == 0 || n_bits % m_bits || m_bits % b) return EXT_EINVAL;
+    if (p->mem_kind != EXT_MEM_HOST && p->mem_kind != EXT_MEM_DEVICE) return EXT_EINVAL;
+    if (n_bits / m_bits > 0xffffffffull) return EXT_EINVAL;
+    std::vector<uint32_t> taps;
+    if (p->n_taps == 0) {
+        try {
+            if (!qext::default_modulus(m_bits, &taps)) return EXT_ENOTSUP;
+        } catch (const std::bad_alloc&) {
+            return EXT_ENOMEM;
+        }
+    } else if (p->n_taps == 1 || p->n_taps == 3) {
+        taps.assign(p->taps, p->taps + p->n_taps);
+        std::sort(taps.begin(), taps.end(), std::greater<uint32_t>());
+        for (size_t k = 0; k < taps.size(); ++k) {
+            if (taps[k] == 0 || taps[k] >= m_bits) return EXT_EINVAL;
+            if (k && taps[k] == taps[k - 1]) return EXT_EINVAL;
+        }
+        if (!qext::modulus_is_irreducible(m_bits, taps.data(), (uint32_t)taps.size()))
+            return EXT_EINVAL;
+    } else {
+        return EXT_EINVAL;
+    }
+    ExtShape shape;
+    if (!qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
+                          (uint32_t)taps.size(), 0, &shape))
+        return EXT_ENOTSUP;
+
+    ext_ctx* c = new (std::nothrow) ext_ctx;
+    if (!c) return EXT_ENOMEM;
+    c->n_bits = n_bits;
+    c->m_bits = m_bits;
+    c->b = b;
+    c->taps = taps;
+    c->shape = shape;
+    c->mem_kind = p->mem_kind;
+    c->cap = p->device_bytes_cap ? p->device_bytes_cap : (256ull << 20);
+    int dev = p->device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+        delete c;
+        return EXT_EDEVICE;
+    }
+    c->device = dev;
+    if (hipSetDevice(dev) != hipSuccess) {
+        delete c;
+        return EXT_EDEVICE;
+    }
+    if (p->use_hip_stream) {
+        c->stream = (hipStream_t)p->hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return EXT_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return EXT_EDEVICE;
+    }
+    *out = c;
+    return EXT_OK;
+}
+
+int ext_get_modulus(const ext_ctx* c, uint32_t* exps, uint32_t cap, uint32_t* n) {
+    if (!c || !exps || !n) return EXT_EINVAL;
+    if (cap < c->taps.size() + 2) return EXT_EINVAL;
+    uint32_t k = 0;
+    exps[k++] = c->m_bits;
+    for (uint32_t t : c->taps) exps[k++] = t;
+    exps[k++] = 0;
+    *n = k;
+    return EXT_OK;
+}
+
+int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
+    if (!c || !buf || cap == 0) return EXT_EINVAL;
+    const ExtShape& s = c->shape;
+    snprintf(buf, cap,
+             "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"base_bits\": %u, \"karatsuba_levels\": %u, "
+             "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
+             "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d}",
+             (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
+             s.groups, s.stage, s.lds_words * 4, qext::kThreads);
+    return EXT_OK;
+}
+
+int ext_sync(ext_ctx* c) {
+    int rc = enter(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return EXT_OK;
+}
+
+int ext_extract(ext_ctx* c, const void* x, const void* y, uint64_t n_pairs, void* out) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if (n_pairs == 0) return EXT_OK;
+    if (!x || !y || !out) return EXT_EINVAL;
+    if (!aligned4(x) || !aligned4(y) || !aligned4(out)) return EXT_EINVAL;
+    const uint64_t nb = c->n_bits / 8, qb = c->m_bits / 8;
+    if (c->mem_kind == EXT_MEM_DEVICE) {
+        const uintptr_t am = c->shape.align - 1;
+        if (((uintptr_t)x & am) || ((uintptr_t)y & am)) return EXT_EINVAL;
+        return launch(c, x, y, out, n_pairs);
+    }
+    // host memory: stage through device scratch, in slices of at most 64 MiB
+    // of input per side
+    const uint64_t slice = std::max<uint64_t>(1, (64ull << 20) / nb);
+    const uint64_t want = std::min(slice, n_pairs);
+    if (c->scratch_pairs < want) {
+        (void)hipFree(c->dx);
+        (void)hipFree(c->dy);
+        (void)hipFree(c->dout);
+        c->dx = c->dy = c->dout = nullptr;
+        c->scratch_pairs = 0;
+        if (hipMalloc((void**)&c->dx, want * nb) != hipSuccess ||
+            hipMalloc((void**)&c->dy, want * nb) != hipSuccess ||
+            hipMalloc((void**)&c->dout, want * qb) != hipSuccess) {
+            (void)hipFree(c->dx);
+            (void)hipFree(c->dy);
+            (void)hipFree(c->dout);
+            c->dx = c->dy = c->dout = nullptr;
+            (void)hipGetLastError();
+            return EXT_ENOMEM;
+        }
+        c->scratch_pairs = want;
+    }
+    for (uint64_t done = 0; done < n_pairs;) {
+        const uint64_t k = std::min(c->scratch_pairs, n_pairs - done);
+        HIP_TRY(c, hipMemcpyAsync(c->dx, (const uint8_t*)x + done * nb, k * nb,
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->dy, (const uint8_t*)y + done * nb, k * nb,
+                                  hipMemcpyHostToDevice, c->stream));
+        rc = launch(c, c->dx, c->dy, c->dout, k);
+        if (rc) return rc;
+        HIP_TRY(c, hipMemcpyAsync((uint8_t*)out + done * qb, c->dout, k * qb,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        done += k;
+    }
+    return EXT_OK;
+}
+
+int ext_destroy(ext_ctx* c) {
+    if (!c) return EXT_OK;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
+    while (!c->streams.empty()) ext_stream_close(c->streams.back(), nullptr);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->dx);
+    (void)hipFree(c->dy);
+    (void)hipFree(c->dout);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return EXT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// streaming form
+// ---------------------------------------------------------------------------
+int ext_stream_open(ext_ctx* c, ext_stream** out) {
+    if (!out) return EXT_EINVAL;
+    *out = nullptr;
+    int rc = enter(c);
+    if (rc) return rc;
+    ext_stream* s = new (std::nothrow) ext_stream;
+    if (!s) return EXT_ENOMEM;
+    s->ctx = c;
+    s->nb = c->n_bits / 8;
+    s->qb = c->m_bits / 8;
+    // every side holds at most cap bytes of pending input plus one block
+    s->buf_bytes = ((c->cap + s->nb - 1) / s->nb + 1) * s->nb;
+    // room for as many outputs as the pending input could produce, times two
+    s->out_slots = 2 * (s->buf_bytes / s->nb);
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k) {
+        ok = hipMalloc((void**)&s->xbuf[k], s->buf_bytes) == hipSuccess &&
+             hipMalloc((void**)&s->ybuf[k], s->buf_bytes) == hipSuccess;
+    }
+    ok = ok && hipMalloc((void**)&s->oring, s->out_slots * s->qb) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->stage_free, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (int k = 0; k < 2; ++k) {
+            (void)hipFree(s->xbuf[k]);
+            (void)hipFree(s->ybuf[k]);
+        }
+        (void)hipFree(s->oring);
+        if (s->stage_free) (void)hipEventDestroy(s->stage_free);
+        (void)hipGetLastError();
+        delete s;
+        return EXT_ENOMEM;
+    }
+    c->streams.push_back(s);
+    *out = s;
+    return EXT_OK;
+}
+
+namespace {
+
+// Make room for `len` more bytes on one side: compact [head, tail) to the
+// front of the other buffer when the tail would run past the end.
+int make_room(ext_stream* s, uint8_t** buf, int* cur, uint64_t* head, uint64_t* tail,
+              uint64_t len) {
+    ext_ctx* c = s->ctx;
+    const uint64_t live = *tail - *head;
+    if (live + len > s->buf_bytes) return EXT_EAGAIN;
+    if (*tail + len <= s->buf_bytes) return EXT_OK;
+    const int nxt = 1 - *cur;
+    if (live)
+        HIP_TRY(c, hipMemcpyAsync(buf[nxt], buf[*cur] + *head, live, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    *cur = nxt;
+    *head = 0;
+    *tail = live;
+    return EXT_OK;
+}
+
+// Queue the copy of one submission (x_len bytes of X, y_len of Y) to the
+// tails of the pending buffers.  Host data go through pinned staging, reused
+// once the previous submission's copies have completed.
+int append(ext_stream* s, const void* x, uint64_t x_len, const void* y, uint64_t y_len) {
+    ext_ctx* c = s->ctx;
+    uint8_t* xdst = s->xbuf[s->xcur] + s->xtail;
+    uint8_t* ydst = s->ybuf[s->ycur] + s->ytail;
+    if (c->mem_kind == EXT_MEM_DEVICE) {
+        if (x_len)
+            HIP_TRY(c, hipMemcpyAsync(xdst, x, x_len, hipMemcpyDeviceToDevice, c->stream));
+        if (y_len)
+            HIP_TRY(c, hipMemcpyAsync(ydst, y, y_len, hipMemcpyDeviceToDevice, c->stream));
+        return EXT_OK;
+    }
+    if (!x_len && !y_len) return EXT_OK;
+    HIP_TRY(c, hipEventSynchronize(s->stage_free));
+    const uint64_t len = x_len + y_len;
+    if (s->stage_bytes < len) {
+        if (s->stage) (void)hipHostFree(s->stage);
+        s->stage = nullptr;
+        s->stage_bytes = 0;
+        if (hipHostMalloc((void**)&s->stage, len, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return EXT_ENOMEM;
+        }
+        s->stage_bytes = len;
+    }
+    if (x_len) memcpy(s->stage, x, x_len);
+    if (y_len) memcpy(s->stage + x_len, y, y_len);
+    if (x_len)
+        HIP_TRY(c, hipMemcpyAsync(xdst, s->stage, x_len, hipMemcpyHostToDevice, c->stream));
+    if (y_len)
+        HIP_TRY(c, hipMemcpyAsync(ydst, s->stage + x_len, y_len, hipMemcpyHostToDevice,
+                                  c->stream));
+    HIP_TRY(c, hipEventRecord(s->stage_free, c->stream));
+    return EXT_OK;
+}
+
+int launch_ready(ext_stream* s) {
+    ext_ctx* c = s->ctx;
+    uint64_t ready = std::min(s->xtail - s->xhead, s->ytail - s->yhead) / s->nb;
+    while (ready) {
+        if (s->ring_used >= s->out_slots) return EXT_EAGAIN;
+        const uint64_t pos = s->ring_write % s->out_slots;
+        uint64_t k = std::min(ready, s->out_slots - s->ring_used);
+        k = std::min(k, s->out_slots - pos);  // no wrap inside one launch
+        const uint8_t* xp = s->xbuf[s->xcur] + s->xhead;
+        const uint8_t* yp = s->ybuf[s->ycur] + s->yhead;
+        if (((uintptr_t)xp | (uintptr_t)yp) & (c->shape.align - 1)) return EXT_EINVAL;
+        int rc = launch(c, xp, yp, s->oring + pos * s->qb, k);
+        if (rc) return rc;
+        Launch L{pos, k, 0, nullptr};
+        HIP_TRY(c, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+        HIP_TRY(c, hipEventRecord(L.done, c->stream));
+        s->inflight.push_back(L);
+        s->ring_write += k;
+        s->ring_used += k;
+        s->launched += k;
+        s->xhead += k * s->nb;
+        s->yhead += k * s->nb;
+        ready -= k;
+    }
+    return EXT_OK;
+}
+
+int copy_out(ext_stream* s, void* out, size_t out_cap, size_t* out_len, uint64_t* blocks_done,
+             bool wait) {
+    ext_ctx* c = s->ctx;
+    size_t written = 0;
+    while (!s->inflight.empty()) {
+        Launch& L = s->inflight.front();
+        if (wait) {
+            HIP_TRY(c, hipEventSynchronize(L.done));
+        } else {
+            hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return fail(c, q);
+        }
+        const uint64_t avail = L.n - L.consumed;
+        const uint64_t fit = (out_cap - written) / s->qb;
+        const uint64_t k = std::min(avail, fit);
+        if (k) {
+            const uint8_t* src = s->oring + (L.ring_pos + L.consumed) * s->qb;
+            const hipMemcpyKind kind = c->mem_kind == EXT_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                                     : hipMemcpyDeviceToHost;
+            HIP_TRY(c, hipMemcpyAsync((uint8_t*)out + written, src, k * s->qb, kind,
+                                      c->copy_stream));
+            HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
+            written += k * s->qb;
+            L.consumed += k;
+            s->returned += k;
+            s->ring_used -= k;
+        }
+        if (L.consumed < L.n) break;  // caller's buffer is full
+        (void)hipEventDestroy(L.done);
+        s->inflight.pop_front();
+    }
+    if (out_len) *out_len = written;
+    if (blocks_done) *blocks_done = s->returned;
+    return EXT_OK;
+}
+
+}  // namespace
+
+int ext_submit(ext_stream* s, const void* x, size_t x_len, const void* y, size_t y_len,
+               uint64_t* seq_out) {
+    if (!s) return EXT_EINVAL;
+    if (s->closed) return EXT_ECLOSED;
+    ext_ctx* c = s->ctx;
+    int rc = enter(c);
+    if (rc) return rc;
+    if ((x_len && !x) || (y_len && !y)) return EXT_EINVAL;
+    // admission: pending bytes on each side must stay within the cap
+    if ((s->xtail - s->xhead) + x_len > s->buf_bytes ||
+        (s->ytail - s->yhead) + y_len > s->buf_bytes)
+        return EXT_EAGAIN;
+    // outputs that this chunk completes must fit in the output ring
+    {
+        const uint64_t nx = (s->xtail - s->xhead + x_len) / s->nb;
+        const uint64_t ny = (s->ytail - s->yhead + y_len) / s->nb;
+        if (s->ring_used + std::min(nx, ny) > s->out_slots) return EXT_EAGAIN;
+    }
+    rc = make_room(s, s->xbuf, &s->xcur, &s->xhead, &s->xtail, x_len);
+    if (rc) return rc;
+    rc = make_room(s, s->ybuf, &s->ycur, &s->yhead, &s->ytail, y_len);
+    if (rc) return rc;
+    rc = append(s, x, x_len, y, y_len);
+    if (rc) return rc;
+    s->xtail += x_len;
+    s->ytail += y_len;
+    rc = launch_ready(s);
+    if (rc) return rc;
+    if (seq_out) *seq_out = s->launched;
+    return EXT_OK;
+}
+
+int ext_poll(ext_stream* s, void* out, size_t out_cap, size_t* out_len, uint64_t* blocks_done) {
+    if (!s) return EXT_EINVAL;
+    if (s->closed) return EXT_ECLOSED;
+    int rc = enter(s->ctx);
+    if (rc) return rc;
+    if (!out && out_cap) return EXT_EINVAL;
+    return copy_out(s, out, out_cap, out_len, blocks_done, false);
+}
+
+int ext_drain(ext_stream* s, void* out, size_t out_cap, size_t* out_len, uint64_t* blocks_done) {
+    if (!s) return EXT_EINVAL;
+    if (s->closed) return EXT_ECLOSED;
+    int rc = enter(s->ctx);
+    if (rc) return rc;
+    if (!out && out_cap) return EXT_EINVAL;
+    return copy_out(s, out, out_cap, out_len, blocks_done, true);
+}
+
+int ext_stream_close(ext_stream* s, uint64_t* dropped_bits) {
+    if (!s) return EXT_EINVAL;
+    ext_ctx* c = s->ctx;
+    const uint64_t px = s->xtail - s->xhead, py = s->ytail - s->yhead;
+    if (dropped_bits) *dropped_bits = 8 * std::max(px, py);
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (Launch& L : s->inflight) (void)hipEventDestroy(L.done);
+    s->inflight.clear();
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(s->xbuf[k]);
+        (void)hipFree(s->ybuf[k]);
+    }
+    (void)hipFree(s->oring);
+    if (s->stage) (void)hipHostFree(s->stage);
+    if (s->stage_free) (void)hipEventDestroy(s->stage_free);
+    auto it = std::find(c->streams.begin(), c->streams.end(), s);
+    if (it != c->streams.end()) c->streams.erase(it);
+    s->closed = true;
+    delete s;
+    return EXT_OK;
+}
+
+}  // extern "C"

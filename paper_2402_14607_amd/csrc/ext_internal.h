@@ -1,0 +1,46 @@
+// ext_internal.h -- shapes and launchers shared by the C ABI (ext_api.cpp)
+// and the gfx950 kernels (ext_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qext {
+
+constexpr int kThreads = 256;           // work-group size of the extraction kernel
+constexpr int kMaxBaseWords = 16;       // largest base-product size, 32-bit words
+constexpr uint32_t kMaxLdsBytes = 32768;
+
+// Launch shape of one (n, m, P) configuration; computed on the host by
+// plan_shape() and passed to the kernel by value.
+struct ExtShape {
+    uint32_t q;        // m, field degree = output bits per block pair
+    uint32_t qw;       // q / 32
+    uint32_t n_e;      // elements per block (n / m)
+    uint32_t nw;       // n / 32, words per block
+    uint32_t bw;       // base-product size in words (B = 32*bw bits)
+    uint32_t levels;   // Karatsuba levels L, q = B * 2^L
+    uint32_t np;       // 3^L sub-products per element product
+    uint32_t ppw;      // block pairs per work-group
+    uint32_t groups;   // element groups per (pair, sub-product) work item
+    uint32_t epg;      // elements per group (n_e / groups)
+    uint32_t stage;    // 1: the work-group's input blocks are staged in LDS
+    uint32_t n_taps;   // 1 (trinomial) or 3 (pentanomial)
+    uint32_t taps[3];  // non-leading nonzero exponents of P, each < q/2
+    uint32_t dn;       // words of the second reduction pass, ceil((max tap - 1)/32)
+    uint32_t lds_words;
+    uint32_t align;    // required byte alignment of x and y (16 when operands are
+                       // read from HBM with 16-byte loads, else 4)
+};
+
+// Fills *s for q, n_e and the taps; returns false if the shape is outside
+// what the kernel supports.  base_words_target: preferred base size (0 =
+// default).
+bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
+                uint32_t base_words_target, ExtShape* s);
+
+// Queue the extraction of n_pairs consecutive block pairs on `stream`.
+// x, y: device, n_pairs*nw words each; out: device, n_pairs*qw words.
+hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
+                          uint32_t* out, uint64_t n_pairs, hipStream_t stream);
+
+}  // namespace qext

@@ -1,0 +1,272 @@
+// ext_kernels.hip -- gfx950 kernels of the block-wise inner-product extractor.
+//
+// One block pair (x, y) of n bits each holds n_e elements of F_{2^q}; the
+// output is Z = sum_i x_i * y_i in F_{2^q} (Def. 3.2), q bits per pair, for
+// every pair of consecutive equal blocks (Algorithm 1).
+//
+// How it is computed (exact GF(2) arithmetic throughout):
+//   * Field addition is XOR and reduction modulo P is linear, so the n_e
+//     carry-less products x_i(t) y_i(t) are summed unreduced and the sum is
+//     reduced once per pair.
+//   * Each q x q carry-less product is split by L levels of Karatsuba into
+//     3^L products of B = q / 2^L bits.  Karatsuba is linear in the
+//     sub-products, so the sum over the n_e elements is taken in the split
+//     domain: sub-product p of the pair is S_p = sum_i X_{i,p} Y_{i,p}, and
+//     each S_p is scattered (XOR) into the unreduced result at its offsets.
+//   * One lane computes one S_p with the shift-and-add (schoolbook) method on
+//     32-bit words held in registers: for every bit s of every word of X,
+//     acc ^= mask(bit) & (Y << s), the AND-XOR fused into one v_bitop3_b32.
+//   * The 2q-1 bit sum is reduced modulo P = t^q + sum t^e + 1 (taps e < q/2)
+//     in two folding passes, and the q-bit result is stored.
+//
+// Work decomposition: a work-group of 256 lanes owns `ppw` consecutive block
+// pairs; its (pair, sub-product, element-group) items are spread over the
+// lanes.  The pairs' input blocks are staged in LDS with coalesced loads
+// (each input word is read from HBM once), every lane builds its Karatsuba
+// operands from LDS, sub-products are combined with LDS atomic XOR, and the
+// reduction reads the combined sum from LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ext_internal.h"
+
+namespace qext {
+namespace {
+
+// acc ^= mask & y   (bitop3 truth table: src0 = 0xF0, src1 = 0xCC, src2 = 0xAA;
+// (0xF0 & 0xCC) ^ 0xAA = 0x6A)
+__device__ __forceinline__ uint32_t and_xor(uint32_t mask, uint32_t y, uint32_t acc) {
+    return __builtin_amdgcn_bitop3_b32(mask, y, acc, 0x6A);
+}
+
+// all-ones if bit s of v is set, else zero
+__device__ __forceinline__ uint32_t bit_mask(uint32_t v, uint32_t s) {
+    return (uint32_t)__builtin_amdgcn_sbfe((int)v, s, 1);
+}
+
+// ({hi, lo} >> sh) & 0xffffffff, sh in [0, 31]
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// acc[0 .. 2BW) ^= x(t) * y(t) over GF(2), x and y BW words each.
+template <int BW>
+__device__ __forceinline__ void clmul_acc(const uint32_t (&x)[BW], const uint32_t (&y)[BW],
+                                          uint32_t (&acc)[2 * BW]) {
+    // shift 0: Y itself, word-aligned
+#pragma unroll
+    for (int a = 0; a < BW; ++a) {
+        const uint32_t m = bit_mask(x[a], 0);
+#pragma unroll
+        for (int w = 0; w < BW; ++w) acc[a + w] = and_xor(m, y[w], acc[a + w]);
+    }
+#pragma unroll 1
+    for (uint32_t s = 1; s < 32; ++s) {
+        uint32_t ys[BW + 1];
+        ys[0] = y[0] << s;
+#pragma unroll
+        for (int w = 1; w < BW; ++w) ys[w] = funnel(y[w], y[w - 1], 32u - s);
+        ys[BW] = y[BW - 1] >> (32u - s);
+#pragma unroll
+        for (int a = 0; a < BW; ++a) {
+            const uint32_t m = bit_mask(x[a], s);
+#pragma unroll
+            for (int w = 0; w <= BW; ++w) acc[a + w] = and_xor(m, ys[w], acc[a + w]);
+        }
+    }
+}
+
+// Read BW words from LDS (or global) at p into r (XOR-accumulate).
+template <int BW>
+__device__ __forceinline__ void xor_words(uint32_t (&r)[BW], const uint32_t* p) {
+    if constexpr (BW % 4 == 0) {
+        const uint4* p4 = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+        for (int k = 0; k < BW / 4; ++k) {
+            const uint4 v = p4[k];
+            r[4 * k + 0] ^= v.x;
+            r[4 * k + 1] ^= v.y;
+            r[4 * k + 2] ^= v.z;
+            r[4 * k + 3] ^= v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < BW; ++k) r[k] ^= p[k];
+    }
+}
+
+// Karatsuba operand of one element: XOR of the B-bit segments hi_mask | sub
+// for every subset sub of mid_mask (segment s = element bits [s*B, (s+1)*B)).
+template <int BW>
+__device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* elem,
+                                             uint32_t hi_mask, uint32_t mid_mask) {
+#pragma unroll
+    for (int w = 0; w < BW; ++w) r[w] = 0;
+    uint32_t sub = mid_mask;
+    for (;;) {
+        xor_words<BW>(r, elem + (hi_mask | sub) * BW);
+        if (sub == 0) break;
+        sub = (sub - 1u) & mid_mask;
+    }
+}
+
+template <int BW>
+__global__ void __launch_bounds__(kThreads)
+ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+              uint32_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t pair0 = (uint64_t)blockIdx.x * sh.ppw;
+    if (pair0 >= n_pairs) return;
+    const uint64_t left = n_pairs - pair0;
+    const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;  // pairs in this group
+
+    const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
+    uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
+    uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
+    uint32_t* cs = ys + (sh.stage ? sh.ppw * nw : 0); // [ppw][2qw]  unreduced sums
+    uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
+
+    for (uint32_t i = tid; i < npw * cw; i += kThreads) cs[i] = 0;
+    const uint32_t* xg = x + pair0 * nw;
+    const uint32_t* yg = y + pair0 * nw;
+    if (sh.stage) {
+        for (uint32_t i = tid; i < npw * nw; i += kThreads) {
+            xs[i] = xg[i];
+            ys[i] = yg[i];
+        }
+    }
+    __syncthreads();
+
+    // ---- sub-products ---------------------------------------------------
+    const uint32_t per_pair = sh.np * sh.groups;
+    const uint32_t items = npw * per_pair;
+    const uint32_t lmask = (1u << sh.levels) - 1u;
+    for (uint32_t it = tid; it < items; it += kThreads) {
+        const uint32_t j = it / per_pair;
+        const uint32_t rem = it - j * per_pair;
+        const uint32_t p = rem / sh.groups;
+        const uint32_t g = rem - p * sh.groups;
+        // Karatsuba path of p: one base-3 digit per level, 0 = low halves,
+        // 1 = high halves, 2 = sum of halves.  Bit l of a mask describes the
+        // level whose halves are B * 2^l bits (l = 0 is the lowest level).
+        uint32_t hi_mask = 0, mid_mask = 0;
+        {
+            uint32_t v = p;
+            for (uint32_t l = 0; l < sh.levels; ++l) {  // l = 0 is the lowest level
+                const uint32_t d = v % 3u;
+                v /= 3u;
+                if (d == 1u) hi_mask |= 1u << l;
+                if (d == 2u) mid_mask |= 1u << l;
+            }
+        }
+        uint32_t acc[2 * BW];
+#pragma unroll
+        for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
+
+        for (uint32_t e = g * sh.epg; e < (g + 1) * sh.epg; ++e) {
+            uint32_t xo[BW], yo[BW];
+            if (sh.stage) {  // operands from the LDS copy
+                form_operand<BW>(xo, xs + j * nw + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(yo, ys + j * nw + e * qw, hi_mask, mid_mask);
+            } else {         // straight from HBM (one sub-product per element)
+                form_operand<BW>(xo, xg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(yo, yg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
+            }
+            clmul_acc<BW>(xo, yo, acc);
+        }
+
+        // Scatter: a low-halves product lands at offsets {0, h}, a high-halves
+        // product at {h, 2h}, a sum-of-halves product at {h}, h = half size
+        // of that level; the offsets of all levels add up.
+        const uint32_t hm = hi_mask | mid_mask;
+        const uint32_t lh = lmask & ~mid_mask;
+        uint32_t* cdst = cs + j * cw;
+        uint32_t sub = lh;
+        for (;;) {
+            const uint32_t off = BW * (hm + sub);
+#pragma unroll
+            for (int w = 0; w < 2 * BW; ++w) atomicXor(cdst + off + w, acc[w]);
+            if (sub == 0) break;
+            sub = (sub - 1u) & lh;
+        }
+    }
+    __syncthreads();
+
+    // ---- reduction modulo P ----------------------------------------------
+    // C = C_lo + t^q C_hi with deg C_hi <= q-2, and t^q = 1 + sum_e t^e.
+    // First pass: C_hi (1 + sum t^e); its part of degree >= q is
+    // D = sum_e (C_hi >> (q - e)), of degree <= max_e - 2 < q/2, folded once more.
+    const uint32_t dn = sh.dn;
+    for (uint32_t i = tid; i < npw * dn; i += kThreads) {
+        const uint32_t j = i / dn, k = i - j * dn;
+        const uint32_t* hi = cs + j * cw + qw;
+        uint32_t d = 0;
+        for (uint32_t t = 0; t < sh.n_taps; ++t) {
+            const uint32_t r = sh.q - sh.taps[t];
+            const uint32_t rw = r >> 5, rb = r & 31u;
+            const uint32_t lo_i = k + rw, hi_i = k + rw + 1;
+            const uint32_t lo = lo_i < qw ? hi[lo_i] : 0u;
+            const uint32_t up = hi_i < qw ? hi[hi_i] : 0u;
+            d ^= rb ? funnel(up, lo, rb) : lo;
+        }
+        ds[j * dn + k] = d;
+    }
+    __syncthreads();
+
+    for (uint32_t i = tid; i < npw * qw; i += kThreads) {
+        const uint32_t j = i / qw, w = i - j * qw;
+        const uint32_t* c = cs + j * cw;
+        const uint32_t* hi = c + qw;
+        const uint32_t* dd = ds + j * dn;
+        uint32_t z = c[w] ^ hi[w] ^ (w < dn ? dd[w] : 0u);
+        for (uint32_t t = 0; t < sh.n_taps; ++t) {
+            const uint32_t e = sh.taps[t];
+            const int32_t src = (int32_t)w - (int32_t)(e >> 5);
+            const uint32_t eb = e & 31u;
+            // word w of (C_hi << e)
+            const uint32_t h1 = src >= 0 ? hi[src] : 0u;
+            const uint32_t h0 = src >= 1 ? hi[src - 1] : 0u;
+            z ^= eb ? funnel(h1, h0, 32u - eb) : h1;
+            // word w of (D << e)
+            const uint32_t d1 = (src >= 0 && (uint32_t)src < dn) ? dd[src] : 0u;
+            const uint32_t d0 = (src >= 1 && (uint32_t)(src - 1) < dn) ? dd[src - 1] : 0u;
+            z ^= eb ? funnel(d1, d0, 32u - eb) : d1;
+        }
+        out[(pair0 + j) * qw + w] = z;
+    }
+}
+
+template <int BW>
+hipError_t launch_bw(const ExtShape& s, const uint32_t* x, const uint32_t* y, uint32_t* out,
+                     uint64_t n_pairs, hipStream_t stream) {
+    const uint64_t groups = (n_pairs + s.ppw - 1) / s.ppw;
+    if (groups > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ext_ip_kernel<BW>, dim3((uint32_t)groups), dim3(kThreads),
+                       s.lds_words * 4u, stream, x, y, out, n_pairs, s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
+                          uint32_t* out, uint64_t n_pairs, hipStream_t stream) {
+    if (n_pairs == 0) return hipSuccess;
+    switch (s.bw) {
+        case 1: return launch_bw<1>(s, x, y, out, n_pairs, stream);
+        case 2: return launch_bw<2>(s, x, y, out, n_pairs, stream);
+        case 3: return launch_bw<3>(s, x, y, out, n_pairs, stream);
+        case 4: return launch_bw<4>(s, x, y, out, n_pairs, stream);
+        case 5: return launch_bw<5>(s, x, y, out, n_pairs, stream);
+        case 6: return launch_bw<6>(s, x, y, out, n_pairs, stream);
+        case 7: return launch_bw<7>(s, x, y, out, n_pairs, stream);
+        case 8: return launch_bw<8>(s, x, y, out, n_pairs, stream);
+        case 9: return launch_bw<9>(s, x, y, out, n_pairs, stream);
+        case 11: return launch_bw<11>(s, x, y, out, n_pairs, stream);
+        case 13: return launch_bw<13>(s, x, y, out, n_pairs, stream);
+        case 15: return launch_bw<15>(s, x, y, out, n_pairs, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace qext

@@ -1,0 +1,74 @@
+"""The C-ABI library on the CPU: it loads, exports every function the
+public header declares, and its host-side logic (modulus convention,
+irreducibility test, argument checks) agrees with the oracle.  No GPU
+compute is launched here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_14607_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qrng_ext.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ext_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), "libqrngext.so does not export %s" % name
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_default_modulus_matches_oracle_table():
+    table = oracle._read_table()
+    for m in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384):
+        assert binding.default_modulus(m) == table[m], m
+    # run-time search for degrees outside the built-in table
+    for m in (32, 96, 160, 192, 224, 320, 384, 768, 1536):
+        assert binding.default_modulus(m) == table[m], m
+
+
+def test_irreducibility_matches_oracle():
+    rng = np.random.Generator(np.random.PCG64(11))
+    for _ in range(60):
+        m = int(rng.integers(8, 300))
+        a, b, c = sorted(rng.choice(np.arange(1, m), 3, replace=False), reverse=True)
+        taps = (int(a), int(b), int(c))
+        assert binding.is_irreducible(m, taps) == oracle.is_irreducible(m, (m,) + taps + (0,))
+    for m in range(2, 64):
+        exps = oracle.modulus(m)
+        assert binding.is_irreducible(m, exps[1:-1])
+
+
+def test_strerror_and_bad_arguments():
+    lib = binding.load()
+    for code in range(-6, 1):
+        assert lib.ext_strerror(code)
+    assert binding.strerror(-4).startswith("device buffer full")
+    with pytest.raises(binding.ExtError):
+        binding.is_irreducible(8, (9,))
+    # ext_create argument checks come before any device call
+    p = binding.ExtParams()
+    lib.ext_params_init(ctypes.byref(p))
+    h = ctypes.c_void_p()
+    assert lib.ext_create(1000, 256, ctypes.byref(p), ctypes.byref(h)) == binding.EXT_EINVAL
+    assert lib.ext_create(0, 256, ctypes.byref(p), ctypes.byref(h)) == binding.EXT_EINVAL
+    assert lib.ext_create(1024, 0, ctypes.byref(p), ctypes.byref(h)) == binding.EXT_EINVAL
+    p.sample_bits = 16
+    assert lib.ext_create(1000 * 24, 24, ctypes.byref(p), ctypes.byref(h)) == binding.EXT_EINVAL
+    assert lib.ext_destroy(None) == 0
+    assert lib.ext_submit(None, None, 0, None, 0, None) == binding.EXT_EINVAL
