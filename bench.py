@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, also run a plain 64 MiB device copy 4 times (the "
+                         "reference kernel that scales HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every block pair is independent, so N GPUs "
@@ -149,6 +152,13 @@ def main():
     ms = start.elapsed_time(stop) / args.steps
     log("timed %d steps: %.4f ms/step (events), %.4f ms/step (wall)"
         % (args.steps, ms, wall * 1e3 / args.steps))
+
+    if args.copy_probe:
+        probe = torch.empty_like(x)
+        for _ in range(4):
+            probe.copy_(x)
+        torch.cuda.synchronize()
+        log("copy probe: 4 x %d bytes device-to-device" % x.numel())
 
     # parity check of the last step's output on sampled pairs (not timed)
     import oracle
