@@ -80,6 +80,12 @@ typedef struct {
     uint64_t device_bytes_cap;  /* per stream: cap on pending input bytes held on the
                                    device (admission); 0 means 256 MiB */
     int32_t device;             /* HIP device ordinal; -1 means the current device */
+    /* launch-plan knobs, 0 = the planner's choice (the autotuner sets them) */
+    uint32_t base_bits;         /* Karatsuba base-product size in bits (multiple of 32) */
+    uint32_t groups;            /* element groups per work item (divides n/m) */
+    uint32_t pairs_per_group;   /* block pairs per work-group */
+    uint32_t autotune;          /* 1: time the candidate plans on the device at create
+                                   time and keep the fastest (cached per shape) */
     uint32_t reserved[4];
 } ext_params;
 
@@ -171,6 +177,42 @@ int ext_drain(ext_stream *s, void *out, size_t out_cap, size_t *out_len, uint64_
  * handle is freed; using it afterwards is undefined.
  */
 int ext_stream_close(ext_stream *s, uint64_t *dropped_bits);
+
+/*
+ * Batched form: many independent stream pairs, each with its own block
+ * length n and output size m, computed by ONE persistent launch per base
+ * size that drains a device work queue of tiles (a stream's next few block
+ * pairs), the launches captured once in a hipGraph and replayed by
+ * ext_batch_run.  Every pointer is device memory of the batch's device and
+ * is borrowed for the life of the batch (the graph holds the addresses; the
+ * contents may change between runs).  Each item uses the conventional
+ * modulus of its m; the shape rules are those of ext_create.
+ */
+typedef struct ext_batch ext_batch;
+typedef struct {
+    uint64_t n_bits;     /* block length n of this stream pair */
+    uint32_t m_bits;     /* output bits per block pair */
+    uint32_t reserved;
+    const void *x, *y;   /* n_pairs * n/8 bytes each */
+    void *out;           /* n_pairs * m/8 bytes */
+    uint64_t n_pairs;
+} ext_batch_item;
+
+/* Plan every item (ext_params.autotune = 1 times candidate plans per shape
+ * on the device first), build the tile queue and capture the launches.
+ * p may be NULL; p->n_taps must be 0.  Uses p->hip_stream when
+ * use_hip_stream is set and the handle is not the null stream, else a stream
+ * of its own. */
+int ext_batch_create(const ext_batch_item *items, uint32_t n_items, const ext_params *p,
+                     ext_batch **out);
+/* Queue one pass over every item (asynchronous, on the batch's stream). */
+int ext_batch_run(ext_batch *b);
+/* Wait for the batch's stream. */
+int ext_batch_sync(ext_batch *b);
+/* One-line JSON: streams, tiles, pairs, launches (base size, tiles, grid). */
+int ext_batch_describe(const ext_batch *b, char *buf, size_t cap);
+/* Wait for queued work, then free.  NULL is accepted. */
+int ext_batch_destroy(ext_batch *b);
 
 /* Write a one-line JSON description of the context's launch plan (base
  * product size, Karatsuba levels, work-group shape) into buf. */

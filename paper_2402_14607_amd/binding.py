@@ -30,6 +30,8 @@ EXPORTED = (
     "ext_params_init", "ext_create", "ext_destroy", "ext_get_modulus", "ext_default_modulus",
     "ext_is_irreducible", "ext_extract", "ext_sync", "ext_stream_open", "ext_submit",
     "ext_poll", "ext_drain", "ext_stream_close", "ext_describe", "ext_strerror",
+    "ext_batch_create", "ext_batch_run", "ext_batch_sync", "ext_batch_describe",
+    "ext_batch_destroy",
 )
 
 
@@ -49,7 +51,23 @@ class ExtParams(ctypes.Structure):
         ("use_hip_stream", ctypes.c_uint32),
         ("device_bytes_cap", ctypes.c_uint64),
         ("device", ctypes.c_int32),
+        ("base_bits", ctypes.c_uint32),
+        ("groups", ctypes.c_uint32),
+        ("pairs_per_group", ctypes.c_uint32),
+        ("autotune", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32 * 4),
+    ]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("n_bits", ctypes.c_uint64),
+        ("m_bits", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("x", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("n_pairs", ctypes.c_uint64),
     ]
 
 
@@ -85,6 +103,12 @@ def load() -> ctypes.CDLL:
         "ext_stream_close": (ctypes.c_int, [vp, u64p]),
         "ext_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
         "ext_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "ext_batch_create": (ctypes.c_int, [ctypes.POINTER(BatchItem), u32,
+                                            ctypes.POINTER(ExtParams), ctypes.POINTER(vp)]),
+        "ext_batch_run": (ctypes.c_int, [vp]),
+        "ext_batch_sync": (ctypes.c_int, [vp]),
+        "ext_batch_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
+        "ext_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -130,26 +154,42 @@ def _ptr(buf) -> int:
     raise TypeError("expected a torch tensor or numpy array, got %r" % type(buf))
 
 
+def make_params(lib, *, device_memory=True, stream=None, taps=None, sample_bits=8,
+                device_bytes_cap=0, device=-1, autotune=False, base_bits=0, groups=0,
+                pairs_per_group=0) -> ExtParams:
+    p = ExtParams()
+    lib.ext_params_init(ctypes.byref(p))
+    p.sample_bits = sample_bits
+    p.mem_kind = EXT_MEM_DEVICE if device_memory else EXT_MEM_HOST
+    if taps:
+        p.n_taps = len(taps)
+        for i, t in enumerate(taps):
+            p.taps[i] = int(t)
+    if stream is not None:
+        p.hip_stream = ctypes.c_void_p(int(stream))
+        p.use_hip_stream = 1
+    if device_bytes_cap:
+        p.device_bytes_cap = device_bytes_cap
+    p.device = device
+    p.autotune = 1 if autotune else 0
+    p.base_bits = base_bits
+    p.groups = groups
+    p.pairs_per_group = pairs_per_group
+    return p
+
+
 class Extractor:
     """One ext_ctx: block length n_bits, m_bits output bits per block pair."""
 
     def __init__(self, n_bits: int, m_bits: int, *, device_memory: bool = True, stream=None,
-                 taps=None, sample_bits: int = 8, device_bytes_cap: int = 0, device: int = -1):
+                 taps=None, sample_bits: int = 8, device_bytes_cap: int = 0, device: int = -1,
+                 autotune: bool = False, base_bits: int = 0, groups: int = 0,
+                 pairs_per_group: int = 0):
         self.lib = load()
-        p = ExtParams()
-        self.lib.ext_params_init(ctypes.byref(p))
-        p.sample_bits = sample_bits
-        p.mem_kind = EXT_MEM_DEVICE if device_memory else EXT_MEM_HOST
-        if taps:
-            p.n_taps = len(taps)
-            for i, t in enumerate(taps):
-                p.taps[i] = int(t)
-        if stream is not None:
-            p.hip_stream = ctypes.c_void_p(int(stream))
-            p.use_hip_stream = 1
-        if device_bytes_cap:
-            p.device_bytes_cap = device_bytes_cap
-        p.device = device
+        p = make_params(self.lib, device_memory=device_memory, stream=stream, taps=taps,
+                        sample_bits=sample_bits, device_bytes_cap=device_bytes_cap,
+                        device=device, autotune=autotune, base_bits=base_bits, groups=groups,
+                        pairs_per_group=pairs_per_group)
         self.n_bits = n_bits
         self.m_bits = m_bits
         self.device_memory = device_memory
@@ -234,3 +274,56 @@ class Stream:
         _check(self.lib.ext_stream_close(self.handle, ctypes.byref(dropped)), "ext_stream_close")
         self.handle = ctypes.c_void_p()
         return dropped.value
+
+
+class Batch:
+    """One ext_batch: many (x, y, out) device-memory stream pairs with their
+    own n_bits and m_bits, run by one persistent launch per base size."""
+
+    def __init__(self, items, *, stream=None, autotune=False, base_bits=0, device=-1):
+        """items: iterable of (n_bits, m_bits, x, y, out, n_pairs) with torch
+        device tensors (kept alive by this object)."""
+        self.lib = load()
+        self._keep = []
+        arr = (BatchItem * max(1, len(items)))()
+        for i, (n, m, x, y, out, n_pairs) in enumerate(items):
+            arr[i].n_bits = n
+            arr[i].m_bits = m
+            arr[i].x = _ptr(x)
+            arr[i].y = _ptr(y)
+            arr[i].out = _ptr(out)
+            arr[i].n_pairs = n_pairs
+            self._keep.append((x, y, out))
+        p = make_params(self.lib, device_memory=True, stream=stream, autotune=autotune,
+                        base_bits=base_bits, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_batch_create(arr, len(items), ctypes.byref(p), ctypes.byref(self.handle)),
+               "ext_batch_create")
+
+    def run(self):
+        _check(self.lib.ext_batch_run(self.handle), "ext_batch_run")
+
+    def sync(self):
+        _check(self.lib.ext_batch_sync(self.handle), "ext_batch_sync")
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(self.lib.ext_batch_describe(self.handle, buf, 4096), "ext_batch_describe")
+        return buf.value.decode()
+
+    def close(self):
+        if self.handle:
+            self.lib.ext_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -18,31 +18,41 @@
 
 namespace qext {
 
+namespace {
+// base-product sizes (words) with a kernel instantiation
+bool base_instantiated(uint32_t bw) {
+    return (bw >= 1 && bw <= 9) || bw == 11 || bw == 13 || bw == 15 || bw == 16;
+}
+}  // namespace
+
 bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
-                uint32_t base_words_target, ExtShape* s) {
+                const PlanKnobs& knobs, ExtShape* s) {
     if (q == 0 || q % 32 || n_e == 0 || (n_taps != 1 && n_taps != 3)) return false;
-    const uint32_t target = base_words_target ? base_words_target : 8u;
+    const uint32_t target = knobs.base_words ? knobs.base_words : 8u;
+    if (target > (uint32_t)kMaxBaseWords) return false;
     const uint32_t qw = q / 32;
     const uint32_t v = (uint32_t)__builtin_ctz(qw);
     const uint32_t odd = qw >> v;
     if (odd > 15) return false;
-    uint32_t bw, levels;
-    if (odd <= target) {
-        uint32_t k = 0;
-        while (k < v && (odd << (k + 1)) <= target) ++k;
-        bw = odd << k;
-        levels = v - k;
-    } else {
-        bw = odd;
-        levels = v;
+    // base size: odd * 2^k words, the largest instantiated one not above the
+    // target (or the odd part itself when that is already larger)
+    uint32_t bw = odd, levels = v;
+    for (uint32_t k = 0; k <= v; ++k) {
+        const uint32_t cand = odd << k;
+        if (cand > target && k > 0) break;
+        if (base_instantiated(cand)) {
+            bw = cand;
+            levels = v - k;
+        }
     }
-    if (levels > 10) return false;
+    if (!base_instantiated(bw) || levels > 10) return false;
     uint32_t max_tap = 0;
     for (uint32_t t = 0; t < n_taps; ++t) {
         if (taps[t] == 0 || taps[t] >= q) return false;
         max_tap = std::max(max_tap, taps[t]);
     }
     if (2 * max_tap > q) return false;  // two folding passes suffice only below q/2
+    if (knobs.groups && n_e % knobs.groups) return false;
 
     ExtShape r{};
     r.q = q;
@@ -57,14 +67,15 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     for (uint32_t t = 0; t < 3; ++t) r.taps[t] = t < n_taps ? taps[t] : 0;
     r.dn = max_tap >= 2 ? (max_tap - 1 + 31) / 32 : 0;
 
-    // Pick the element grouping and pairs per work-group that keep the most
-    // lanes busy, with the LDS footprint under kMaxLdsBytes.
+    // Element grouping and pairs per work-group: keep the most lanes busy
+    // with the LDS footprint under kMaxLdsBytes (unless fixed by the knobs).
     double best_util = -1.0;
     for (uint32_t stage_try = levels > 0 ? 1u : 0u;; stage_try = 0) {
         for (uint32_t g = 1; g <= n_e; ++g) {
-            if (n_e % g) continue;
+            if (n_e % g || (knobs.groups && g != knobs.groups)) continue;
             const uint32_t per_pair = r.np * g;
             uint32_t ppw = per_pair >= (uint32_t)kThreads ? 1u : (uint32_t)kThreads / per_pair;
+            if (knobs.ppw) ppw = knobs.ppw;
             auto lds_words = [&](uint32_t pp) {
                 return pp * ((stage_try ? 2 * r.nw : 0) + 2 * qw + r.dn);
             };
@@ -269,8 +280,10 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         return EXT_EINVAL;
     }
     ExtShape shape;
+    qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group};
+    if (p->base_bits % 32) return EXT_EINVAL;
     if (!qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
-                          (uint32_t)taps.size(), 0, &shape))
+                          (uint32_t)taps.size(), knobs, &shape))
         return EXT_ENOTSUP;
 
     ext_ctx* c = new (std::nothrow) ext_ctx;
@@ -305,6 +318,20 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return EXT_EDEVICE;
+    }
+    if (p->autotune) {
+        qext::PlanKnobs tuned;
+        ExtShape ts;
+        if (qext::autotune_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
+                                 (uint32_t)taps.size(), c->stream, &tuned, nullptr) != hipSuccess ||
+            !qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
+                              (uint32_t)taps.size(), tuned, &ts)) {
+            (void)hipStreamDestroy(c->copy_stream);
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return EXT_EDEVICE;
+        }
+        c->shape = ts;
     }
     *out = c;
     return EXT_OK;

@@ -32,15 +32,52 @@ struct ExtShape {
                        // read from HBM with 16-byte loads, else 4)
 };
 
+// Tuning choices for one shape; 0 in a field means "planner's choice".
+struct PlanKnobs {
+    uint32_t base_words;  // base-product size in 32-bit words (1..16)
+    uint32_t groups;      // element groups per work item (divides n_e)
+    uint32_t ppw;         // block pairs per work-group
+};
+
 // Fills *s for q, n_e and the taps; returns false if the shape is outside
-// what the kernel supports.  base_words_target: preferred base size (0 =
-// default).
+// what the kernel supports.
 bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
-                uint32_t base_words_target, ExtShape* s);
+                const PlanKnobs& knobs, ExtShape* s);
+
+// One stream of a batch, as the batched kernel reads it from device memory.
+struct BatchStream {
+    const uint32_t* x;
+    const uint32_t* y;
+    uint32_t* out;
+    uint64_t n_pairs;
+    ExtShape shape;
+};
+
+// One work-group's worth of a batch: pairs [pair0, pair0 + npw) of a stream.
+struct BatchTile {
+    uint32_t stream;
+    uint32_t npw;
+    uint64_t pair0;
+};
 
 // Queue the extraction of n_pairs consecutive block pairs on `stream`.
 // x, y: device, n_pairs*nw words each; out: device, n_pairs*qw words.
 hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
                           uint32_t* out, uint64_t n_pairs, hipStream_t stream);
+
+// Queue the queue-head reset and one persistent launch of `grid` work-groups
+// over n_tiles tiles (all streams of the launch share base size bw).
+// streams, tiles, head: device memory.
+hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile* tiles,
+                        uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
+                        hipStream_t stream);
+
+// Autotuner: time the candidate plans of (q, n_e, taps) on `stream` and
+// return the fastest as knobs (cached per device and shape).
+hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
+                          hipStream_t stream, PlanKnobs* best, float* best_ms);
+
+// Resident work-groups per CU of the batched kernel at this LDS size.
+hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu);
 
 }  // namespace qext

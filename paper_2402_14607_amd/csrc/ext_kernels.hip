@@ -110,17 +110,15 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
     }
 }
 
+// One work-group's share: block pairs [pair0, pair0 + npw) of one stream
+// with shape sh (npw <= sh.ppw).  lds holds sh.lds_words words.  Ends after
+// the last global store, without a barrier.
 template <int BW>
-__global__ void __launch_bounds__(kThreads)
-ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
-              uint32_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
-    extern __shared__ uint32_t lds[];
+__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ x,
+                                              const uint32_t* __restrict__ y,
+                                              uint32_t* __restrict__ out, uint64_t pair0,
+                                              uint32_t npw, uint32_t* lds) {
     const uint32_t tid = threadIdx.x;
-    const uint64_t pair0 = (uint64_t)blockIdx.x * sh.ppw;
-    if (pair0 >= n_pairs) return;
-    const uint64_t left = n_pairs - pair0;
-    const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;  // pairs in this group
-
     const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
     uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
     uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
@@ -237,6 +235,48 @@ ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
     }
 }
 
+// Plain form: work-group g takes pairs [g*ppw, (g+1)*ppw) of one stream.
+template <int BW>
+__global__ void __launch_bounds__(kThreads)
+ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+              uint32_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
+    extern __shared__ uint32_t lds[];
+    const uint64_t pair0 = (uint64_t)blockIdx.x * sh.ppw;
+    if (pair0 >= n_pairs) return;
+    const uint64_t left = n_pairs - pair0;
+    const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;
+    extract_group<BW>(sh, x, y, out, pair0, npw, lds);
+}
+
+// Batched form: a persistent grid drains a device work queue of tiles
+// (stream, first pair, pair count) shared by many streams of different
+// shapes.  Each work-group takes the next tile with one atomic add on the
+// queue head and stops once the head passes n_tiles, so every wave exits.
+template <int BW>
+__global__ void __launch_bounds__(kThreads)
+ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __restrict__ tiles,
+                 uint32_t n_tiles, uint32_t* __restrict__ head) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(head, 1u);
+        __syncthreads();
+        const uint32_t t = __builtin_amdgcn_readfirstlane(next);
+        if (t >= n_tiles) break;
+        const BatchTile tile = tiles[t];
+        const BatchStream& st = streams[tile.stream];
+        const ExtShape sh = st.shape;
+        extract_group<BW>(sh, st.x, st.y, st.out, tile.pair0, tile.npw, lds);
+        __syncthreads();  // LDS and `next` are reused by the next tile
+    }
+}
+
+// Clears the queue head (a kernel, not a memset node, so that the pair can be
+// captured in a graph and replayed).
+__global__ void reset_head_kernel(uint32_t* head) {
+    if (threadIdx.x == 0) *head = 0u;
+}
+
 template <int BW>
 hipError_t launch_bw(const ExtShape& s, const uint32_t* x, const uint32_t* y, uint32_t* out,
                      uint64_t n_pairs, hipStream_t stream) {
@@ -247,26 +287,58 @@ hipError_t launch_bw(const ExtShape& s, const uint32_t* x, const uint32_t* y, ui
     return hipGetLastError();
 }
 
+template <int BW>
+hipError_t launch_batch_bw(const BatchStream* streams, const BatchTile* tiles, uint32_t n_tiles,
+                           uint32_t* head, uint32_t grid, uint32_t lds_bytes,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
+    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(kThreads), lds_bytes, stream,
+                       streams, tiles, n_tiles, head);
+    return hipGetLastError();
+}
+
+template <int BW>
+hipError_t occupancy_bw(uint32_t lds_bytes, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ext_batch_kernel<BW>,
+                                                        kThreads, lds_bytes);
+}
+
 }  // namespace
+
+#define QEXT_BW_CASES(F, ...)                      \
+    switch (bw) {                                  \
+        case 1: return F<1>(__VA_ARGS__);          \
+        case 2: return F<2>(__VA_ARGS__);          \
+        case 3: return F<3>(__VA_ARGS__);          \
+        case 4: return F<4>(__VA_ARGS__);          \
+        case 5: return F<5>(__VA_ARGS__);          \
+        case 6: return F<6>(__VA_ARGS__);          \
+        case 7: return F<7>(__VA_ARGS__);          \
+        case 8: return F<8>(__VA_ARGS__);          \
+        case 9: return F<9>(__VA_ARGS__);          \
+        case 11: return F<11>(__VA_ARGS__);        \
+        case 13: return F<13>(__VA_ARGS__);        \
+        case 15: return F<15>(__VA_ARGS__);        \
+        case 16: return F<16>(__VA_ARGS__);        \
+        default: return hipErrorInvalidValue;      \
+    }
+
+hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile* tiles,
+                        uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
+                        hipStream_t stream) {
+    if (n_tiles == 0) return hipSuccess;
+    QEXT_BW_CASES(launch_batch_bw, streams, tiles, n_tiles, head, grid, lds_bytes, stream)
+}
+
+hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu) {
+    QEXT_BW_CASES(occupancy_bw, lds_bytes, blocks_per_cu)
+}
 
 hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
                           uint32_t* out, uint64_t n_pairs, hipStream_t stream) {
     if (n_pairs == 0) return hipSuccess;
-    switch (s.bw) {
-        case 1: return launch_bw<1>(s, x, y, out, n_pairs, stream);
-        case 2: return launch_bw<2>(s, x, y, out, n_pairs, stream);
-        case 3: return launch_bw<3>(s, x, y, out, n_pairs, stream);
-        case 4: return launch_bw<4>(s, x, y, out, n_pairs, stream);
-        case 5: return launch_bw<5>(s, x, y, out, n_pairs, stream);
-        case 6: return launch_bw<6>(s, x, y, out, n_pairs, stream);
-        case 7: return launch_bw<7>(s, x, y, out, n_pairs, stream);
-        case 8: return launch_bw<8>(s, x, y, out, n_pairs, stream);
-        case 9: return launch_bw<9>(s, x, y, out, n_pairs, stream);
-        case 11: return launch_bw<11>(s, x, y, out, n_pairs, stream);
-        case 13: return launch_bw<13>(s, x, y, out, n_pairs, stream);
-        case 15: return launch_bw<15>(s, x, y, out, n_pairs, stream);
-        default: return hipErrorInvalidValue;
-    }
+    const uint32_t bw = s.bw;
+    QEXT_BW_CASES(launch_bw, s, x, y, out, n_pairs, stream)
 }
 
 }  // namespace qext

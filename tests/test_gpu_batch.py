@@ -1,0 +1,156 @@
+"""Batched form on the GPU: many stream pairs with different block lengths in
+one persistent launch per base size, replayed from a captured hipGraph.
+
+Every stream's output in the batch must equal the CPU oracle's, and equal
+what the plain form gives for that stream alone (bit-exact).  Graph replays
+are interleaved with eager work and each replay is checked.
+"""
+from __future__ import annotations
+
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_14607_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    binding.load()
+    return d
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def to_dev(dev, arr):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+
+
+def plain_alone(dev, n, m, x, y, n_pairs):
+    import torch
+
+    out = torch.zeros(max(1, n_pairs * m // 8), dtype=torch.uint8, device=dev)
+    with binding.Extractor(n, m, device_memory=True,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        ex.extract(x, y, out, n_pairs)
+        ex.sync()
+    return out[: n_pairs * m // 8].cpu().numpy()
+
+
+def make_items(dev, specs, seed):
+    """specs: list of (n, m, pairs) -> items with random data, plus host copies."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    items, host = [], []
+    for n, m, pairs in specs:
+        xh = rng.integers(0, 256, max(1, pairs * n // 8), dtype=np.uint8)
+        yh = rng.integers(0, 256, max(1, pairs * n // 8), dtype=np.uint8)
+        out = torch.full((max(1, pairs * m // 8),), 0xA5, dtype=torch.uint8, device=dev)
+        items.append((n, m, to_dev(dev, xh), to_dev(dev, yh), out, pairs))
+        host.append((xh, yh))
+    return items, host
+
+
+MIXED = [(2048, 512, 17), (4096, 1024, 5), (8192, 2048, 9), (16384, 4096, 3), (32768, 8192, 2),
+         (1024, 256, 40), (384, 96, 33), (96 * 5, 96, 7), (2048, 2048, 4), (8192, 512, 6),
+         (2048, 512, 0), (65536, 16384, 1)]
+
+
+def test_mixed_batch_against_oracle(dev):
+    items, host = make_items(dev, MIXED, 77)
+    say("mixed batch: %d streams" % len(items))
+    with binding.Batch(items) as b:
+        desc = json.loads(b.describe())
+        assert desc["graph"] is True
+        assert len(desc["launches"]) >= 2  # 256-bit base and the 96-bit stream's own base
+        b.run()
+        b.sync()
+        for (n, m, x, y, out, pairs), (xh, yh) in zip(items, host):
+            got = out[: pairs * m // 8].cpu().numpy()
+            want = oracle.ext_blocks(xh, yh, n, m, n_pairs=pairs)
+            assert np.array_equal(got, want), (n, m, pairs)
+            if pairs:
+                assert np.array_equal(got, plain_alone(dev, n, m, x, y, pairs)), (n, m)
+
+
+def test_graph_replays_with_eager_work_between(dev):
+    import torch
+
+    items, host = make_items(dev, MIXED[:6], 78)
+    with binding.Batch(items) as b:
+        for rep in range(4):
+            say("replay %d" % rep)
+            # eager work between replays: rewrite every input in place
+            for (n, m, x, y, out, pairs) in items:
+                x.copy_(torch.roll(x, shifts=rep + 1))
+                y.bitwise_xor_(torch.full_like(y, rep * 37 + 1))
+                out.fill_(0xA5)
+            torch.cuda.synchronize()
+            b.run()
+            b.sync()
+            for (n, m, x, y, out, pairs) in items:
+                got = out[: pairs * m // 8].cpu().numpy()
+                want = oracle.ext_blocks(x.cpu().numpy(), y.cpu().numpy(), n, m, n_pairs=pairs)
+                assert np.array_equal(got, want), (rep, n, m)
+
+
+def test_batched_workload_alone_equals_mixed(dev):
+    """The full batched workload (64 streams, 4096 pairs each, n from 2048
+    to 32768): every stream alone (plain form) equals its bytes in the mix;
+    first and last pair of each stream against the oracle."""
+    import torch
+
+    w = inputs.batched()
+    say("batched workload: %d streams" % len(w.streams))
+    items = []
+    for s in w.streams:
+        out = torch.zeros(s.n_pairs * s.m_bits // 8, dtype=torch.uint8, device=dev)
+        items.append((s.n_bits, s.m_bits, to_dev(dev, s.x), to_dev(dev, s.y), out, s.n_pairs))
+    with binding.Batch(items, autotune=True) as b:
+        say(b.describe())
+        b.run()
+        b.sync()
+        for k, ((n, m, x, y, out, pairs), s) in enumerate(zip(items, w.streams)):
+            got = out.cpu().numpy()
+            alone = plain_alone(dev, n, m, x, y, pairs)
+            assert np.array_equal(got, alone), "stream %d differs alone vs in the mix" % k
+            if k % 8 == 0:
+                idx = np.asarray([0, pairs - 1], dtype=np.uint64)
+                want = oracle.ext_sampled(s.x, s.y, idx, n, m)
+                qb = m // 8
+                g = np.concatenate([got[:qb], got[(pairs - 1) * qb:]])
+                assert np.array_equal(g, want), "stream %d vs oracle" % k
+
+
+def test_autotuned_plan_is_bit_identical(dev):
+    import torch
+
+    w = inputs.plain_workload(8192, 2048, 300, 61, 62)
+    x, y = to_dev(dev, w.x), to_dev(dev, w.y)
+    outs = []
+    for kw in (dict(), dict(autotune=True), dict(base_bits=128), dict(base_bits=512),
+               dict(groups=4), dict(groups=2, base_bits=128)):
+        out = torch.zeros(300 * 256, dtype=torch.uint8, device=dev)
+        with binding.Extractor(8192, 2048, device_memory=True,
+                               stream=torch.cuda.current_stream(dev).cuda_stream, **kw) as ex:
+            say("plan %s: %s" % (kw, ex.describe()))
+            ex.extract(x, y, out, 300)
+            ex.sync()
+        outs.append(out.cpu().numpy())
+    want = oracle.ext_blocks(w.x, w.y, 8192, 2048)
+    for o in outs:
+        assert np.array_equal(o, want)
