@@ -214,6 +214,106 @@ int ext_batch_describe(const ext_batch *b, char *buf, size_t cap);
 /* Wait for queued work, then free.  NULL is accepted. */
 int ext_batch_destroy(ext_batch *b);
 
+/*
+ * Served form: continuous batching of many generator channels.  Each channel
+ * is an (X, Y) pair of raw sample streams with its own block length n and
+ * output size m (conventional modulus).  Chunks of any length arrive through
+ * ext_server_submit (host memory, copied before the call returns); a
+ * scheduler thread inside the server repeatedly takes everything that
+ * arrived, moves it to the channels' device rings and computes every block
+ * pair completed so far on every channel in one persistent launch per base
+ * size, while the previous cycle is still on the GPU (at most two cycles in
+ * flight).  Outputs come back per channel, in block order, exactly once.
+ * Admission: a channel holds at most ring_blocks blocks between received and
+ * polled, and a cycle takes at most stage_bytes of input and returns at most
+ * outbox_bytes of output; beyond that ext_server_submit returns EXT_EAGAIN
+ * and consumes nothing.  All calls are thread-safe.
+ */
+typedef struct ext_server ext_server;
+typedef struct {
+    uint32_t max_channels;  /* channel slots (default 256) */
+    uint32_t ring_blocks;   /* device ring per channel side, in blocks (default 512) */
+    uint64_t stage_bytes;   /* input bytes one cycle can take (default 64 MiB) */
+    uint64_t outbox_bytes;  /* output bytes one cycle can return (default 32 MiB) */
+    uint32_t max_tiles;     /* work-group tiles per cycle (default 131072) */
+    uint32_t max_descs;     /* copy ranges per cycle (default 65536) */
+    uint32_t poll_us;       /* scheduler re-check period while a cycle runs (default 20) */
+    uint32_t reserved[5];
+} ext_server_config;
+typedef struct {
+    uint64_t cycles, tiles, pairs, bytes_in;
+    uint64_t eagain_ring;   /* submissions refused: channel ring full */
+    uint64_t eagain_stage;  /* submissions refused: cycle staging full */
+    uint64_t gpu_busy_ns;   /* sum over cycles of launch-to-harvest time */
+    uint64_t reserved[5];
+} ext_server_stats;
+
+void ext_server_config_init(ext_server_config *c);
+/* cfg and p may be NULL (defaults); p->n_taps must be 0; p->autotune,
+ * base_bits, groups, pairs_per_group, device and hip_stream apply. */
+int ext_server_create(const ext_server_config *cfg, const ext_params *p, ext_server **out);
+/* Open a channel; *channel receives its index.  EXT_EAGAIN: no free slot. */
+int ext_server_open(ext_server *s, uint64_t n_bits, uint32_t m_bits, uint32_t *channel);
+int ext_server_submit(ext_server *s, uint32_t channel, const void *x, size_t x_len,
+                      const void *y, size_t y_len);
+/* Non-blocking.  Copies finished outputs (whole blocks, block order) into
+ * host memory out; ready_ns (may be NULL, room for out_cap/(m/8) entries)
+ * receives for each returned block the steady-clock time (ns) at which the
+ * server saw it finish; *blocks_done the blocks returned so far. */
+int ext_server_poll(ext_server *s, uint32_t channel, void *out, size_t out_cap, size_t *out_len,
+                    uint64_t *ready_ns, uint64_t *blocks_done);
+/* Close a channel after its launched pairs finish; the trailing partial
+ * block and any unpolled output are dropped (*dropped_bits: input bits not
+ * part of a complete pair, larger side). */
+int ext_server_close(ext_server *s, uint32_t channel, uint64_t *dropped_bits);
+int ext_server_stats_get(ext_server *s, ext_server_stats *out);
+/* Stop the scheduler after the cycles in flight, then free everything. */
+int ext_server_destroy(ext_server *s);
+
+/*
+ * Load generator for the served form: replays Poisson chunk arrivals on many
+ * channels in real time against either the server (EXT_SIM_SERVED) or the
+ * plain streaming form with one ext_stream and one launch per arriving chunk
+ * per channel (EXT_SIM_PLAIN), and measures per-block latency from the
+ * scheduled arrival of the chunk that completes a block to the moment a
+ * poll returns its output.
+ */
+enum { EXT_SIM_SERVED = 0, EXT_SIM_PLAIN = 1 };
+typedef struct {
+    uint32_t n_channels;
+    uint32_t mode;                  /* EXT_SIM_SERVED or EXT_SIM_PLAIN */
+    const uint64_t *n_bits;         /* per channel */
+    const uint32_t *m_bits;         /* per channel */
+    const uint8_t *const *pool_x;   /* per channel: source bytes, read cyclically */
+    const uint8_t *const *pool_y;
+    const uint64_t *pool_bytes;     /* per channel: pool length, a multiple of n/8 */
+    double raw_bytes_per_s;         /* aggregate X+Y input rate, split evenly over channels */
+    uint32_t min_chunk_blocks, max_chunk_blocks;  /* chunk = k blocks of X and of Y, k uniform */
+    double warmup_s, duration_s;    /* latency counted for arrivals in [warmup, warmup+duration) */
+    double grace_s;                 /* wait after the last arrival for outstanding blocks */
+    double max_lag_s;               /* stop submitting once this far behind schedule (0 = never);
+                                       the chunks left count as missing */
+    uint64_t seed;
+    uint8_t *const *capture;        /* optional per channel: every output byte, in order */
+    const uint64_t *capture_cap;    /* per channel capacity of capture */
+    const ext_server_config *server_cfg;  /* served mode; NULL = defaults */
+    const ext_params *params;       /* NULL = defaults */
+} ext_sim_config;
+typedef struct {
+    double window_s;                /* measurement window length */
+    double out_gbps, in_gbps;       /* bits of blocks arrived in the window and returned, / window */
+    double offered_in_gbps;         /* raw bits scheduled in the window / window */
+    double lat_p50_us, lat_p99_us, lat_max_us, lat_mean_us;
+    uint64_t blocks_measured;       /* blocks arrived in the window */
+    uint64_t blocks_missing;        /* of those, not returned before the grace time ran out */
+    uint64_t chunks, eagain;
+    double max_submit_lag_us;       /* worst lateness of a submission behind its schedule */
+    uint64_t cycles;                /* served mode: scheduler cycles */
+    uint64_t reserved[6];
+} ext_sim_result;
+/* capture_len (may be NULL): per channel, bytes written to capture. */
+int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t *capture_len);
+
 /* Write a one-line JSON description of the context's launch plan (base
  * product size, Karatsuba levels, work-group shape) into buf. */
 int ext_describe(const ext_ctx *c, char *buf, size_t cap);

@@ -31,8 +31,13 @@ EXPORTED = (
     "ext_is_irreducible", "ext_extract", "ext_sync", "ext_stream_open", "ext_submit",
     "ext_poll", "ext_drain", "ext_stream_close", "ext_describe", "ext_strerror",
     "ext_batch_create", "ext_batch_run", "ext_batch_sync", "ext_batch_describe",
-    "ext_batch_destroy",
+    "ext_batch_destroy", "ext_server_config_init", "ext_server_create", "ext_server_open",
+    "ext_server_submit", "ext_server_poll", "ext_server_close", "ext_server_stats_get",
+    "ext_server_destroy", "ext_serve_simulate",
 )
+
+EXT_SIM_SERVED = 0
+EXT_SIM_PLAIN = 1
 
 
 class ExtError(RuntimeError):
@@ -69,6 +74,59 @@ class BatchItem(ctypes.Structure):
         ("out", ctypes.c_void_p),
         ("n_pairs", ctypes.c_uint64),
     ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("max_channels", ctypes.c_uint32),
+        ("ring_blocks", ctypes.c_uint32),
+        ("stage_bytes", ctypes.c_uint64),
+        ("outbox_bytes", ctypes.c_uint64),
+        ("max_tiles", ctypes.c_uint32),
+        ("max_descs", ctypes.c_uint32),
+        ("poll_us", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("cycles", "tiles", "pairs", "bytes_in", "eagain_ring", "eagain_stage",
+                 "gpu_busy_ns")] + [("reserved", ctypes.c_uint64 * 5)]
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_channels", ctypes.c_uint32),
+        ("mode", ctypes.c_uint32),
+        ("n_bits", ctypes.POINTER(ctypes.c_uint64)),
+        ("m_bits", ctypes.POINTER(ctypes.c_uint32)),
+        ("pool_x", ctypes.POINTER(ctypes.c_void_p)),
+        ("pool_y", ctypes.POINTER(ctypes.c_void_p)),
+        ("pool_bytes", ctypes.POINTER(ctypes.c_uint64)),
+        ("raw_bytes_per_s", ctypes.c_double),
+        ("min_chunk_blocks", ctypes.c_uint32),
+        ("max_chunk_blocks", ctypes.c_uint32),
+        ("warmup_s", ctypes.c_double),
+        ("duration_s", ctypes.c_double),
+        ("grace_s", ctypes.c_double),
+        ("max_lag_s", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("capture", ctypes.POINTER(ctypes.c_void_p)),
+        ("capture_cap", ctypes.POINTER(ctypes.c_uint64)),
+        ("server_cfg", ctypes.POINTER(ServerConfig)),
+        ("params", ctypes.POINTER(ExtParams)),
+    ]
+
+
+class SimResult(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("window_s", "out_gbps", "in_gbps", "offered_in_gbps", "lat_p50_us",
+                 "lat_p99_us", "lat_max_us", "lat_mean_us")] + \
+               [(n, ctypes.c_uint64) for n in ("blocks_measured", "blocks_missing", "chunks",
+                                               "eagain")] + \
+               [("max_submit_lag_us", ctypes.c_double), ("cycles", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 6)]
 
 
 _lib = None
@@ -109,6 +167,17 @@ def load() -> ctypes.CDLL:
         "ext_batch_sync": (ctypes.c_int, [vp]),
         "ext_batch_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
         "ext_batch_destroy": (ctypes.c_int, [vp]),
+        "ext_server_config_init": (None, [ctypes.POINTER(ServerConfig)]),
+        "ext_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ExtParams),
+                                             ctypes.POINTER(vp)]),
+        "ext_server_open": (ctypes.c_int, [vp, u64, u32, ctypes.POINTER(u32)]),
+        "ext_server_submit": (ctypes.c_int, [vp, u32, vp, sz, vp, sz]),
+        "ext_server_poll": (ctypes.c_int, [vp, u32, vp, sz, szp, u64p, u64p]),
+        "ext_server_close": (ctypes.c_int, [vp, u32, u64p]),
+        "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
+        "ext_server_destroy": (ctypes.c_int, [vp]),
+        "ext_serve_simulate": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult),
+                                              u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -327,3 +396,129 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def server_config(**kw) -> ServerConfig:
+    lib = load()
+    c = ServerConfig()
+    lib.ext_server_config_init(ctypes.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """One ext_server (continuous batching over many channels).  Host-memory
+    numpy arrays in and out."""
+
+    def __init__(self, *, config: ServerConfig | None = None, autotune=False, device=-1):
+        self.lib = load()
+        self.cfg = config or server_config()
+        p = make_params(self.lib, device_memory=False, autotune=autotune, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_server_create(ctypes.byref(self.cfg), ctypes.byref(p),
+                                          ctypes.byref(self.handle)), "ext_server_create")
+
+    def open(self, n_bits: int, m_bits: int) -> int:
+        ch = ctypes.c_uint32()
+        _check(self.lib.ext_server_open(self.handle, n_bits, m_bits, ctypes.byref(ch)),
+               "ext_server_open")
+        return ch.value
+
+    def submit(self, ch: int, x: np.ndarray, y: np.ndarray) -> int:
+        x = np.ascontiguousarray(x, dtype=np.uint8)
+        y = np.ascontiguousarray(y, dtype=np.uint8)
+        rc = self.lib.ext_server_submit(self.handle, ch, x.ctypes.data if x.size else None, x.size,
+                                        y.ctypes.data if y.size else None, y.size)
+        if rc == EXT_EAGAIN:
+            return rc
+        return _check(rc, "ext_server_submit")
+
+    def poll(self, ch: int, out: np.ndarray):
+        n = ctypes.c_size_t()
+        done = ctypes.c_uint64()
+        _check(self.lib.ext_server_poll(self.handle, ch, out.ctypes.data, out.size, ctypes.byref(n),
+                                        None, ctypes.byref(done)), "ext_server_poll")
+        return n.value, done.value
+
+    def close_channel(self, ch: int) -> int:
+        d = ctypes.c_uint64()
+        _check(self.lib.ext_server_close(self.handle, ch, ctypes.byref(d)), "ext_server_close")
+        return d.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self.lib.ext_server_stats_get(self.handle, ctypes.byref(st)), "ext_server_stats_get")
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_ if n != "reserved"}
+
+    def close(self):
+        if self.handle:
+            self.lib.ext_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max_chunk=64,
+             warmup_s=1.0, duration_s=5.0, grace_s=2.0, max_lag_s=0.0, seed=4, capture=False,
+             config: ServerConfig | None = None, autotune=False):
+    """Run the load generator.  channels: list of (n_bits, m_bits, pool_x, pool_y)
+    with uint8 numpy pools.  Returns (result dict, list of captured outputs or None)."""
+    lib = load()
+    n = len(channels)
+    nbits = (ctypes.c_uint64 * n)(*[c[0] for c in channels])
+    mbits = (ctypes.c_uint32 * n)(*[c[1] for c in channels])
+    pools = [(np.ascontiguousarray(c[2], dtype=np.uint8), np.ascontiguousarray(c[3], dtype=np.uint8))
+             for c in channels]
+    px = (ctypes.c_void_p * n)(*[p[0].ctypes.data for p in pools])
+    py = (ctypes.c_void_p * n)(*[p[1].ctypes.data for p in pools])
+    plen = (ctypes.c_uint64 * n)(*[min(p[0].size, p[1].size) for p in pools])
+    cfg = SimConfig()
+    cfg.n_channels = n
+    cfg.mode = mode
+    cfg.n_bits = nbits
+    cfg.m_bits = mbits
+    cfg.pool_x = px
+    cfg.pool_y = py
+    cfg.pool_bytes = plen
+    cfg.raw_bytes_per_s = raw_bytes_per_s
+    cfg.min_chunk_blocks = min_chunk
+    cfg.max_chunk_blocks = max_chunk
+    cfg.warmup_s = warmup_s
+    cfg.duration_s = duration_s
+    cfg.grace_s = grace_s
+    cfg.max_lag_s = max_lag_s
+    cfg.seed = seed
+    caps = None
+    if capture:
+        bufs = []
+        for (nb_, mb_, _, _) in channels:
+            # generous: every chunk of the horizon at the channel's share of the rate
+            share = raw_bytes_per_s / n * (warmup_s + duration_s) * 3.0 + 64 * nb_ // 8 * 4
+            bufs.append(np.zeros(int(share * mb_ / (2 * nb_)) + 1024, dtype=np.uint8))
+        caps = bufs
+        cfg.capture = (ctypes.c_void_p * n)(*[b.ctypes.data for b in bufs])
+        cfg.capture_cap = (ctypes.c_uint64 * n)(*[b.size for b in bufs])
+    sc = config or server_config()
+    cfg.server_cfg = ctypes.pointer(sc)
+    p = make_params(lib, device_memory=False, autotune=autotune)
+    cfg.params = ctypes.pointer(p)
+    res = SimResult()
+    clen = (ctypes.c_uint64 * n)()
+    rc = lib.ext_serve_simulate(ctypes.byref(cfg), ctypes.byref(res), clen)
+    if rc not in (EXT_OK, EXT_EAGAIN):
+        raise ExtError(rc, "ext_serve_simulate")
+    out = {n_: getattr(res, n_) for n_, _ in SimResult._fields_ if n_ != "reserved"}
+    out["admission_gave_up"] = rc == EXT_EAGAIN
+    captured = [b[: clen[i]] for i, b in enumerate(caps)] if caps is not None else None
+    return out, captured

@@ -12,7 +12,8 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqrngext.so")
-SOURCES = ["ext_kernels.hip", "ext_api.cpp", "ext_batch.cpp", "gf2_modulus.cpp"]
+SOURCES = ["ext_kernels.hip", "ext_api.cpp", "ext_batch.cpp", "ext_server.cpp", "serve_sim.cpp",
+           "gf2_modulus.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -279,7 +279,7 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                     const double per_pair = (double)st.shape.np * st.shape.n_e;
                     for (uint64_t p0 = 0; p0 < st.n_pairs; p0 += st.shape.ppw) {
                         const uint32_t k = (uint32_t)std::min<uint64_t>(st.shape.ppw, st.n_pairs - p0);
-                        tl.push_back({per_pair * k, BatchTile{si, k, p0}});
+                        tl.push_back({per_pair * k, BatchTile{si, k, p0, p0 * st.shape.qw}});
                     }
                 }
                 // longest tiles first, so the queue ends with short ones

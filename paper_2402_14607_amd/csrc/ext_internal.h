@@ -53,11 +53,14 @@ struct BatchStream {
     ExtShape shape;
 };
 
-// One work-group's worth of a batch: pairs [pair0, pair0 + npw) of a stream.
+// One work-group's worth of a batch: npw consecutive pairs of a stream,
+// whose blocks start at pair slot in_pair0 of the stream's x and y, and
+// whose outputs go to word out_word0 of the stream's out.
 struct BatchTile {
     uint32_t stream;
     uint32_t npw;
-    uint64_t pair0;
+    uint64_t in_pair0;
+    uint64_t out_word0;
 };
 
 // Queue the extraction of n_pairs consecutive block pairs on `stream`.
@@ -76,6 +79,19 @@ hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile
 // return the fastest as knobs (cached per device and shape).
 hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                           hipStream_t stream, PlanKnobs* best, float* best_ms);
+
+// One byte range to move from a staging buffer into a device ring.
+struct ScatterDesc {
+    uint64_t src_off;  // byte offset in the staging buffer
+    uint8_t* dst;      // device destination
+    uint32_t len;      // bytes
+    uint32_t pad;
+};
+
+// Queue the copy of every descriptor's range (src: device staging buffer,
+// descs: device array).
+hipError_t launch_scatter(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
+                          hipStream_t stream);
 
 // Resident work-groups per CU of the batched kernel at this LDS size.
 hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu);

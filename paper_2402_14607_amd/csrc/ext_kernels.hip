@@ -110,14 +110,15 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
     }
 }
 
-// One work-group's share: block pairs [pair0, pair0 + npw) of one stream
-// with shape sh (npw <= sh.ppw).  lds holds sh.lds_words words.  Ends after
-// the last global store, without a barrier.
+// One work-group's share: npw consecutive block pairs of one stream with
+// shape sh (npw <= sh.ppw); xg, yg point at the first pair's blocks and out at
+// its output.  lds holds sh.lds_words words.  Ends after the last global
+// store, without a barrier.
 template <int BW>
-__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ x,
-                                              const uint32_t* __restrict__ y,
-                                              uint32_t* __restrict__ out, uint64_t pair0,
-                                              uint32_t npw, uint32_t* lds) {
+__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ xg,
+                                              const uint32_t* __restrict__ yg,
+                                              uint32_t* __restrict__ out, uint32_t npw,
+                                              uint32_t* lds) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
     uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
@@ -126,8 +127,6 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
     uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
 
     for (uint32_t i = tid; i < npw * cw; i += kThreads) cs[i] = 0;
-    const uint32_t* xg = x + pair0 * nw;
-    const uint32_t* yg = y + pair0 * nw;
     if (sh.stage) {
         for (uint32_t i = tid; i < npw * nw; i += kThreads) {
             xs[i] = xg[i];
@@ -231,7 +230,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
             const uint32_t d0 = (src >= 1 && (uint32_t)(src - 1) < dn) ? dd[src - 1] : 0u;
             z ^= eb ? funnel(d1, d0, 32u - eb) : d1;
         }
-        out[(pair0 + j) * qw + w] = z;
+        out[(uint64_t)j * qw + w] = z;
     }
 }
 
@@ -245,7 +244,7 @@ ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
     if (pair0 >= n_pairs) return;
     const uint64_t left = n_pairs - pair0;
     const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;
-    extract_group<BW>(sh, x, y, out, pair0, npw, lds);
+    extract_group<BW>(sh, x + pair0 * sh.nw, y + pair0 * sh.nw, out + pair0 * sh.qw, npw, lds);
 }
 
 // Batched form: a persistent grid drains a device work queue of tiles
@@ -266,8 +265,28 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         const BatchTile tile = tiles[t];
         const BatchStream& st = streams[tile.stream];
         const ExtShape sh = st.shape;
-        extract_group<BW>(sh, st.x, st.y, st.out, tile.pair0, tile.npw, lds);
+        extract_group<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
+                          st.out + tile.out_word0, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
+    }
+}
+
+// Copies each descriptor's byte range from the staging buffer to its
+// destination (one work-group per descriptor, 32-bit words when aligned).
+__global__ void __launch_bounds__(kThreads)
+scatter_kernel(const uint8_t* __restrict__ src, const ScatterDesc* __restrict__ descs,
+               uint32_t n_descs) {
+    for (uint32_t d = blockIdx.x; d < n_descs; d += gridDim.x) {
+        const ScatterDesc sd = descs[d];
+        const uint8_t* s = src + sd.src_off;
+        uint8_t* t = sd.dst;
+        if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 3u) == 0) {
+            const uint32_t* s4 = reinterpret_cast<const uint32_t*>(s);
+            uint32_t* t4 = reinterpret_cast<uint32_t*>(t);
+            for (uint32_t i = threadIdx.x; i < sd.len / 4; i += kThreads) t4[i] = s4[i];
+        } else {
+            for (uint32_t i = threadIdx.x; i < sd.len; i += kThreads) t[i] = s[i];
+        }
     }
 }
 
@@ -328,6 +347,14 @@ hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile
                         hipStream_t stream) {
     if (n_tiles == 0) return hipSuccess;
     QEXT_BW_CASES(launch_batch_bw, streams, tiles, n_tiles, head, grid, lds_bytes, stream)
+}
+
+hipError_t launch_scatter(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
+                          hipStream_t stream) {
+    if (n_descs == 0) return hipSuccess;
+    const uint32_t grid = n_descs < 2048u ? n_descs : 2048u;
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(kThreads), 0, stream, src, descs, n_descs);
+    return hipGetLastError();
 }
 
 hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu) {

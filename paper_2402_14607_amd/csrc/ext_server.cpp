@@ -1,0 +1,596 @@
+// ext_server.cpp -- served form: continuous batching of many generator
+// channels (each an (X, Y) pair of sample streams with its own block length).
+//
+// Data path, per cycle of the scheduler thread:
+//   submit() copies raw chunks into the cycle's pinned staging area and notes
+//   where each byte range goes in its channel's device ring (X and Y rings of
+//   R blocks each; block l lives in slot l mod R, so a block never wraps).
+//   The scheduler then queues on one HIP stream: the staging copy to the
+//   device, a scatter kernel that moves the ranges into the rings, one
+//   persistent launch per base size over a tile queue holding every block
+//   pair completed so far on every channel, and the copy of the outputs back
+//   to pinned memory; an event marks the cycle done.  Up to two cycles are in
+//   flight: chunks that arrive while one is on the GPU go into the next.
+//   Completed outputs are moved to per-channel host rings that poll() reads.
+//
+// Admission: a channel may hold at most R blocks between "received" and
+// "polled"; a cycle's staging area and outbox are bounded.  submit() answers
+// EXT_EAGAIN when either would overflow; nothing is consumed then.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/qrng_ext.h"
+#include "ext_internal.h"
+#include "gf2_modulus.h"
+
+using qext::BatchStream;
+using qext::BatchTile;
+using qext::ExtShape;
+using qext::ScatterDesc;
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Channel {
+    bool open = false;
+    uint64_t n_bits = 0, nb = 0, qb = 0;
+    uint32_t m_bits = 0;
+    ExtShape shape{};
+    uint64_t R = 0;               // ring blocks
+    uint8_t* ring_x = nullptr;    // device, R * nb bytes
+    uint8_t* ring_y = nullptr;
+    uint64_t x_recv = 0, y_recv = 0;   // bytes accepted (reserved in some cycle)
+    uint64_t x_ok = 0, y_ok = 0;       // bytes scattered by cycles already launched
+    uint64_t launched = 0, completed = 0, polled = 0;  // block pairs
+    std::vector<uint8_t> out_ring;             // R * qb bytes, slot l mod R
+    std::vector<uint64_t> ready_ns;            // R completion times
+};
+
+struct Range {
+    uint32_t ch;
+    uint32_t n;
+    uint64_t first_pair;
+    uint64_t out_off;  // byte offset in the outbox
+};
+
+struct Group {
+    uint32_t bw, tile_off, n_tiles, lds_bytes, grid;
+};
+
+// A submission's end position on one side, recorded in the cycle that holds it.
+struct Resv {
+    uint32_t ch;
+    uint32_t side;  // 0 = X, 1 = Y
+    uint64_t end;
+};
+
+struct Slot {
+    uint8_t* h_in = nullptr;   // pinned: data | descs | streams | tiles
+    uint8_t* d_in = nullptr;   // device mirror (+ queue heads)
+    uint8_t* h_out = nullptr;  // pinned outbox
+    uint8_t* d_out = nullptr;  // device outbox
+    hipEvent_t done = nullptr;
+    uint64_t data_used = 0;
+    uint32_t n_descs = 0;
+    int pending = 0;            // submissions still copying into h_in
+    std::vector<Resv> resv;
+    std::vector<Range> ranges;
+    std::vector<Group> groups;
+    uint32_t n_tiles = 0;
+    uint64_t out_bytes = 0;
+    uint64_t launched_ns = 0;
+};
+
+}  // namespace
+
+struct ext_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cus = 1;
+    ext_server_config cfg{};
+    ext_params params{};
+    std::vector<Channel> ch;
+    // slot layout
+    size_t off_desc = 0, off_streams = 0, off_tiles = 0, off_heads = 0, in_bytes = 0;
+    Slot slots[3];
+    int filling = 0;
+    std::deque<int> inflight;
+    std::map<std::pair<uint32_t, uint32_t>, int> occ_cache;  // (bw, lds) -> blocks per CU
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread sched;
+    bool stop = false;
+    int sticky = EXT_OK;
+    ext_server_stats stats{};
+};
+
+namespace {
+
+void server_free(ext_server* s) {
+    for (Slot& sl : s->slots) {
+        if (sl.h_in) (void)hipHostFree(sl.h_in);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        (void)hipFree(sl.d_in);
+        (void)hipFree(sl.d_out);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (Channel& c : s->ch) {
+        (void)hipFree(c.ring_x);
+        (void)hipFree(c.ring_y);
+    }
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+// Move finished cycles' outputs into the channels' host rings (lock held).
+void harvest(ext_server* s) {
+    while (!s->inflight.empty()) {
+        Slot& sl = s->slots[s->inflight.front()];
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) return;
+        if (q != hipSuccess) {
+            s->sticky = EXT_EDEVICE;
+            return;
+        }
+        const uint64_t t = now_ns();
+        for (const Range& r : sl.ranges) {
+            Channel& c = s->ch[r.ch];
+            for (uint32_t k = 0; k < r.n; ++k) {
+                const uint64_t slot = (r.first_pair + k) % c.R;
+                memcpy(c.out_ring.data() + slot * c.qb, sl.h_out + r.out_off + k * c.qb, c.qb);
+                c.ready_ns[slot] = t;
+            }
+            c.completed += r.n;
+        }
+        s->stats.gpu_busy_ns += t - sl.launched_ns;
+        sl.ranges.clear();
+        sl.data_used = 0;
+        sl.n_descs = 0;
+        s->inflight.pop_front();
+    }
+}
+
+int occupancy(ext_server* s, uint32_t bw, uint32_t lds) {
+    auto key = std::make_pair(bw, lds);
+    auto it = s->occ_cache.find(key);
+    if (it != s->occ_cache.end()) return it->second;
+    int occ = 0;
+    if (qext::batch_occupancy(bw, lds, &occ) != hipSuccess || occ <= 0) occ = 1;
+    s->occ_cache[key] = occ;
+    return occ;
+}
+
+// Take the filling slot, add every ready block pair, and queue the cycle
+// (lock held on entry and exit; released around the HIP calls).
+int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
+    const int idx = s->filling;
+    Slot& sl = s->slots[idx];
+    // the next filling slot: one that is neither in flight nor this one
+    int next = -1;
+    for (int k = 0; k < 3; ++k) {
+        if (k == idx) continue;
+        if (std::find(s->inflight.begin(), s->inflight.end(), k) == s->inflight.end()) next = k;
+    }
+    if (next < 0) return EXT_OK;
+    // new submissions go to `next` from here on; wait for copies into this one
+    s->filling = next;
+    while (sl.pending > 0) s->cv.wait(lk);
+    for (const Resv& r : sl.resv) {
+        Channel& c = s->ch[r.ch];
+        uint64_t& ok = r.side ? c.y_ok : c.x_ok;
+        ok = std::max(ok, r.end);
+    }
+    sl.resv.clear();
+
+    // tiles of every channel's ready pairs, grouped by base size
+    std::map<uint32_t, std::vector<BatchTile>> by_bw;
+    std::map<uint32_t, uint32_t> lds_of;
+    uint64_t out_off = 0;
+    uint32_t n_tiles = 0;
+    sl.ranges.clear();
+    for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
+        Channel& c = s->ch[ci];
+        if (!c.open) continue;
+        uint64_t ready = std::min(c.x_ok, c.y_ok) / c.nb - c.launched;
+        while (ready) {
+            const uint64_t slot0 = c.launched % c.R;
+            uint64_t k = std::min<uint64_t>(ready, c.R - slot0);            // no ring wrap
+            k = std::min<uint64_t>(k, (s->cfg.outbox_bytes - out_off) / c.qb);  // outbox room
+            const uint64_t tiles_needed = (k + c.shape.ppw - 1) / c.shape.ppw;
+            if (n_tiles + tiles_needed > s->cfg.max_tiles)
+                k = std::min<uint64_t>(k, (uint64_t)(s->cfg.max_tiles - n_tiles) * c.shape.ppw);
+            if (k == 0) break;
+            sl.ranges.push_back(Range{ci, (uint32_t)k, c.launched, out_off});
+            auto& vec = by_bw[c.shape.bw];
+            lds_of[c.shape.bw] = std::max(lds_of[c.shape.bw], c.shape.lds_words * 4);
+            for (uint64_t p = 0; p < k; p += c.shape.ppw) {
+                const uint32_t n = (uint32_t)std::min<uint64_t>(c.shape.ppw, k - p);
+                vec.push_back(BatchTile{ci, n, slot0 + p, (out_off + p * c.qb) / 4});
+                ++n_tiles;
+            }
+            out_off += k * c.qb;
+            c.launched += k;
+            ready -= k;
+        }
+    }
+    if (sl.data_used == 0 && n_tiles == 0) return EXT_OK;  // (the slot stays free)
+
+    // metadata into the slot's pinned area
+    BatchStream* hs = reinterpret_cast<BatchStream*>(sl.h_in + s->off_streams);
+    for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
+        const Channel& c = s->ch[ci];
+        hs[ci] = BatchStream{(const uint32_t*)c.ring_x, (const uint32_t*)c.ring_y,
+                             (uint32_t*)sl.d_out, 0, c.shape};
+    }
+    BatchTile* ht = reinterpret_cast<BatchTile*>(sl.h_in + s->off_tiles);
+    sl.groups.clear();
+    uint32_t t_off = 0;
+    for (auto& kv : by_bw) {
+        Group g{kv.first, t_off, (uint32_t)kv.second.size(), lds_of[kv.first], 0};
+        memcpy(ht + t_off, kv.second.data(), kv.second.size() * sizeof(BatchTile));
+        g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles,
+                                              (uint64_t)s->cus * occupancy(s, g.bw, g.lds_bytes));
+        t_off += g.n_tiles;
+        sl.groups.push_back(g);
+    }
+    sl.n_tiles = n_tiles;
+    sl.out_bytes = out_off;
+    s->inflight.push_back(idx);
+    s->stats.cycles += 1;
+    s->stats.tiles += n_tiles;
+    for (const Range& r : sl.ranges) s->stats.pairs += r.n;
+
+    // queue the cycle without holding the lock (submit() now fills `next`)
+    lk.unlock();
+    hipError_t e = hipSuccess;
+    const size_t meta_bytes =
+        s->off_tiles + (size_t)n_tiles * sizeof(BatchTile) - s->off_desc;
+    sl.launched_ns = now_ns();
+    if (sl.data_used)
+        e = hipMemcpyAsync(sl.d_in, sl.h_in, sl.data_used, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.d_in + s->off_desc, sl.h_in + s->off_desc, meta_bytes,
+                           hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = qext::launch_scatter(sl.d_in, reinterpret_cast<const ScatterDesc*>(sl.d_in + s->off_desc),
+                                 sl.n_descs, s->stream);
+    for (size_t gi = 0; gi < sl.groups.size() && e == hipSuccess; ++gi) {
+        const Group& g = sl.groups[gi];
+        e = qext::launch_batch(g.bw, reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
+                               reinterpret_cast<const BatchTile*>(sl.d_in + s->off_tiles) + g.tile_off,
+                               g.n_tiles, reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi,
+                               g.grid, g.lds_bytes, s->stream);
+    }
+    if (e == hipSuccess && sl.out_bytes)
+        e = hipMemcpyAsync(sl.h_out, sl.d_out, sl.out_bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, s->stream);
+    lk.lock();
+    if (e != hipSuccess) {
+        s->sticky = EXT_EDEVICE;
+        return EXT_EDEVICE;
+    }
+    return EXT_OK;
+}
+
+bool has_work(ext_server* s) {
+    if (s->slots[s->filling].data_used) return true;
+    for (const Channel& c : s->ch)
+        if (c.open && std::min(c.x_ok, c.y_ok) / c.nb > c.launched) return true;
+    return false;
+}
+
+void scheduler(ext_server* s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (s->stop && s->inflight.empty()) break;
+        harvest(s);
+        if (s->sticky) {
+            s->cv.notify_all();
+            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+            if (s->stop) break;
+            continue;
+        }
+        if (!s->stop && s->inflight.size() < 2 && has_work(s)) {
+            launch_cycle(s, lk);
+            s->cv.notify_all();
+            continue;
+        }
+        if (!s->inflight.empty()) {
+            // a cycle is on the GPU: look again shortly (or when data arrive)
+            s->cv.wait_for(lk, std::chrono::microseconds(s->cfg.poll_us));
+        } else {
+            s->cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void ext_server_config_init(ext_server_config* c) {
+    if (!c) return;
+    memset(c, 0, sizeof *c);
+    c->max_channels = 256;
+    c->ring_blocks = 512;
+    c->stage_bytes = 64ull << 20;
+    c->outbox_bytes = 32ull << 20;
+    c->max_tiles = 1u << 17;
+    c->max_descs = 1u << 16;
+    c->poll_us = 20;
+}
+
+int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_server** out) {
+    if (!out) return EXT_EINVAL;
+    *out = nullptr;
+    ext_server_config dc;
+    ext_server_config_init(&dc);
+    if (!cfg) cfg = &dc;
+    ext_params dp;
+    ext_params_init(&dp);
+    if (!p) p = &dp;
+    if (p->n_taps || cfg->max_channels == 0 || cfg->ring_blocks == 0 || cfg->stage_bytes == 0 ||
+        cfg->outbox_bytes < 4 || cfg->max_tiles == 0 || cfg->max_descs < 4)
+        return EXT_EINVAL;
+    ext_server* s = new (std::nothrow) ext_server;
+    if (!s) return EXT_ENOMEM;
+    s->cfg = *cfg;
+    if (!s->cfg.poll_us) s->cfg.poll_us = 20;
+    s->params = *p;
+    int dev = p->device;
+    if ((dev < 0 && hipGetDevice(&dev) != hipSuccess) || hipSetDevice(dev) != hipSuccess) {
+        delete s;
+        return EXT_EDEVICE;
+    }
+    s->device = dev;
+    if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        s->cus = 1;
+    if (p->use_hip_stream && p->hip_stream) {
+        s->stream = (hipStream_t)p->hip_stream;
+    } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
+        s->own_stream = true;
+    } else {
+        delete s;
+        return EXT_EDEVICE;
+    }
+    s->off_desc = align_up(cfg->stage_bytes, 256);
+    s->off_streams = align_up(s->off_desc + (size_t)cfg->max_descs * sizeof(ScatterDesc), 256);
+    s->off_tiles = align_up(s->off_streams + (size_t)cfg->max_channels * sizeof(BatchStream), 256);
+    s->off_heads = align_up(s->off_tiles + (size_t)cfg->max_tiles * sizeof(BatchTile), 256);
+    s->in_bytes = s->off_heads + 64 * sizeof(uint32_t);
+    bool ok = true;
+    for (Slot& sl : s->slots) {
+        ok = ok && hipHostMalloc((void**)&sl.h_in, s->in_bytes, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&sl.h_out, cfg->outbox_bytes, hipHostMallocDefault) ==
+                       hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.d_in, s->in_bytes) == hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.d_out, cfg->outbox_bytes) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+    }
+    try {
+        s->ch.resize(cfg->max_channels);
+    } catch (const std::bad_alloc&) {
+        ok = false;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        server_free(s);
+        return EXT_ENOMEM;
+    }
+    try {
+        s->sched = std::thread(scheduler, s);
+    } catch (...) {
+        server_free(s);
+        return EXT_ENOMEM;
+    }
+    *out = s;
+    return EXT_OK;
+}
+
+int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* channel) {
+    if (!s || !channel || n_bits == 0 || m_bits == 0 || n_bits % m_bits ||
+        n_bits / m_bits > 0xffffffffull)
+        return EXT_EINVAL;
+    std::vector<uint32_t> taps;
+    try {
+        if (!qext::default_modulus(m_bits, &taps)) return EXT_ENOTSUP;
+    } catch (const std::bad_alloc&) {
+        return EXT_ENOMEM;
+    }
+    const uint32_t n_e = (uint32_t)(n_bits / m_bits);
+    qext::PlanKnobs knobs{s->params.base_bits / 32, s->params.groups, s->params.pairs_per_group};
+    if (s->params.autotune &&
+        qext::autotune_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), s->stream, &knobs,
+                             nullptr) != hipSuccess)
+        return EXT_EDEVICE;
+    ExtShape shape;
+    if (!qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), knobs, &shape))
+        return EXT_ENOTSUP;
+    const uint64_t nb = n_bits / 8, qb = m_bits / 8;
+    if (qb > s->cfg.outbox_bytes) return EXT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->sticky) return s->sticky;
+    uint32_t ci = 0;
+    while (ci < s->ch.size() && (s->ch[ci].open || s->ch[ci].ring_x)) ++ci;
+    if (ci == s->ch.size()) return EXT_EAGAIN;
+    Channel& c = s->ch[ci];
+    c = Channel{};
+    c.n_bits = n_bits;
+    c.m_bits = m_bits;
+    c.nb = nb;
+    c.qb = qb;
+    c.shape = shape;
+    c.R = s->cfg.ring_blocks;
+    if (c.R * nb > s->cfg.stage_bytes) c.R = std::max<uint64_t>(1, s->cfg.stage_bytes / nb);
+    try {
+        c.out_ring.resize(c.R * qb);
+        c.ready_ns.resize(c.R);
+    } catch (const std::bad_alloc&) {
+        return EXT_ENOMEM;
+    }
+    if (hipMalloc((void**)&c.ring_x, c.R * nb) != hipSuccess ||
+        hipMalloc((void**)&c.ring_y, c.R * nb) != hipSuccess) {
+        (void)hipFree(c.ring_x);
+        (void)hipFree(c.ring_y);
+        c.ring_x = c.ring_y = nullptr;
+        (void)hipGetLastError();
+        return EXT_ENOMEM;
+    }
+    c.open = true;
+    *channel = ci;
+    return EXT_OK;
+}
+
+int ext_server_submit(ext_server* s, uint32_t channel, const void* x, size_t x_len, const void* y,
+                      size_t y_len) {
+    if (!s || (x_len && !x) || (y_len && !y)) return EXT_EINVAL;
+    if (x_len > 0xffffffffull || y_len > 0xffffffffull) return EXT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->sticky) return s->sticky;
+    if (channel >= s->ch.size() || !s->ch[channel].open) return EXT_ECLOSED;
+    Channel& c = s->ch[channel];
+    const uint64_t limit = (c.polled + c.R) * c.nb;
+    if (c.x_recv + x_len > limit || c.y_recv + y_len > limit) {
+        s->stats.eagain_ring += 1;
+        return EXT_EAGAIN;
+    }
+    Slot& sl = s->slots[s->filling];
+    // each side needs at most two descriptors (ring wrap)
+    if (sl.data_used + x_len + y_len > s->cfg.stage_bytes || sl.n_descs + 4 > s->cfg.max_descs) {
+        s->stats.eagain_stage += 1;
+        s->cv.notify_all();
+        return EXT_EAGAIN;
+    }
+    // reserve staging space and descriptors, then copy without the lock
+    const uint64_t ring_bytes = c.R * c.nb;
+    ScatterDesc* descs = reinterpret_cast<ScatterDesc*>(sl.h_in + s->off_desc);
+    uint8_t* dst_x = sl.h_in + sl.data_used;
+    auto reserve = [&](size_t len, uint64_t pos, uint8_t* ring) {
+        uint64_t done = 0;
+        while (done < len) {
+            const uint64_t off = (pos + done) % ring_bytes;
+            const uint64_t k = std::min<uint64_t>(len - done, ring_bytes - off);
+            descs[sl.n_descs++] = ScatterDesc{sl.data_used + done, ring + off, (uint32_t)k, channel};
+            done += k;
+        }
+        sl.data_used += len;
+    };
+    if (x_len) {
+        reserve(x_len, c.x_recv, c.ring_x);
+        c.x_recv += x_len;
+        sl.resv.push_back(Resv{channel, 0, c.x_recv});
+    }
+    uint8_t* dst_y = sl.h_in + sl.data_used;
+    if (y_len) {
+        reserve(y_len, c.y_recv, c.ring_y);
+        c.y_recv += y_len;
+        sl.resv.push_back(Resv{channel, 1, c.y_recv});
+    }
+    sl.pending += 1;
+    s->stats.bytes_in += x_len + y_len;
+    lk.unlock();
+    if (x_len) memcpy(dst_x, x, x_len);
+    if (y_len) memcpy(dst_y, y, y_len);
+    lk.lock();
+    sl.pending -= 1;
+    s->cv.notify_all();
+    return EXT_OK;
+}
+
+int ext_server_poll(ext_server* s, uint32_t channel, void* out, size_t out_cap, size_t* out_len,
+                    uint64_t* ready_ns, uint64_t* blocks_done) {
+    if (!s || (out_cap && !out)) return EXT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->sticky) return s->sticky;
+    if (channel >= s->ch.size() || !s->ch[channel].open) return EXT_ECLOSED;
+    Channel& c = s->ch[channel];
+    const uint64_t k = std::min<uint64_t>(c.completed - c.polled, out_cap / c.qb);
+    for (uint64_t i = 0; i < k; ++i) {
+        const uint64_t slot = (c.polled + i) % c.R;
+        memcpy((uint8_t*)out + i * c.qb, c.out_ring.data() + slot * c.qb, c.qb);
+        if (ready_ns) ready_ns[i] = c.ready_ns[slot];
+    }
+    c.polled += k;
+    if (out_len) *out_len = k * c.qb;
+    if (blocks_done) *blocks_done = c.polled;
+    if (k) s->cv.notify_all();
+    return EXT_OK;
+}
+
+int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
+    if (!s) return EXT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (channel >= s->ch.size() || !s->ch[channel].open) return EXT_ECLOSED;
+    Channel& c = s->ch[channel];
+    // let every launched pair of this channel finish before its rings go
+    while (c.completed < c.launched && !s->sticky) {
+        s->cv.notify_all();
+        s->cv.wait_for(lk, std::chrono::microseconds(200));
+    }
+    const uint64_t full = std::min(c.x_recv, c.y_recv) / c.nb;
+    if (dropped_bits) *dropped_bits = 8 * (std::max(c.x_recv, c.y_recv) - full * c.nb);
+    c.open = false;
+    // bytes of this channel still waiting in the filling cycle must not be
+    // scattered into rings that are about to be freed
+    {
+        Slot& sl = s->slots[s->filling];
+        while (sl.pending > 0) s->cv.wait(lk);
+        ScatterDesc* descs = reinterpret_cast<ScatterDesc*>(sl.h_in + s->off_desc);
+        for (uint32_t i = 0; i < sl.n_descs; ++i)
+            if (descs[i].pad == channel) descs[i].len = 0;
+        sl.resv.erase(std::remove_if(sl.resv.begin(), sl.resv.end(),
+                                     [&](const Resv& r) { return r.ch == channel; }),
+                      sl.resv.end());
+    }
+    // pairs received but not yet launched are dropped with the channel; wait
+    // for the stream before freeing the rings
+    lk.unlock();
+    (void)hipStreamSynchronize(s->stream);
+    lk.lock();
+    (void)hipFree(c.ring_x);
+    (void)hipFree(c.ring_y);
+    c.ring_x = c.ring_y = nullptr;
+    return EXT_OK;
+}
+
+int ext_server_stats_get(ext_server* s, ext_server_stats* out) {
+    if (!s || !out) return EXT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return s->sticky;
+}
+
+int ext_server_destroy(ext_server* s) {
+    if (!s) return EXT_OK;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->sched.joinable()) s->sched.join();
+    (void)hipStreamSynchronize(s->stream);
+    server_free(s);
+    return EXT_OK;
+}
+
+}  // extern "C"

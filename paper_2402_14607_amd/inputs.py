@@ -121,3 +121,19 @@ def batched(n_streams: int = 64, pairs_per_stream: int = 4096, seed: int = 3) ->
         n = int(n)
         w.streams.append(plain_workload(n, n // 4, pairs_per_stream, 1000 + 2 * s, 1001 + 2 * s))
     return w
+
+
+def served_channels(n_channels: int = 256, seed: int = 4):
+    """Channel shapes of the served workload: channel c with c % 4 == 3 is an
+    AR(1) forward-block-stress source (n = 65536, m = 16384); every other
+    channel is i.i.d. Gaussian with n drawn uniformly from BATCHED_N_CHOICES
+    (seed 4) and m = n/4.  Returns a list of (n_bits, m_bits, kind)."""
+    rng = _rng(seed)
+    ns = rng.choice(np.asarray(BATCHED_N_CHOICES), size=n_channels)
+    out = []
+    for c in range(n_channels):
+        if c % 4 == 3:
+            out.append((65536, 16384, "ar1"))
+        else:
+            out.append((int(ns[c]), int(ns[c]) // 4, "gaussian"))
+    return out

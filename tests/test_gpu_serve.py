@@ -1,0 +1,211 @@
+"""Served form on the GPU: continuous batching over many channels.
+
+Each channel's output from the server must equal the CPU oracle's and the
+plain form's on the same input (alone vs in the mix, bit-exact), however the
+chunks were cut and interleaved; admission answers EAGAIN and recovers; the
+load generator's captured outputs match the plain form channel by channel.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_14607_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    binding.load()
+    return d
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def plain(n, m, x, y):
+    pairs = (8 * min(x.size, y.size)) // n
+    out = np.zeros(max(1, pairs * m // 8), dtype=np.uint8)
+    with binding.Extractor(n, m, device_memory=False) as ex:
+        ex.extract(np.ascontiguousarray(x), np.ascontiguousarray(y), out, pairs)
+    return out[: pairs * m // 8]
+
+
+def drain(srv, chans, expect_bytes, timeout_s=30.0):
+    import time
+
+    got = {c: [] for c in chans}
+    have = {c: 0 for c in chans}
+    t_end = time.time() + timeout_s
+    while any(have[c] < expect_bytes[c] for c in chans):
+        assert time.time() < t_end, "server did not return every block"
+        for c in chans:
+            buf = np.empty(1 << 16, dtype=np.uint8)
+            n, _ = srv.poll(c, buf)
+            if n:
+                got[c].append(buf[:n].copy())
+                have[c] += n
+    return {c: np.concatenate(got[c]) if got[c] else np.zeros(0, np.uint8) for c in chans}
+
+
+SHAPES = [(1024, 256, "gaussian"), (8192, 2048, "gaussian"), (2048, 512, "gaussian"),
+          (65536, 16384, "ar1"), (480, 96, "gaussian"), (32768, 8192, "gaussian")]
+
+
+def test_server_interleaved_random_chunks(dev):
+    """X and Y of six channels cut independently into random byte lengths,
+    submissions of all channels interleaved at random, small rings so that
+    admission refuses and recovers: every channel's output equals the
+    oracle's."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    streams = []
+    for i, (n, m, kind) in enumerate(SHAPES):
+        pairs = 3 if n >= 32768 else 25
+        streams.append(inputs.plain_workload(n, m, pairs, 300 + 2 * i, 301 + 2 * i, kind=kind))
+    with binding.Server(config=binding.server_config(ring_blocks=6)) as srv:
+        chans = [srv.open(w.n_bits, w.m_bits) for w in streams]
+        outs = {c: [] for c in chans}
+        pos = [[0, 0] for _ in streams]
+        empty = np.zeros(0, np.uint8)
+        todo = list(range(len(streams)))
+        refused = 0
+        while todo:
+            i = int(rng.choice(todo))
+            w, c = streams[i], chans[i]
+            side = int(rng.integers(0, 2))
+            if pos[i][side] == (w.x.size if side == 0 else w.y.size):
+                side = 1 - side
+            arr = w.x if side == 0 else w.y
+            p = pos[i][side]
+            k = int(min(arr.size - p, rng.integers(1, 3 * w.n_bits // 8)))
+            chunk = arr[p:p + k]
+            rc = srv.submit(c, chunk if side == 0 else empty, chunk if side == 1 else empty)
+            if rc == binding.EXT_OK:
+                pos[i][side] += k
+            else:
+                refused += 1
+            buf = np.empty(1 << 16, dtype=np.uint8)
+            got, _ = srv.poll(c, buf)
+            if got:
+                outs[c].append(buf[:got].copy())
+            if pos[i][0] == w.x.size and pos[i][1] == w.y.size:
+                todo.remove(i)
+        want_bytes = {c: w.n_pairs * w.m_bits // 8 - sum(a.size for a in outs[c])
+                      for c, w in zip(chans, streams)}
+        rest = drain(srv, chans, want_bytes)
+        say("server stats: %s, refused %d" % (srv.stats(), refused))
+        assert refused > 0
+        for c, w in zip(chans, streams):
+            got = np.concatenate(outs[c] + [rest[c]])
+            assert np.array_equal(got, oracle.ext_blocks(w.x, w.y, w.n_bits, w.m_bits)), \
+                (w.n_bits, w.m_bits)
+
+
+def test_server_outputs_equal_plain_form_any_chunking(dev):
+    rng = np.random.Generator(np.random.PCG64(22))
+    streams = [inputs.plain_workload(n, m, 40 if n < 32768 else 4, 400 + i, 500 + i, kind=kind)
+               for i, (n, m, kind) in enumerate(SHAPES)]
+    with binding.Server() as srv:
+        chans = [srv.open(w.n_bits, w.m_bits) for w in streams]
+        for c, w in zip(chans, streams):
+            px = py = 0
+            while px < w.x.size or py < w.y.size:
+                kx = int(min(w.x.size - px, rng.integers(0, 5 * w.n_bits // 8)))
+                ky = int(min(w.y.size - py, rng.integers(0, 5 * w.n_bits // 8)))
+                assert srv.submit(c, w.x[px:px + kx], w.y[py:py + ky]) == binding.EXT_OK
+                px += kx
+                py += ky
+        outs = drain(srv, chans, {c: w.n_pairs * w.m_bits // 8 for c, w in zip(chans, streams)})
+        for c, w in zip(chans, streams):
+            assert np.array_equal(outs[c], plain(w.n_bits, w.m_bits, w.x, w.y)), w.n_bits
+        st = srv.stats()
+        assert st["pairs"] == sum(w.n_pairs for w in streams)
+
+
+def test_server_admission_and_close(dev):
+    n, m = 8192, 2048
+    nb = n // 8
+    w = inputs.plain_workload(n, m, 20, 61, 62)
+    tail = np.arange(100, dtype=np.uint8)
+    with binding.Server(config=binding.server_config(ring_blocks=4)) as srv:
+        c = srv.open(n, m)
+        empty = np.zeros(0, np.uint8)
+        # X alone runs ahead until the 4-block ring is full
+        sent = 0
+        while srv.submit(c, w.x[sent * nb:(sent + 1) * nb], empty) == binding.EXT_OK:
+            sent += 1
+        assert sent == 4
+        # Y catches up; outputs come back; ring space returns after polling
+        got = []
+        py = 0
+        px = sent
+        while py < 20:
+            if srv.submit(c, empty, w.y[py * nb:(py + 1) * nb]) == binding.EXT_OK:
+                py += 1
+            if px < 20 and srv.submit(c, w.x[px * nb:(px + 1) * nb], empty) == binding.EXT_OK:
+                px += 1
+            buf = np.empty(1 << 16, dtype=np.uint8)
+            k, _ = srv.poll(c, buf)
+            if k:
+                got.append(buf[:k].copy())
+        rest = drain(srv, [c], {c: 20 * 256 - sum(g.size for g in got)})
+        out = np.concatenate(got + [rest[c]])
+        assert np.array_equal(out, oracle.ext_blocks(w.x, w.y, n, m))
+        assert srv.submit(c, tail, empty) == binding.EXT_OK
+        assert srv.close_channel(c) == 8 * tail.size
+        with pytest.raises(binding.ExtError):
+            srv.submit(c, tail, tail)
+
+
+def test_load_generator_alone_vs_mix(dev):
+    """Poisson chunk arrivals on 12 channels of mixed shapes through the
+    server: every channel's captured output equals the plain form on the
+    bytes it was fed (pools large enough that they are read once)."""
+    specs = [(2048, 512), (4096, 1024), (8192, 2048), (16384, 4096), (32768, 8192),
+             (65536, 16384)] * 2
+    rate = 150e6  # raw bytes/s, X + Y, all channels
+    horizon = 1.3
+    chans = []
+    for i, (n, m) in enumerate(specs):
+        share = rate / len(specs) * horizon / 2 * 2.5  # bytes per side, generous
+        pairs = int(share // (n // 8)) + 64
+        kind = "ar1" if n == 65536 else "gaussian"
+        w = inputs.plain_workload(n, m, pairs, 700 + i, 800 + i, kind=kind)
+        chans.append((n, m, w.x, w.y))
+    say("load generator: %d channels, %.0f MB/s" % (len(chans), rate / 1e6))
+    res, cap = binding.simulate(chans, raw_bytes_per_s=rate, warmup_s=0.3, duration_s=1.0,
+                                grace_s=3.0, seed=9, capture=True)
+    say("result: %s" % res)
+    assert res["blocks_missing"] == 0
+    assert not res["admission_gave_up"]
+    for (n, m, x, y), c in zip(chans, cap):
+        blocks = c.size // (m // 8)
+        assert blocks > 0
+        nb = n // 8
+        assert np.array_equal(c, plain(n, m, x[:blocks * nb], y[:blocks * nb])), (n, m)
+
+
+def test_load_generator_plain_mode_runs(dev):
+    specs = [(2048, 512), (8192, 2048), (65536, 16384)]
+    rate = 30e6
+    chans = []
+    for i, (n, m) in enumerate(specs):
+        share = rate / len(specs) * 0.7 / 2 * 2.5  # bytes per side, generous
+        w = inputs.plain_workload(n, m, int(share // (n // 8)) + 64, 900 + i, 950 + i)
+        chans.append((n, m, w.x, w.y))
+    res, cap = binding.simulate(chans, mode=binding.EXT_SIM_PLAIN, raw_bytes_per_s=rate,
+                                warmup_s=0.2, duration_s=0.5, grace_s=2.0, seed=3, capture=True)
+    say("plain mode: %s" % res)
+    assert res["blocks_measured"] > 0
+    for (n, m, x, y), c in zip(chans, cap):
+        blocks = c.size // (m // 8)
+        nb = n // 8
+        assert np.array_equal(c, plain(n, m, x[:blocks * nb], y[:blocks * nb]))
