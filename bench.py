@@ -154,7 +154,8 @@ def batched_leg(dev, stream, steps: int, warmup: int):
     return res
 
 
-def served_leg(w, duration_s: float, warmup_s: float):
+def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
+                                                             "plain_at_1/16_load")):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
     1..64 blocks, 64 Gbps aggregate raw input; three quarters i.i.d. Gaussian
     with n from 2048..32768, one quarter AR(1) with n = 65536.  Served form
@@ -183,10 +184,14 @@ def served_leg(w, duration_s: float, warmup_s: float):
                        "input; 192 iid Gaussian (n in 2048..32768, m=n/4), 64 AR(1) "
                        "(n=65536, m=16384)",
            "window_s": duration_s}
-    for name, mode, lag in (("served", binding.EXT_SIM_SERVED, 0.0),
-                            ("plain", binding.EXT_SIM_PLAIN, 1.0)):
-        log("served leg: %s form, %.0f s window" % (name, duration_s))
-        res, _ = binding.simulate(chans, mode=mode, raw_bytes_per_s=rate, warmup_s=warmup_s,
+    runs = (("served", binding.EXT_SIM_SERVED, rate, 0.0),
+            ("plain", binding.EXT_SIM_PLAIN, rate, 0.5),
+            ("plain_at_1/16_load", binding.EXT_SIM_PLAIN, rate / 16, 0.5))
+    for name, mode, r, lag in runs:
+        if name not in modes:
+            continue
+        log("served leg: %s, %.1f Gbps raw, %.0f s window" % (name, r * 8 / 1e9, duration_s))
+        res, _ = binding.simulate(chans, mode=mode, raw_bytes_per_s=r, warmup_s=warmup_s,
                                   duration_s=duration_s, grace_s=2.0, max_lag_s=lag, seed=4)
         log("served leg: %s: %s" % (name, json.dumps(res)))
         out[name] = {
@@ -200,7 +205,11 @@ def served_leg(w, duration_s: float, warmup_s: float):
             "blocks_missing": int(res["blocks_missing"]),
             "eagain": int(res["eagain"]),
             "max_submit_lag_ms": round(res["max_submit_lag_us"] / 1e3, 3),
+            "chunks_submitted": int(res["chunks"]),
             "cycles": int(res["cycles"]),
+            "mean_cycle_ms": round(res["mean_cycle_us"] / 1e3, 4),
+            "eagain_ring": int(res["eagain_ring"]),
+            "eagain_stage": int(res["eagain_stage"]),
         }
     return out
 
@@ -214,6 +223,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-modes", default="served,plain,plain_at_1/16_load",
+                    help="comma-separated subset of the served-leg runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, also run a plain 64 MiB device copy 4 times (the "
                          "reference kernel that scales HBM traffic counters)")
@@ -295,7 +306,8 @@ def main():
 
     served = None
     if not args.no_served:
-        served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0)
+        served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
+                            modes=args.serve_modes.split(","))
 
     sec = ms * 1e-3
     out_gbps = N_PAIRS * M_BITS / sec / 1e9

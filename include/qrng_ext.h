@@ -86,7 +86,9 @@ typedef struct {
     uint32_t pairs_per_group;   /* block pairs per work-group */
     uint32_t autotune;          /* 1: time the candidate plans on the device at create
                                    time and keep the fastest (cached per shape) */
-    uint32_t reserved[4];
+    uint32_t threads;           /* work-group size, 0 = 256; 1024 shortens the critical
+                                   path of shapes with more than 256 items per pair */
+    uint32_t reserved[3];
 } ext_params;
 
 /* Fill *p with defaults (b = 8, conventional modulus, host memory, a stream
@@ -222,23 +224,26 @@ int ext_batch_destroy(ext_batch *b);
  * scheduler thread inside the server repeatedly takes everything that
  * arrived, moves it to the channels' device rings and computes every block
  * pair completed so far on every channel in one persistent launch per base
- * size, while the previous cycle is still on the GPU (at most two cycles in
- * flight).  Outputs come back per channel, in block order, exactly once.
- * Admission: a channel holds at most ring_blocks blocks between received and
- * polled, and a cycle takes at most stage_bytes of input and returns at most
+ * size, while earlier cycles are still on the GPU (at most three in flight).  Outputs come back per channel, in block order, exactly once.
+ * Admission: a channel holds at most its ring's worth of blocks between
+ * received and polled, and a cycle takes at most stage_bytes of input and returns at most
  * outbox_bytes of output; beyond that ext_server_submit returns EXT_EAGAIN
  * and consumes nothing.  All calls are thread-safe.
  */
 typedef struct ext_server ext_server;
 typedef struct {
     uint32_t max_channels;  /* channel slots (default 256) */
-    uint32_t ring_blocks;   /* device ring per channel side, in blocks (default 512) */
+    uint32_t ring_blocks;   /* device ring per channel side, in blocks; 0 = sized by
+                               ring_bytes (default 0) */
     uint64_t stage_bytes;   /* input bytes one cycle can take (default 64 MiB) */
     uint64_t outbox_bytes;  /* output bytes one cycle can return (default 32 MiB) */
     uint32_t max_tiles;     /* work-group tiles per cycle (default 131072) */
     uint32_t max_descs;     /* copy ranges per cycle (default 65536) */
     uint32_t poll_us;       /* scheduler re-check period while a cycle runs (default 20) */
-    uint32_t reserved[5];
+    uint32_t reserved0;
+    uint64_t ring_bytes;    /* when ring_blocks == 0: ring per channel side in bytes, rounded
+                               down to whole blocks, at least 128 blocks (default 4 MiB) */
+    uint32_t reserved[2];
 } ext_server_config;
 typedef struct {
     uint64_t cycles, tiles, pairs, bytes_in;
@@ -262,6 +267,10 @@ int ext_server_submit(ext_server *s, uint32_t channel, const void *x, size_t x_l
  * server saw it finish; *blocks_done the blocks returned so far. */
 int ext_server_poll(ext_server *s, uint32_t channel, void *out, size_t out_cap, size_t *out_len,
                     uint64_t *ready_ns, uint64_t *blocks_done);
+/* Wait up to timeout_us for channels with output not yet polled; writes up
+ * to cap channel indices to chans and their count to *n (0 on timeout). */
+int ext_server_ready(ext_server *s, uint32_t *chans, uint32_t cap, uint32_t *n,
+                     uint32_t timeout_us);
 /* Close a channel after its launched pairs finish; the trailing partial
  * block and any unpolled output are dropped (*dropped_bits: input bits not
  * part of a complete pair, larger side). */
@@ -294,6 +303,8 @@ typedef struct {
     double max_lag_s;               /* stop submitting once this far behind schedule (0 = never);
                                        the chunks left count as missing */
     uint64_t seed;
+    uint32_t producer_threads;      /* submitting threads (channels split among them); 0 = 4 */
+    uint32_t reserved0;
     uint8_t *const *capture;        /* optional per channel: every output byte, in order */
     const uint64_t *capture_cap;    /* per channel capacity of capture */
     const ext_server_config *server_cfg;  /* served mode; NULL = defaults */
@@ -309,7 +320,10 @@ typedef struct {
     uint64_t chunks, eagain;
     double max_submit_lag_us;       /* worst lateness of a submission behind its schedule */
     uint64_t cycles;                /* served mode: scheduler cycles */
-    uint64_t reserved[6];
+    uint64_t eagain_ring;           /* served mode: refusals because a channel ring was full */
+    uint64_t eagain_stage;          /* served mode: refusals because a cycle was full */
+    double mean_cycle_us;           /* served mode: mean launch-to-harvest time of a cycle */
+    uint64_t reserved[3];
 } ext_sim_result;
 /* capture_len (may be NULL): per channel, bytes written to capture. */
 int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t *capture_len);

@@ -33,7 +33,7 @@ EXPORTED = (
     "ext_batch_create", "ext_batch_run", "ext_batch_sync", "ext_batch_describe",
     "ext_batch_destroy", "ext_server_config_init", "ext_server_create", "ext_server_open",
     "ext_server_submit", "ext_server_poll", "ext_server_close", "ext_server_stats_get",
-    "ext_server_destroy", "ext_serve_simulate",
+    "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
 )
 
 EXT_SIM_SERVED = 0
@@ -60,7 +60,8 @@ class ExtParams(ctypes.Structure):
         ("groups", ctypes.c_uint32),
         ("pairs_per_group", ctypes.c_uint32),
         ("autotune", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("threads", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -85,7 +86,9 @@ class ServerConfig(ctypes.Structure):
         ("max_tiles", ctypes.c_uint32),
         ("max_descs", ctypes.c_uint32),
         ("poll_us", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("reserved0", ctypes.c_uint32),
+        ("ring_bytes", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 
@@ -112,6 +115,8 @@ class SimConfig(ctypes.Structure):
         ("grace_s", ctypes.c_double),
         ("max_lag_s", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("producer_threads", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
         ("capture", ctypes.POINTER(ctypes.c_void_p)),
         ("capture_cap", ctypes.POINTER(ctypes.c_uint64)),
         ("server_cfg", ctypes.POINTER(ServerConfig)),
@@ -126,7 +131,8 @@ class SimResult(ctypes.Structure):
                [(n, ctypes.c_uint64) for n in ("blocks_measured", "blocks_missing", "chunks",
                                                "eagain")] + \
                [("max_submit_lag_us", ctypes.c_double), ("cycles", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 6)]
+                ("eagain_ring", ctypes.c_uint64), ("eagain_stage", ctypes.c_uint64),
+                ("mean_cycle_us", ctypes.c_double), ("reserved", ctypes.c_uint64 * 3)]
 
 
 _lib = None
@@ -174,6 +180,7 @@ def load() -> ctypes.CDLL:
         "ext_server_submit": (ctypes.c_int, [vp, u32, vp, sz, vp, sz]),
         "ext_server_poll": (ctypes.c_int, [vp, u32, vp, sz, szp, u64p, u64p]),
         "ext_server_close": (ctypes.c_int, [vp, u32, u64p]),
+        "ext_server_ready": (ctypes.c_int, [vp, ctypes.POINTER(u32), u32, ctypes.POINTER(u32), u32]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
         "ext_server_destroy": (ctypes.c_int, [vp]),
         "ext_serve_simulate": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult),
@@ -225,7 +232,7 @@ def _ptr(buf) -> int:
 
 def make_params(lib, *, device_memory=True, stream=None, taps=None, sample_bits=8,
                 device_bytes_cap=0, device=-1, autotune=False, base_bits=0, groups=0,
-                pairs_per_group=0) -> ExtParams:
+                pairs_per_group=0, threads=0) -> ExtParams:
     p = ExtParams()
     lib.ext_params_init(ctypes.byref(p))
     p.sample_bits = sample_bits
@@ -244,6 +251,7 @@ def make_params(lib, *, device_memory=True, stream=None, taps=None, sample_bits=
     p.base_bits = base_bits
     p.groups = groups
     p.pairs_per_group = pairs_per_group
+    p.threads = threads
     return p
 
 
@@ -253,12 +261,12 @@ class Extractor:
     def __init__(self, n_bits: int, m_bits: int, *, device_memory: bool = True, stream=None,
                  taps=None, sample_bits: int = 8, device_bytes_cap: int = 0, device: int = -1,
                  autotune: bool = False, base_bits: int = 0, groups: int = 0,
-                 pairs_per_group: int = 0):
+                 pairs_per_group: int = 0, threads: int = 0):
         self.lib = load()
         p = make_params(self.lib, device_memory=device_memory, stream=stream, taps=taps,
                         sample_bits=sample_bits, device_bytes_cap=device_bytes_cap,
                         device=device, autotune=autotune, base_bits=base_bits, groups=groups,
-                        pairs_per_group=pairs_per_group)
+                        pairs_per_group=pairs_per_group, threads=threads)
         self.n_bits = n_bits
         self.m_bits = m_bits
         self.device_memory = device_memory
@@ -471,6 +479,7 @@ class Server:
 
 def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max_chunk=64,
              warmup_s=1.0, duration_s=5.0, grace_s=2.0, max_lag_s=0.0, seed=4, capture=False,
+             producer_threads=4,
              config: ServerConfig | None = None, autotune=False):
     """Run the load generator.  channels: list of (n_bits, m_bits, pool_x, pool_y)
     with uint8 numpy pools.  Returns (result dict, list of captured outputs or None)."""
@@ -499,6 +508,7 @@ def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max
     cfg.grace_s = grace_s
     cfg.max_lag_s = max_lag_s
     cfg.seed = seed
+    cfg.producer_threads = producer_threads
     caps = None
     if capture:
         bufs = []

@@ -53,6 +53,8 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     }
     if (2 * max_tap > q) return false;  // two folding passes suffice only below q/2
     if (knobs.groups && n_e % knobs.groups) return false;
+    const uint32_t threads = knobs.threads ? knobs.threads : (uint32_t)kThreads;
+    if (threads % 64 || threads > (uint32_t)kMaxThreads) return false;
 
     ExtShape r{};
     r.q = q;
@@ -74,7 +76,7 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
         for (uint32_t g = 1; g <= n_e; ++g) {
             if (n_e % g || (knobs.groups && g != knobs.groups)) continue;
             const uint32_t per_pair = r.np * g;
-            uint32_t ppw = per_pair >= (uint32_t)kThreads ? 1u : (uint32_t)kThreads / per_pair;
+            uint32_t ppw = per_pair >= threads ? 1u : threads / per_pair;
             if (knobs.ppw) ppw = knobs.ppw;
             auto lds_words = [&](uint32_t pp) {
                 return pp * ((stage_try ? 2 * r.nw : 0) + 2 * qw + r.dn);
@@ -82,8 +84,8 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
             while (ppw > 1 && lds_words(ppw) * 4 > kMaxLdsBytes) --ppw;
             if (lds_words(ppw) * 4 > 65536) continue;
             const uint64_t items = (uint64_t)ppw * per_pair;
-            const uint64_t rounds = (items + kThreads - 1) / kThreads;
-            const double util = (double)items / (double)(rounds * kThreads);
+            const uint64_t rounds = (items + threads - 1) / threads;
+            const double util = (double)items / (double)(rounds * threads);
             if (util > best_util + 1e-9) {
                 best_util = util;
                 r.groups = g;
@@ -97,6 +99,7 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     }
     if (best_util < 0) return false;
     r.align = (!r.stage && bw % 4 == 0) ? 16u : 4u;
+    r.threads = threads;
     *s = r;
     return true;
 }
@@ -280,7 +283,7 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         return EXT_EINVAL;
     }
     ExtShape shape;
-    qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group};
+    qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group, p->threads};
     if (p->base_bits % 32) return EXT_EINVAL;
     if (!qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
                           (uint32_t)taps.size(), knobs, &shape))
@@ -356,7 +359,7 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
              "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
              "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d}",
              (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
-             s.groups, s.stage, s.lds_words * 4, qext::kThreads);
+             s.groups, s.stage, s.lds_words * 4, s.threads);
     return EXT_OK;
 }
 

@@ -41,7 +41,8 @@ std::map<TuneKey, std::pair<PlanKnobs, float>> g_tune_cache;
 
 // Time every candidate plan of (q, n_e, taps) on `stream` over synthetic
 // blocks and return the fastest.  Candidates: base sizes of 128, 256 and 512
-// bits, every element grouping, the planner's pairs per work-group.
+// bits, every element grouping, the planner's pairs per work-group, and
+// 1024-lane work-groups for shapes with more than 256 items per pair.
 hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                           hipStream_t stream, PlanKnobs* best, float* best_ms) {
     int dev = 0;
@@ -59,16 +60,20 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
         }
     }
     std::vector<std::pair<PlanKnobs, ExtShape>> cands;
+    for (uint32_t nt : {(uint32_t)kThreads, (uint32_t)kMaxThreads})
     for (uint32_t bwt : {4u, 8u, 16u})
         for (uint32_t g = 1; g <= n_e; ++g) {
             if (n_e % g) continue;
-            PlanKnobs k{bwt, g, 0};
+            PlanKnobs k{bwt, g, 0, nt};
             ExtShape s;
             if (!plan_shape(q, n_e, taps, n_taps, k, &s)) continue;
+            // wide groups only where one pair has more items than a narrow group has lanes
+            if (nt != (uint32_t)kThreads && (uint64_t)s.np * s.groups <= (uint64_t)kThreads) continue;
             bool dup = false;
             for (auto& c : cands)
-                dup |= c.second.bw == s.bw && c.second.groups == s.groups && c.second.ppw == s.ppw;
-            if (!dup) cands.push_back({PlanKnobs{s.bw, s.groups, s.ppw}, s});
+                dup |= c.second.bw == s.bw && c.second.groups == s.groups && c.second.ppw == s.ppw &&
+                       c.second.threads == s.threads;
+            if (!dup) cands.push_back({PlanKnobs{s.bw, s.groups, s.ppw, s.threads}, s});
         }
     if (cands.empty()) return hipErrorInvalidValue;
 
@@ -149,7 +154,7 @@ struct ext_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     struct Group {
-        uint32_t bw, tile_off, n_tiles, lds_bytes, grid;
+        uint32_t bw, threads, tile_off, n_tiles, lds_bytes, grid;
     };
     std::vector<Group> groups;
     std::vector<BatchStream> streams;  // host copy (device pointers inside)
@@ -180,7 +185,8 @@ void batch_free(ext_batch* b) {
 int enqueue(ext_batch* b) {
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto& g = b->groups[gi];
-        hipError_t e = qext::launch_batch(g.bw, b->d_streams, b->d_tiles + g.tile_off, g.n_tiles,
+        hipError_t e = qext::launch_batch(g.bw, g.threads, b->d_streams, b->d_tiles + g.tile_off,
+                                          g.n_tiles,
                                           b->d_heads + gi, g.grid, g.lds_bytes, b->stream);
         if (e != hipSuccess) return EXT_EDEVICE;
     }
@@ -224,7 +230,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
     int rc = EXT_OK;
     try {
         // plan every stream
-        std::map<uint32_t, std::vector<uint32_t>> by_bw;  // bw -> stream indices
+        // launches: one per (base size, work-group size) -> stream indices
+        std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_bw;
         for (uint32_t i = 0; i < n_items && rc == EXT_OK; ++i) {
             const ext_batch_item& it = items[i];
             if (it.n_bits == 0 || it.m_bits == 0 || it.n_bits % it.m_bits ||
@@ -238,7 +245,7 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 break;
             }
             const uint32_t n_e = (uint32_t)(it.n_bits / it.m_bits);
-            qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group};
+            qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group, p->threads};
             if (p->autotune) {
                 if (qext::autotune_shape(it.m_bits, n_e, taps.data(), (uint32_t)taps.size(),
                                          b->stream, &knobs, nullptr) != hipSuccess) {
@@ -259,7 +266,7 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
             BatchStream st{(const uint32_t*)it.x, (const uint32_t*)it.y, (uint32_t*)it.out,
                            it.n_pairs, s};
             b->streams.push_back(st);
-            by_bw[s.bw].push_back(i);
+            by_bw[{s.bw, s.threads}].push_back(i);
             b->total_pairs += it.n_pairs;
             b->total_bitmacs += (double)it.n_pairs * (double)it.n_bits * (double)it.m_bits;
         }
@@ -270,7 +277,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 rc = EXT_EDEVICE;
             for (auto& kv : by_bw) {
                 if (rc != EXT_OK) break;
-                ext_batch::Group g{kv.first, (uint32_t)b->tiles.size(), 0, 0, 0};
+                ext_batch::Group g{kv.first.first, kv.first.second, (uint32_t)b->tiles.size(), 0, 0,
+                                   0};
                 std::vector<std::pair<double, BatchTile>> tl;
                 for (uint32_t si : kv.second) {
                     const BatchStream& st = b->streams[si];
@@ -288,7 +296,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 for (auto& t : tl) b->tiles.push_back(t.second);
                 g.n_tiles = (uint32_t)tl.size();
                 int occ = 0;
-                if (qext::batch_occupancy(g.bw, g.lds_bytes, &occ) != hipSuccess || occ <= 0)
+                if (qext::batch_occupancy(g.bw, g.threads, g.lds_bytes, &occ) != hipSuccess ||
+                    occ <= 0)
                     occ = 1;
                 g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles, (uint64_t)cus * occ);
                 if (g.n_tiles) b->groups.push_back(g);
@@ -372,8 +381,9 @@ int ext_batch_describe(const ext_batch* b, char* buf, size_t cap) {
     for (size_t i = 0; i < b->groups.size() && n < cap; ++i) {
         const auto& g = b->groups[i];
         n += (size_t)snprintf(buf + n, cap - n,
-                              "%s{\"base_bits\": %u, \"tiles\": %u, \"grid\": %u, \"lds_bytes\": %u}",
-                              i ? ", " : "", g.bw * 32, g.n_tiles, g.grid, g.lds_bytes);
+                              "%s{\"base_bits\": %u, \"threads\": %u, \"tiles\": %u, \"grid\": %u, "
+                              "\"lds_bytes\": %u}",
+                              i ? ", " : "", g.bw * 32, g.threads, g.n_tiles, g.grid, g.lds_bytes);
     }
     if (n < cap) snprintf(buf + n, cap - n, "]}");
     return EXT_OK;

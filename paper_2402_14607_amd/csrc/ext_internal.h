@@ -6,7 +6,8 @@
 
 namespace qext {
 
-constexpr int kThreads = 256;           // work-group size of the extraction kernel
+constexpr int kThreads = 256;           // default work-group size of the extraction kernel
+constexpr int kMaxThreads = 1024;       // largest work-group size of the extraction kernels
 constexpr int kMaxBaseWords = 16;       // largest base-product size, 32-bit words
 constexpr uint32_t kMaxLdsBytes = 32768;
 
@@ -30,6 +31,7 @@ struct ExtShape {
     uint32_t lds_words;
     uint32_t align;    // required byte alignment of x and y (16 when operands are
                        // read from HBM with 16-byte loads, else 4)
+    uint32_t threads;  // work-group size (a multiple of 64, at most kMaxThreads)
 };
 
 // Tuning choices for one shape; 0 in a field means "planner's choice".
@@ -37,6 +39,7 @@ struct PlanKnobs {
     uint32_t base_words;  // base-product size in 32-bit words (1..16)
     uint32_t groups;      // element groups per work item (divides n_e)
     uint32_t ppw;         // block pairs per work-group
+    uint32_t threads;     // work-group size (256 or 1024)
 };
 
 // Fills *s for q, n_e and the taps; returns false if the shape is outside
@@ -69,11 +72,12 @@ hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* 
                           uint32_t* out, uint64_t n_pairs, hipStream_t stream);
 
 // Queue the queue-head reset and one persistent launch of `grid` work-groups
-// over n_tiles tiles (all streams of the launch share base size bw).
+// of `threads` lanes over n_tiles tiles (all streams of the launch share base
+// size bw and work-group size).
 // streams, tiles, head: device memory.
-hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile* tiles,
-                        uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
-                        hipStream_t stream);
+hipError_t launch_batch(uint32_t bw, uint32_t threads, const BatchStream* streams,
+                        const BatchTile* tiles, uint32_t n_tiles, uint32_t* head, uint32_t grid,
+                        uint32_t lds_bytes, hipStream_t stream);
 
 // Autotuner: time the candidate plans of (q, n_e, taps) on `stream` and
 // return the fastest as knobs (cached per device and shape).
@@ -88,12 +92,20 @@ struct ScatterDesc {
     uint32_t pad;
 };
 
-// Queue the copy of every descriptor's range (src: device staging buffer,
-// descs: device array).
-hipError_t launch_scatter(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
-                          hipStream_t stream);
+// Queue a served cycle's staging kernel: copy every descriptor's range from
+// src (the host's pinned staging area, read over the bus) into its ring, copy
+// meta_bytes (a multiple of 16) from meta_src (pinned) to meta_dst (device),
+// and clear n_heads queue heads.
+hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
+                        const void* meta_src, void* meta_dst, uint32_t meta_bytes, uint32_t* heads,
+                        uint32_t n_heads, hipStream_t stream);
+
+// As launch_batch without the queue-head reset (the caller clears the head).
+hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
+                                const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
+                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream);
 
 // Resident work-groups per CU of the batched kernel at this LDS size.
-hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu);
 
 }  // namespace qext

@@ -120,15 +120,16 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
                                               uint32_t* __restrict__ out, uint32_t npw,
                                               uint32_t* lds) {
     const uint32_t tid = threadIdx.x;
+    const uint32_t nt = blockDim.x;  // sh.threads lanes
     const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
     uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
     uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
     uint32_t* cs = ys + (sh.stage ? sh.ppw * nw : 0); // [ppw][2qw]  unreduced sums
     uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
 
-    for (uint32_t i = tid; i < npw * cw; i += kThreads) cs[i] = 0;
+    for (uint32_t i = tid; i < npw * cw; i += nt) cs[i] = 0;
     if (sh.stage) {
-        for (uint32_t i = tid; i < npw * nw; i += kThreads) {
+        for (uint32_t i = tid; i < npw * nw; i += nt) {
             xs[i] = xg[i];
             ys[i] = yg[i];
         }
@@ -139,7 +140,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
     const uint32_t per_pair = sh.np * sh.groups;
     const uint32_t items = npw * per_pair;
     const uint32_t lmask = (1u << sh.levels) - 1u;
-    for (uint32_t it = tid; it < items; it += kThreads) {
+    for (uint32_t it = tid; it < items; it += nt) {
         const uint32_t j = it / per_pair;
         const uint32_t rem = it - j * per_pair;
         const uint32_t p = rem / sh.groups;
@@ -195,7 +196,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
     // First pass: C_hi (1 + sum t^e); its part of degree >= q is
     // D = sum_e (C_hi >> (q - e)), of degree <= max_e - 2 < q/2, folded once more.
     const uint32_t dn = sh.dn;
-    for (uint32_t i = tid; i < npw * dn; i += kThreads) {
+    for (uint32_t i = tid; i < npw * dn; i += nt) {
         const uint32_t j = i / dn, k = i - j * dn;
         const uint32_t* hi = cs + j * cw + qw;
         uint32_t d = 0;
@@ -211,7 +212,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
     }
     __syncthreads();
 
-    for (uint32_t i = tid; i < npw * qw; i += kThreads) {
+    for (uint32_t i = tid; i < npw * qw; i += nt) {
         const uint32_t j = i / qw, w = i - j * qw;
         const uint32_t* c = cs + j * cw;
         const uint32_t* hi = c + qw;
@@ -236,7 +237,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
 
 // Plain form: work-group g takes pairs [g*ppw, (g+1)*ppw) of one stream.
 template <int BW>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kMaxThreads)
 ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
               uint32_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
     extern __shared__ uint32_t lds[];
@@ -252,7 +253,7 @@ ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
 // shapes.  Each work-group takes the next tile with one atomic add on the
 // queue head and stops once the head passes n_tiles, so every wave exits.
 template <int BW>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kMaxThreads)
 ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __restrict__ tiles,
                  uint32_t n_tiles, uint32_t* __restrict__ head) {
     extern __shared__ uint32_t lds[];
@@ -264,23 +265,36 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         if (t >= n_tiles) break;
         const BatchTile tile = tiles[t];
         const BatchStream& st = streams[tile.stream];
-        const ExtShape sh = st.shape;
+        const ExtShape& sh = st.shape;  // read in place (a local copy would go to scratch)
         extract_group<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
                           st.out + tile.out_word0, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
 }
 
-// Copies each descriptor's byte range from the staging buffer to its
-// destination (one work-group per descriptor, 32-bit words when aligned).
+// Start of a served cycle, reading the host's pinned staging area directly:
+// every work-group copies its share of the descriptors' byte ranges into the
+// channels' rings (16-byte accesses when aligned), the grid copies the cycle's
+// metadata (stream table and tiles) into device memory, and work-group 0 clears
+// the queue heads.  No copy engine is involved, so the cycle's kernels follow
+// one another on one stream with no host-side dependency.
 __global__ void __launch_bounds__(kThreads)
-scatter_kernel(const uint8_t* __restrict__ src, const ScatterDesc* __restrict__ descs,
-               uint32_t n_descs) {
+stage_kernel(const uint8_t* __restrict__ src, const ScatterDesc* __restrict__ descs,
+             uint32_t n_descs, const uint4* __restrict__ meta_src, uint4* __restrict__ meta_dst,
+             uint32_t meta_vec, uint32_t* __restrict__ heads, uint32_t n_heads) {
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < n_heads; i += kThreads) heads[i] = 0u;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < meta_vec; i += gridDim.x * kThreads)
+        meta_dst[i] = meta_src[i];
     for (uint32_t d = blockIdx.x; d < n_descs; d += gridDim.x) {
         const ScatterDesc sd = descs[d];
         const uint8_t* s = src + sd.src_off;
         uint8_t* t = sd.dst;
-        if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 3u) == 0) {
+        if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 15u) == 0) {
+            const uint4* s16 = reinterpret_cast<const uint4*>(s);
+            uint4* t16 = reinterpret_cast<uint4*>(t);
+            for (uint32_t i = threadIdx.x; i < sd.len / 16; i += kThreads) t16[i] = s16[i];
+        } else if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 3u) == 0) {
             const uint32_t* s4 = reinterpret_cast<const uint32_t*>(s);
             uint32_t* t4 = reinterpret_cast<uint32_t*>(t);
             for (uint32_t i = threadIdx.x; i < sd.len / 4; i += kThreads) t4[i] = s4[i];
@@ -301,25 +315,34 @@ hipError_t launch_bw(const ExtShape& s, const uint32_t* x, const uint32_t* y, ui
                      uint64_t n_pairs, hipStream_t stream) {
     const uint64_t groups = (n_pairs + s.ppw - 1) / s.ppw;
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ext_ip_kernel<BW>, dim3((uint32_t)groups), dim3(kThreads),
+    hipLaunchKernelGGL(ext_ip_kernel<BW>, dim3((uint32_t)groups), dim3(s.threads),
                        s.lds_words * 4u, stream, x, y, out, n_pairs, s);
     return hipGetLastError();
 }
 
 template <int BW>
-hipError_t launch_batch_bw(const BatchStream* streams, const BatchTile* tiles, uint32_t n_tiles,
-                           uint32_t* head, uint32_t grid, uint32_t lds_bytes,
+hipError_t launch_batch_bw(uint32_t threads, const BatchStream* streams, const BatchTile* tiles,
+                           uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
                            hipStream_t stream) {
     hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
-    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(kThreads), lds_bytes, stream,
+    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
                        streams, tiles, n_tiles, head);
     return hipGetLastError();
 }
 
 template <int BW>
-hipError_t occupancy_bw(uint32_t lds_bytes, int* blocks_per_cu) {
+hipError_t launch_batch_only_bw(uint32_t threads, const BatchStream* streams,
+                                const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
+                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream) {
+    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
+                       streams, tiles, n_tiles, head);
+    return hipGetLastError();
+}
+
+template <int BW>
+hipError_t occupancy_bw(uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ext_batch_kernel<BW>,
-                                                        kThreads, lds_bytes);
+                                                        threads, lds_bytes);
 }
 
 }  // namespace
@@ -342,28 +365,46 @@ hipError_t occupancy_bw(uint32_t lds_bytes, int* blocks_per_cu) {
         default: return hipErrorInvalidValue;      \
     }
 
-hipError_t launch_batch(uint32_t bw, const BatchStream* streams, const BatchTile* tiles,
-                        uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
-                        hipStream_t stream) {
+hipError_t launch_batch(uint32_t bw, uint32_t threads, const BatchStream* streams,
+                        const BatchTile* tiles, uint32_t n_tiles, uint32_t* head, uint32_t grid,
+                        uint32_t lds_bytes, hipStream_t stream) {
     if (n_tiles == 0) return hipSuccess;
-    QEXT_BW_CASES(launch_batch_bw, streams, tiles, n_tiles, head, grid, lds_bytes, stream)
+    if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64) return hipErrorInvalidValue;
+    QEXT_BW_CASES(launch_batch_bw, threads, streams, tiles, n_tiles, head, grid, lds_bytes, stream)
 }
 
-hipError_t launch_scatter(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
-                          hipStream_t stream) {
-    if (n_descs == 0) return hipSuccess;
-    const uint32_t grid = n_descs < 2048u ? n_descs : 2048u;
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(kThreads), 0, stream, src, descs, n_descs);
+hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
+                        const void* meta_src, void* meta_dst, uint32_t meta_bytes, uint32_t* heads,
+                        uint32_t n_heads, hipStream_t stream) {
+    if (meta_bytes % 16) return hipErrorInvalidValue;
+    const uint32_t meta_vec = meta_bytes / 16;
+    uint32_t grid = n_descs;
+    grid = grid > (meta_vec + kThreads - 1) / kThreads ? grid : (meta_vec + kThreads - 1) / kThreads;
+    grid = grid < 1u ? 1u : (grid > 8192u ? 8192u : grid);
+    hipLaunchKernelGGL(stage_kernel, dim3(grid), dim3(kThreads), 0, stream, src, descs, n_descs,
+                       static_cast<const uint4*>(meta_src), static_cast<uint4*>(meta_dst), meta_vec,
+                       heads, n_heads);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(uint32_t bw, uint32_t lds_bytes, int* blocks_per_cu) {
-    QEXT_BW_CASES(occupancy_bw, lds_bytes, blocks_per_cu)
+hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
+                                const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
+                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream) {
+    if (n_tiles == 0) return hipSuccess;
+    if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64) return hipErrorInvalidValue;
+    QEXT_BW_CASES(launch_batch_only_bw, threads, streams, tiles, n_tiles, head, grid, lds_bytes,
+                  stream)
+}
+
+hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {
+    QEXT_BW_CASES(occupancy_bw, threads, lds_bytes, blocks_per_cu)
 }
 
 hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
                           uint32_t* out, uint64_t n_pairs, hipStream_t stream) {
     if (n_pairs == 0) return hipSuccess;
+    if (s.threads == 0 || s.threads > (uint32_t)kMaxThreads || s.threads % 64)
+        return hipErrorInvalidValue;
     const uint32_t bw = s.bw;
     QEXT_BW_CASES(launch_bw, s, x, y, out, n_pairs, stream)
 }

@@ -5,12 +5,14 @@
 //   submit() copies raw chunks into the cycle's pinned staging area and notes
 //   where each byte range goes in its channel's device ring (X and Y rings of
 //   R blocks each; block l lives in slot l mod R, so a block never wraps).
-//   The scheduler then queues on one HIP stream: the staging copy to the
-//   device, a scatter kernel that moves the ranges into the rings, one
-//   persistent launch per base size over a tile queue holding every block
-//   pair completed so far on every channel, and the copy of the outputs back
-//   to pinned memory; an event marks the cycle done.  Up to two cycles are in
-//   flight: chunks that arrive while one is on the GPU go into the next.
+//   The scheduler then queues on one HIP stream a staging kernel that reads
+//   the pinned staging area over the bus and moves the ranges into the rings
+//   (and the cycle's tile queue into device memory), then one persistent
+//   launch per base size over a tile queue holding every block pair completed
+//   so far on every channel, which writes the outputs straight into a pinned
+//   outbox; an event marks the cycle done.  No copy engine takes part, so no
+//   dependency between engines has to be resolved by the host.  Up to three
+//   cycles are in flight, and chunks that arrive meanwhile go into the next.
 //   Completed outputs are moved to per-channel host rings that poll() reads.
 //
 // Admission: a channel may hold at most R blocks between "received" and
@@ -28,6 +30,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/qrng_ext.h"
@@ -72,7 +75,7 @@ struct Range {
 };
 
 struct Group {
-    uint32_t bw, tile_off, n_tiles, lds_bytes, grid;
+    uint32_t bw, threads, tile_off, n_tiles, lds_bytes, grid;
 };
 
 // A submission's end position on one side, recorded in the cycle that holds it.
@@ -83,11 +86,10 @@ struct Resv {
 };
 
 struct Slot {
-    uint8_t* h_in = nullptr;   // pinned: data | descs | streams | tiles
-    uint8_t* d_in = nullptr;   // device mirror (+ queue heads)
-    uint8_t* h_out = nullptr;  // pinned outbox
-    uint8_t* d_out = nullptr;  // device outbox
-    hipEvent_t done = nullptr;
+    uint8_t* h_in = nullptr;   // pinned, read by the GPU: data | descs | streams | tiles
+    uint8_t* d_in = nullptr;   // device: streams | tiles | queue heads (same offsets)
+    uint8_t* h_out = nullptr;  // pinned outbox, written by the GPU
+    hipEvent_t done = nullptr; // the cycle's outputs are in h_out
     uint64_t data_used = 0;
     uint32_t n_descs = 0;
     int pending = 0;            // submissions still copying into h_in
@@ -111,12 +113,15 @@ struct ext_server {
     std::vector<Channel> ch;
     // slot layout
     size_t off_desc = 0, off_streams = 0, off_tiles = 0, off_heads = 0, in_bytes = 0;
-    Slot slots[3];
+    static constexpr int kSlots = 4;  // one filling, up to three in flight
+    Slot slots[kSlots];
     int filling = 0;
     std::deque<int> inflight;
-    std::map<std::pair<uint32_t, uint32_t>, int> occ_cache;  // (bw, lds) -> blocks per CU
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int> occ_cache;  // (bw, threads, lds)
     std::mutex mu;
     std::condition_variable cv;
+    std::condition_variable ready_cv;  // signalled when a cycle's outputs land
+    int ready_waiters = 0;
     std::thread sched;
     bool stop = false;
     int sticky = EXT_OK;
@@ -130,7 +135,6 @@ void server_free(ext_server* s) {
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
         (void)hipFree(sl.d_in);
-        (void)hipFree(sl.d_out);
         if (sl.done) (void)hipEventDestroy(sl.done);
     }
     for (Channel& c : s->ch) {
@@ -162,6 +166,7 @@ void harvest(ext_server* s) {
             c.completed += r.n;
         }
         s->stats.gpu_busy_ns += t - sl.launched_ns;
+        if (s->ready_waiters && !sl.ranges.empty()) s->ready_cv.notify_all();
         sl.ranges.clear();
         sl.data_used = 0;
         sl.n_descs = 0;
@@ -169,12 +174,12 @@ void harvest(ext_server* s) {
     }
 }
 
-int occupancy(ext_server* s, uint32_t bw, uint32_t lds) {
-    auto key = std::make_pair(bw, lds);
+int occupancy(ext_server* s, uint32_t bw, uint32_t threads, uint32_t lds) {
+    auto key = std::make_tuple(bw, threads, lds);
     auto it = s->occ_cache.find(key);
     if (it != s->occ_cache.end()) return it->second;
     int occ = 0;
-    if (qext::batch_occupancy(bw, lds, &occ) != hipSuccess || occ <= 0) occ = 1;
+    if (qext::batch_occupancy(bw, threads, lds, &occ) != hipSuccess || occ <= 0) occ = 1;
     s->occ_cache[key] = occ;
     return occ;
 }
@@ -186,7 +191,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     Slot& sl = s->slots[idx];
     // the next filling slot: one that is neither in flight nor this one
     int next = -1;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < ext_server::kSlots; ++k) {
         if (k == idx) continue;
         if (std::find(s->inflight.begin(), s->inflight.end(), k) == s->inflight.end()) next = k;
     }
@@ -202,8 +207,8 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     sl.resv.clear();
 
     // tiles of every channel's ready pairs, grouped by base size
-    std::map<uint32_t, std::vector<BatchTile>> by_bw;
-    std::map<uint32_t, uint32_t> lds_of;
+    std::map<std::pair<uint32_t, uint32_t>, std::vector<BatchTile>> by_bw;  // (bw, threads)
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> lds_of;
     uint64_t out_off = 0;
     uint32_t n_tiles = 0;
     sl.ranges.clear();
@@ -220,8 +225,9 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
                 k = std::min<uint64_t>(k, (uint64_t)(s->cfg.max_tiles - n_tiles) * c.shape.ppw);
             if (k == 0) break;
             sl.ranges.push_back(Range{ci, (uint32_t)k, c.launched, out_off});
-            auto& vec = by_bw[c.shape.bw];
-            lds_of[c.shape.bw] = std::max(lds_of[c.shape.bw], c.shape.lds_words * 4);
+            const auto key = std::make_pair(c.shape.bw, c.shape.threads);
+            auto& vec = by_bw[key];
+            lds_of[key] = std::max(lds_of[key], c.shape.lds_words * 4);
             for (uint64_t p = 0; p < k; p += c.shape.ppw) {
                 const uint32_t n = (uint32_t)std::min<uint64_t>(c.shape.ppw, k - p);
                 vec.push_back(BatchTile{ci, n, slot0 + p, (out_off + p * c.qb) / 4});
@@ -239,16 +245,27 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
         const Channel& c = s->ch[ci];
         hs[ci] = BatchStream{(const uint32_t*)c.ring_x, (const uint32_t*)c.ring_y,
-                             (uint32_t*)sl.d_out, 0, c.shape};
+                             (uint32_t*)sl.h_out, 0, c.shape};
     }
     BatchTile* ht = reinterpret_cast<BatchTile*>(sl.h_in + s->off_tiles);
     sl.groups.clear();
     uint32_t t_off = 0;
     for (auto& kv : by_bw) {
-        Group g{kv.first, t_off, (uint32_t)kv.second.size(), lds_of[kv.first], 0};
+        // longest tiles first: a lane's critical path is its rounds times the
+        // base products per item
+        auto cost = [&](const BatchTile& t) {
+            const ExtShape& sh = s->ch[t.stream].shape;
+            const uint64_t items = (uint64_t)t.npw * sh.np * sh.groups;
+            return ((items + sh.threads - 1) / sh.threads) * sh.epg;
+        };
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [&](const BatchTile& a, const BatchTile& b) { return cost(a) > cost(b); });
+        Group g{kv.first.first, kv.first.second, t_off, (uint32_t)kv.second.size(),
+                lds_of[kv.first], 0};
         memcpy(ht + t_off, kv.second.data(), kv.second.size() * sizeof(BatchTile));
         g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles,
-                                              (uint64_t)s->cus * occupancy(s, g.bw, g.lds_bytes));
+                                              (uint64_t)s->cus *
+                                                  occupancy(s, g.bw, g.threads, g.lds_bytes));
         t_off += g.n_tiles;
         sl.groups.push_back(g);
     }
@@ -262,26 +279,23 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     // queue the cycle without holding the lock (submit() now fills `next`)
     lk.unlock();
     hipError_t e = hipSuccess;
+    // one stream, two kernels: staging (reads the pinned area over the bus),
+    // then one persistent launch per base size writing outputs straight into
+    // the pinned outbox
     const size_t meta_bytes =
-        s->off_tiles + (size_t)n_tiles * sizeof(BatchTile) - s->off_desc;
+        (s->off_tiles + (size_t)n_tiles * sizeof(BatchTile) - s->off_streams + 15) / 16 * 16;
     sl.launched_ns = now_ns();
-    if (sl.data_used)
-        e = hipMemcpyAsync(sl.d_in, sl.h_in, sl.data_used, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.d_in + s->off_desc, sl.h_in + s->off_desc, meta_bytes,
-                           hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-        e = qext::launch_scatter(sl.d_in, reinterpret_cast<const ScatterDesc*>(sl.d_in + s->off_desc),
-                                 sl.n_descs, s->stream);
+    e = qext::launch_stage(sl.h_in, reinterpret_cast<const ScatterDesc*>(sl.h_in + s->off_desc),
+                           sl.n_descs, sl.h_in + s->off_streams, sl.d_in + s->off_streams,
+                           (uint32_t)meta_bytes, reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads),
+                           (uint32_t)sl.groups.size(), s->stream);
     for (size_t gi = 0; gi < sl.groups.size() && e == hipSuccess; ++gi) {
         const Group& g = sl.groups[gi];
-        e = qext::launch_batch(g.bw, reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
-                               reinterpret_cast<const BatchTile*>(sl.d_in + s->off_tiles) + g.tile_off,
-                               g.n_tiles, reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi,
-                               g.grid, g.lds_bytes, s->stream);
+        e = qext::launch_batch_noreset(
+            g.bw, g.threads, reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
+            reinterpret_cast<const BatchTile*>(sl.d_in + s->off_tiles) + g.tile_off, g.n_tiles,
+            reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi, g.grid, g.lds_bytes, s->stream);
     }
-    if (e == hipSuccess && sl.out_bytes)
-        e = hipMemcpyAsync(sl.h_out, sl.d_out, sl.out_bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, s->stream);
     lk.lock();
     if (e != hipSuccess) {
@@ -310,7 +324,7 @@ void scheduler(ext_server* s) {
             if (s->stop) break;
             continue;
         }
-        if (!s->stop && s->inflight.size() < 2 && has_work(s)) {
+        if (!s->stop && s->inflight.size() < (size_t)ext_server::kSlots - 1 && has_work(s)) {
             launch_cycle(s, lk);
             s->cv.notify_all();
             continue;
@@ -332,7 +346,8 @@ void ext_server_config_init(ext_server_config* c) {
     if (!c) return;
     memset(c, 0, sizeof *c);
     c->max_channels = 256;
-    c->ring_blocks = 512;
+    c->ring_blocks = 0;
+    c->ring_bytes = 4ull << 20;
     c->stage_bytes = 64ull << 20;
     c->outbox_bytes = 32ull << 20;
     c->max_tiles = 1u << 17;
@@ -349,7 +364,8 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
     ext_params dp;
     ext_params_init(&dp);
     if (!p) p = &dp;
-    if (p->n_taps || cfg->max_channels == 0 || cfg->ring_blocks == 0 || cfg->stage_bytes == 0 ||
+    if (p->n_taps || cfg->max_channels == 0 || (cfg->ring_blocks == 0 && cfg->ring_bytes == 0) ||
+        cfg->stage_bytes == 0 ||
         cfg->outbox_bytes < 4 || cfg->max_tiles == 0 || cfg->max_descs < 4)
         return EXT_EINVAL;
     ext_server* s = new (std::nothrow) ext_server;
@@ -376,15 +392,17 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
     s->off_desc = align_up(cfg->stage_bytes, 256);
     s->off_streams = align_up(s->off_desc + (size_t)cfg->max_descs * sizeof(ScatterDesc), 256);
     s->off_tiles = align_up(s->off_streams + (size_t)cfg->max_channels * sizeof(BatchStream), 256);
-    s->off_heads = align_up(s->off_tiles + (size_t)cfg->max_tiles * sizeof(BatchTile), 256);
+    // (+16: the metadata copy is rounded up to 16 bytes)
+    s->off_heads = align_up(s->off_tiles + (size_t)cfg->max_tiles * sizeof(BatchTile) + 16, 256);
     s->in_bytes = s->off_heads + 64 * sizeof(uint32_t);
     bool ok = true;
     for (Slot& sl : s->slots) {
-        ok = ok && hipHostMalloc((void**)&sl.h_in, s->in_bytes, hipHostMallocDefault) == hipSuccess;
-        ok = ok && hipHostMalloc((void**)&sl.h_out, cfg->outbox_bytes, hipHostMallocDefault) ==
+        // coherent (fine-grained) host memory: the GPU reads the staging area
+        // and writes the outbox over the bus, visible once the cycle's event is
+        ok = ok && hipHostMalloc((void**)&sl.h_in, s->in_bytes, hipHostMallocCoherent) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&sl.h_out, cfg->outbox_bytes, hipHostMallocCoherent) ==
                        hipSuccess;
         ok = ok && hipMalloc((void**)&sl.d_in, s->in_bytes) == hipSuccess;
-        ok = ok && hipMalloc((void**)&sl.d_out, cfg->outbox_bytes) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
     }
     try {
@@ -418,7 +436,8 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
         return EXT_ENOMEM;
     }
     const uint32_t n_e = (uint32_t)(n_bits / m_bits);
-    qext::PlanKnobs knobs{s->params.base_bits / 32, s->params.groups, s->params.pairs_per_group};
+    qext::PlanKnobs knobs{s->params.base_bits / 32, s->params.groups, s->params.pairs_per_group,
+                          s->params.threads};
     if (s->params.autotune &&
         qext::autotune_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), s->stream, &knobs,
                              nullptr) != hipSuccess)
@@ -426,6 +445,14 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     ExtShape shape;
     if (!qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), knobs, &shape))
         return EXT_ENOTSUP;
+    // latency: a shape with more work items per pair than one 256-lane group
+    // has lanes runs on 1024-lane groups (one round instead of several)
+    if (!s->params.threads && (uint64_t)shape.np * shape.groups > (uint64_t)qext::kThreads) {
+        qext::PlanKnobs wide = knobs;
+        wide.threads = qext::kMaxThreads;
+        ExtShape ws;
+        if (qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), wide, &ws)) shape = ws;
+    }
     const uint64_t nb = n_bits / 8, qb = m_bits / 8;
     if (qb > s->cfg.outbox_bytes) return EXT_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
@@ -440,8 +467,8 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     c.nb = nb;
     c.qb = qb;
     c.shape = shape;
-    c.R = s->cfg.ring_blocks;
-    if (c.R * nb > s->cfg.stage_bytes) c.R = std::max<uint64_t>(1, s->cfg.stage_bytes / nb);
+    c.R = s->cfg.ring_blocks ? s->cfg.ring_blocks
+                             : std::max<uint64_t>(128, s->cfg.ring_bytes / nb);
     try {
         c.out_ring.resize(c.R * qb);
         c.ready_ns.resize(c.R);
@@ -475,8 +502,10 @@ int ext_server_submit(ext_server* s, uint32_t channel, const void* x, size_t x_l
         return EXT_EAGAIN;
     }
     Slot& sl = s->slots[s->filling];
-    // each side needs at most two descriptors (ring wrap)
-    if (sl.data_used + x_len + y_len > s->cfg.stage_bytes || sl.n_descs + 4 > s->cfg.max_descs) {
+    // descriptors: one per 16 KiB piece, plus one per side for the ring wrap
+    const uint64_t need_descs = (x_len + 16383) / 16384 + (y_len + 16383) / 16384 + 4;
+    if (sl.data_used + x_len + y_len > s->cfg.stage_bytes ||
+        sl.n_descs + need_descs > s->cfg.max_descs) {
         s->stats.eagain_stage += 1;
         s->cv.notify_all();
         return EXT_EAGAIN;
@@ -485,11 +514,14 @@ int ext_server_submit(ext_server* s, uint32_t channel, const void* x, size_t x_l
     const uint64_t ring_bytes = c.R * c.nb;
     ScatterDesc* descs = reinterpret_cast<ScatterDesc*>(sl.h_in + s->off_desc);
     uint8_t* dst_x = sl.h_in + sl.data_used;
+    // copy ranges of at most kPiece bytes, none crossing the ring's end, so the
+    // scatter kernel spreads a large chunk over many work-groups
+    constexpr uint64_t kPiece = 16384;
     auto reserve = [&](size_t len, uint64_t pos, uint8_t* ring) {
         uint64_t done = 0;
         while (done < len) {
             const uint64_t off = (pos + done) % ring_bytes;
-            const uint64_t k = std::min<uint64_t>(len - done, ring_bytes - off);
+            const uint64_t k = std::min<uint64_t>({len - done, ring_bytes - off, kPiece});
             descs[sl.n_descs++] = ScatterDesc{sl.data_used + done, ring + off, (uint32_t)k, channel};
             done += k;
         }
@@ -535,6 +567,30 @@ int ext_server_poll(ext_server* s, uint32_t channel, void* out, size_t out_cap, 
     if (blocks_done) *blocks_done = c.polled;
     if (k) s->cv.notify_all();
     return EXT_OK;
+}
+
+int ext_server_ready(ext_server* s, uint32_t* chans, uint32_t cap, uint32_t* n,
+                     uint32_t timeout_us) {
+    if (!s || !n || (cap && !chans)) return EXT_EINVAL;
+    *n = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto collect = [&] {
+        uint32_t k = 0;
+        for (uint32_t ci = 0; ci < s->ch.size() && k < cap; ++ci) {
+            const Channel& c = s->ch[ci];
+            if (c.open && c.completed > c.polled) chans[k++] = ci;
+        }
+        return k;
+    };
+    uint32_t k = collect();
+    if (!k && timeout_us) {
+        s->ready_waiters += 1;
+        s->ready_cv.wait_for(lk, std::chrono::microseconds(timeout_us));
+        s->ready_waiters -= 1;
+        k = collect();
+    }
+    *n = k;
+    return s->sticky;
 }
 
 int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
@@ -586,6 +642,7 @@ int ext_server_destroy(ext_server* s) {
         std::unique_lock<std::mutex> lk(s->mu);
         s->stop = true;
         s->cv.notify_all();
+        s->ready_cv.notify_all();
     }
     if (s->sched.joinable()) s->sched.join();
     (void)hipStreamSynchronize(s->stream);

@@ -3,8 +3,9 @@
 // Channel c receives chunks at the jumps of a Poisson process of rate
 // lambda_c = (raw_bytes_per_s / n_channels) / (2 * nb_c * mean_k); a chunk is
 // k blocks of X and k blocks of Y (k uniform on [min, max]), read cyclically
-// from the channel's pools.  A producer thread submits every chunk at its
-// scheduled time (or as soon after as admission allows); a consumer thread
+// from the channel's pools.  Producer threads (channels split among them)
+// submit every chunk at its scheduled time (or as soon after as admission
+// allows); a consumer thread
 // polls every channel and takes, for each returned block, the latency from
 // the scheduled arrival of the chunk that completed it to the poll that
 // returned it.  The same trace can drive the server or the plain streaming
@@ -109,8 +110,14 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
         else
             ext_params_init(&p);
         p.mem_kind = EXT_MEM_HOST;
-        const uint64_t ring = cfg->server_cfg ? cfg->server_cfg->ring_blocks : 512;
         for (uint32_t c = 0; c < nc && rc == EXT_OK; ++c) {
+            // the same per-channel device budget the server would give the channel
+            uint64_t ring = 0;
+            if (cfg->server_cfg && cfg->server_cfg->ring_blocks)
+                ring = cfg->server_cfg->ring_blocks;
+            else
+                ring = std::max<uint64_t>(
+                    128, (cfg->server_cfg ? cfg->server_cfg->ring_bytes : (4ull << 20)) / ch[c]->nb);
             p.device_bytes_cap = ring * ch[c]->nb;
             rc = ext_create(cfg->n_bits[c], cfg->m_bits[c], &p, &ch[c]->ctx);
             if (rc == EXT_OK) rc = ext_stream_open(ch[c]->ctx, &ch[c]->st);
@@ -133,16 +140,21 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     std::atomic<bool> producer_done{false};
     std::atomic<int> fail{EXT_OK};
     std::atomic<uint64_t> eagain{0}, max_lag{0}, chunks_done{0};
-    uint64_t unsubmitted_in_window = 0;  // blocks of chunks never submitted (producer only)
+    std::atomic<uint64_t> unsubmitted_in_window{0};  // blocks of chunks never submitted
     const uint64_t lag_limit = cfg->max_lag_s > 0 ? (uint64_t)(cfg->max_lag_s * 1e9) : ~0ull;
+    const uint32_t n_prod = cfg->producer_threads ? cfg->producer_threads : 4;
+    std::atomic<uint32_t> producers_left{n_prod};
 
-    std::thread producer([&] {
+    // producer p submits the chunks of channels c with c % n_prod == p, in time order
+    auto produce = [&](uint32_t pid) {
         size_t next = 0;
         for (; next < ev.size(); ++next) {
             const Event& e = ev[next];
+            if (e.ch % n_prod != pid) continue;
             if (fail.load()) break;
             const uint64_t target = t0 + e.t_ns;
-            if (now_ns() > target && now_ns() - target > lag_limit) break;
+            const uint64_t t_now = now_ns();
+            if (t_now > target && t_now - target > lag_limit) break;
             for (;;) {
                 const uint64_t t = now_ns();
                 if (t >= target) break;
@@ -176,7 +188,9 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             }
             if (fail.load()) break;
             const uint64_t lag = now_ns() - target;
-            if (lag > max_lag.load()) max_lag.store(lag);
+            uint64_t prev = max_lag.load();
+            while (lag > prev && !max_lag.compare_exchange_weak(prev, lag)) {
+            }
             c.pool_pos += len;
             {
                 std::lock_guard<std::mutex> g(c.mu);
@@ -185,15 +199,25 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             }
             chunks_done++;
         }
+        uint64_t left = 0;
         for (; next < ev.size(); ++next) {
+            if (ev[next].ch % n_prod != pid) continue;
             const uint64_t target = t0 + ev[next].t_ns;
-            if (target >= win_lo && target < win_hi) unsubmitted_in_window += ev[next].k;
+            if (target >= win_lo && target < win_hi) left += ev[next].k;
         }
-        producer_done.store(true);
-    });
+        unsubmitted_in_window += left;
+        if (--producers_left == 0) producer_done.store(true);
+    };
+    std::vector<std::thread> producers;
+    for (uint32_t pidx = 0; pidx < n_prod; ++pidx) producers.emplace_back(produce, pidx);
 
-    std::vector<uint64_t> lat;  // ns, blocks arrived in the window
-    lat.reserve(1 << 20);
+    // latencies of blocks arrived in the window: 1 us bins up to ~1 s, exact
+    // maximum and sum kept aside (a fixed histogram never reallocates, so the
+    // bookkeeping never stalls the threads that share a channel's lock)
+    constexpr uint64_t kBins = 1u << 20;
+    std::vector<uint32_t> hist(kBins, 0);
+    uint64_t lat_n = 0, lat_max = 0;
+    double lat_sum = 0;
     double out_bits = 0, in_bits = 0;
     std::thread consumer([&] {
         uint64_t maxqb = 0;
@@ -201,9 +225,24 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
         std::vector<uint8_t> buf(maxqb * 256);
         const uint64_t deadline_after = (uint64_t)(cfg->grace_s * 1e9);
         uint64_t producer_end = 0;
+        std::vector<uint32_t> ready(nc);
+        std::vector<uint64_t> arrivals;
+        arrivals.reserve(buf.size());
         for (;;) {
             bool progress = false;
-            for (uint32_t ci = 0; ci < nc && !fail.load(); ++ci) {
+            uint32_t n_ready = nc;
+            if (srv) {
+                // sleep until some channel has output, then visit only those
+                const int r = ext_server_ready(srv, ready.data(), nc, &n_ready, 200);
+                if (r != EXT_OK) {
+                    fail.store(r);
+                    break;
+                }
+            } else {
+                for (uint32_t i = 0; i < nc; ++i) ready[i] = i;
+            }
+            for (uint32_t ri = 0; ri < n_ready && !fail.load(); ++ri) {
+                const uint32_t ci = ready[ri];
                 Chan& c = *ch[ci];
                 size_t len = 0;
                 int r;
@@ -222,18 +261,29 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
                 const uint64_t t = now_ns();
                 progress = true;
                 const uint64_t nblk = len / c.qb;
-                std::lock_guard<std::mutex> g(c.mu);
-                for (uint64_t i = 0; i < nblk; ++i) {
-                    const uint64_t blk = c.returned + i;
-                    while (!c.chunks.empty() && c.chunks.front().first <= blk) c.chunks.pop_front();
-                    if (c.chunks.empty()) break;  // cannot happen: outputs follow submissions
-                    const uint64_t arr = c.chunks.front().second;
-                    if (arr >= win_lo && arr < win_hi) {
-                        lat.push_back(t - arr);
-                        out_bits += 8.0 * c.qb;
-                        in_bits += 16.0 * c.nb;
+                // arrival time of each returned block: the chunk that completed it
+                arrivals.clear();
+                {
+                    std::lock_guard<std::mutex> g(c.mu);
+                    for (uint64_t i = 0; i < nblk; ++i) {
+                        const uint64_t blk = c.returned + i;
+                        while (!c.chunks.empty() && c.chunks.front().first <= blk)
+                            c.chunks.pop_front();
+                        if (c.chunks.empty()) break;  // cannot happen: outputs follow submissions
+                        arrivals.push_back(c.chunks.front().second);
                     }
                 }
+                for (uint64_t arr : arrivals) {
+                    if (arr < win_lo || arr >= win_hi) continue;
+                    const uint64_t l = t - arr;
+                    hist[std::min<uint64_t>(l / 1000, kBins - 1)] += 1;
+                    lat_n += 1;
+                    lat_sum += (double)l;
+                    lat_max = std::max(lat_max, l);
+                    out_bits += 8.0 * c.qb;
+                    in_bits += 16.0 * c.nb;
+                }
+                std::lock_guard<std::mutex> g(c.mu);
                 if (cfg->capture && cfg->capture[ci] && cfg->capture_cap) {
                     const uint64_t room = cfg->capture_cap[ci] - c.captured;
                     const uint64_t k = std::min<uint64_t>(room, len);
@@ -258,11 +308,11 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             if (!progress) std::this_thread::yield();
         }
     });
-    producer.join();
+    for (auto& t : producers) t.join();
     consumer.join();
 
     // blocks that arrived in the window but never came back
-    uint64_t missing = unsubmitted_in_window;
+    uint64_t missing = unsubmitted_in_window.load();
     for (auto& c : ch) {
         std::lock_guard<std::mutex> g(c->mu);
         uint64_t prev_end = 0;
@@ -275,7 +325,12 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     }
     if (srv) {
         ext_server_stats st;
-        if (ext_server_stats_get(srv, &st) == EXT_OK) res->cycles = st.cycles;
+        if (ext_server_stats_get(srv, &st) == EXT_OK) {
+            res->cycles = st.cycles;
+            res->eagain_ring = st.eagain_ring;
+            res->eagain_stage = st.eagain_stage;
+            res->mean_cycle_us = st.cycles ? st.gpu_busy_ns / 1e3 / st.cycles : 0.0;
+        }
     }
     if (capture_len)
         for (uint32_t c = 0; c < nc; ++c) capture_len[c] = ch[c]->captured;
@@ -283,27 +338,30 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     const int f = fail.load();
     if (f != EXT_OK && f != EXT_EAGAIN) return f;
 
-    std::sort(lat.begin(), lat.end());
     res->window_s = cfg->duration_s;
     res->out_gbps = out_bits / cfg->duration_s / 1e9;
     res->in_gbps = in_bits / cfg->duration_s / 1e9;
     res->offered_in_gbps = offered_bits / cfg->duration_s / 1e9;
-    res->blocks_measured = lat.size() + missing;
+    res->blocks_measured = lat_n + missing;
     res->blocks_missing = missing;
     res->chunks = chunks_done.load();
     res->eagain = eagain.load();
     res->max_submit_lag_us = max_lag.load() / 1e3;
-    if (!lat.empty()) {
+    if (lat_n) {
+        // percentile = upper edge of the 1 us bin holding the rank-th latency
         auto pct = [&](double q) {
-            size_t i = (size_t)(q * (double)(lat.size() - 1) + 0.5);
-            return lat[std::min(i, lat.size() - 1)] / 1e3;
+            const uint64_t rank = (uint64_t)(q * (double)(lat_n - 1)) + 1;
+            uint64_t acc = 0;
+            for (uint64_t b = 0; b < kBins; ++b) {
+                acc += hist[b];
+                if (acc >= rank) return b + 1 >= kBins ? lat_max / 1e3 : (double)(b + 1);
+            }
+            return lat_max / 1e3;
         };
         res->lat_p50_us = pct(0.50);
         res->lat_p99_us = pct(0.99);
-        res->lat_max_us = lat.back() / 1e3;
-        double sum = 0;
-        for (uint64_t v : lat) sum += (double)v;
-        res->lat_mean_us = sum / lat.size() / 1e3;
+        res->lat_max_us = lat_max / 1e3;
+        res->lat_mean_us = lat_sum / lat_n / 1e3;
     }
     return f == EXT_EAGAIN ? EXT_EAGAIN : EXT_OK;
 }

@@ -143,7 +143,8 @@ def test_autotuned_plan_is_bit_identical(dev):
     x, y = to_dev(dev, w.x), to_dev(dev, w.y)
     outs = []
     for kw in (dict(), dict(autotune=True), dict(base_bits=128), dict(base_bits=512),
-               dict(groups=4), dict(groups=2, base_bits=128)):
+               dict(groups=4), dict(groups=2, base_bits=128), dict(threads=1024),
+               dict(threads=1024, base_bits=128, groups=4)):
         out = torch.zeros(300 * 256, dtype=torch.uint8, device=dev)
         with binding.Extractor(8192, 2048, device_memory=True,
                                stream=torch.cuda.current_stream(dev).cuda_stream, **kw) as ex:
@@ -154,3 +155,20 @@ def test_autotuned_plan_is_bit_identical(dev):
     want = oracle.ext_blocks(w.x, w.y, 8192, 2048)
     for o in outs:
         assert np.array_equal(o, want)
+
+
+def test_wide_workgroups_large_field(dev):
+    """1024-lane work-groups (one round for the 729 items of an m = 16384
+    pair) give the oracle's bytes, in the plain form and in a batch."""
+    import torch
+
+    w = inputs.plain_workload(65536, 16384, 3, 31, 32, kind="ar1")
+    want = oracle.ext_blocks(w.x, w.y, 65536, 16384)
+    x, y = to_dev(dev, w.x), to_dev(dev, w.y)
+    out = torch.zeros(3 * 2048, dtype=torch.uint8, device=dev)
+    with binding.Extractor(65536, 16384, device_memory=True, threads=1024,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        say(ex.describe())
+        ex.extract(x, y, out, 3)
+        ex.sync()
+    assert np.array_equal(out.cpu().numpy(), want)
