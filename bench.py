@@ -155,7 +155,8 @@ def batched_leg(dev, stream, steps: int, warmup: int):
 
 
 def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
-                                                             "plain_at_1/16_load")):
+                                                             "plain_at_1/16_load"),
+               wg_per_cu: int = 0, max_inflight: int = 0):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
     1..64 blocks, 64 Gbps aggregate raw input; three quarters i.i.d. Gaussian
     with n from 2048..32768, one quarter AR(1) with n = 65536.  Served form
@@ -192,7 +193,10 @@ def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
             continue
         log("served leg: %s, %.1f Gbps raw, %.0f s window" % (name, r * 8 / 1e9, duration_s))
         res, _ = binding.simulate(chans, mode=mode, raw_bytes_per_s=r, warmup_s=warmup_s,
-                                  duration_s=duration_s, grace_s=2.0, max_lag_s=lag, seed=4)
+                                  duration_s=duration_s, grace_s=2.0, max_lag_s=lag, seed=4,
+                                  config=binding.server_config(
+                                      wg_per_cu=wg_per_cu,
+                                      **({"max_inflight": max_inflight} if max_inflight else {})))
         log("served leg: %s: %s" % (name, json.dumps(res)))
         out[name] = {
             "output_gbps": round(res["out_gbps"], 3),
@@ -225,6 +229,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-modes", default="served,plain,plain_at_1/16_load",
                     help="comma-separated subset of the served-leg runs")
+    ap.add_argument("--serve-inflight", type=int, default=0,
+                    help="server cycles queued on the GPU at once (0 = library default)")
+    ap.add_argument("--serve-wg-per-cu", type=int, default=0,
+                    help="persistent work-groups per CU in a served cycle (0 = as many as fit)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, also run a plain 64 MiB device copy 4 times (the "
                          "reference kernel that scales HBM traffic counters)")
@@ -307,7 +315,8 @@ def main():
     served = None
     if not args.no_served:
         served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
-                            modes=args.serve_modes.split(","))
+                            modes=args.serve_modes.split(","), wg_per_cu=args.serve_wg_per_cu,
+                            max_inflight=args.serve_inflight)
 
     sec = ms * 1e-3
     out_gbps = N_PAIRS * M_BITS / sec / 1e9

@@ -224,7 +224,8 @@ int ext_batch_destroy(ext_batch *b);
  * scheduler thread inside the server repeatedly takes everything that
  * arrived, moves it to the channels' device rings and computes every block
  * pair completed so far on every channel in one persistent launch per base
- * size, while earlier cycles are still on the GPU (at most three in flight).  Outputs come back per channel, in block order, exactly once.
+ * size, while earlier cycles may still be on the GPU (at most max_inflight).
+ * Outputs come back per channel, in block order, exactly once.
  * Admission: a channel holds at most its ring's worth of blocks between
  * received and polled, and a cycle takes at most stage_bytes of input and returns at most
  * outbox_bytes of output; beyond that ext_server_submit returns EXT_EAGAIN
@@ -239,11 +240,17 @@ typedef struct {
     uint64_t outbox_bytes;  /* output bytes one cycle can return (default 32 MiB) */
     uint32_t max_tiles;     /* work-group tiles per cycle (default 131072) */
     uint32_t max_descs;     /* copy ranges per cycle (default 65536) */
-    uint32_t poll_us;       /* scheduler re-check period while a cycle runs (default 20) */
-    uint32_t reserved0;
+    uint32_t poll_us;       /* scheduler re-check period while a cycle runs; 0 or 1 = keep
+                               checking (yielding the CPU between checks; default 0) */
+    uint32_t wg_per_cu;     /* at most this many persistent work-groups per CU in a
+                               cycle's launch (enforced through the LDS request when the
+                               device allows it); 0 = as many as fit (default 0) */
     uint64_t ring_bytes;    /* when ring_blocks == 0: ring per channel side in bytes, rounded
                                down to whole blocks, at least 128 blocks (default 4 MiB) */
-    uint32_t reserved[2];
+    uint32_t max_inflight;  /* cycles queued on the GPU at once, 1..3: 1 gives the lowest
+                               latency at light load, more overlap the host's launch work
+                               with the GPU at heavy load (default 1) */
+    uint32_t reserved;
 } ext_server_config;
 typedef struct {
     uint64_t cycles, tiles, pairs, bytes_in;

@@ -86,9 +86,10 @@ class ServerConfig(ctypes.Structure):
         ("max_tiles", ctypes.c_uint32),
         ("max_descs", ctypes.c_uint32),
         ("poll_us", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("wg_per_cu", ctypes.c_uint32),
         ("ring_bytes", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("max_inflight", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 

@@ -11,8 +11,9 @@
 //   launch per base size over a tile queue holding every block pair completed
 //   so far on every channel, which writes the outputs straight into a pinned
 //   outbox; an event marks the cycle done.  No copy engine takes part, so no
-//   dependency between engines has to be resolved by the host.  Up to three
-//   cycles are in flight, and chunks that arrive meanwhile go into the next.
+//   dependency between engines has to be resolved by the host.  Up to
+//   max_inflight cycles are queued, and chunks that arrive meanwhile go into
+//   the next.
 //   Completed outputs are moved to per-channel host rings that poll() reads.
 //
 // Admission: a channel may hold at most R blocks between "received" and
@@ -108,12 +109,15 @@ struct ext_server {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int cus = 1;
+    uint32_t lds_per_cu = 65536;     // LDS bytes per CU
+    uint32_t lds_per_block = 65536;  // largest LDS request of one work-group
     ext_server_config cfg{};
     ext_params params{};
     std::vector<Channel> ch;
     // slot layout
     size_t off_desc = 0, off_streams = 0, off_tiles = 0, off_heads = 0, in_bytes = 0;
-    static constexpr int kSlots = 4;  // one filling, up to three in flight
+    static constexpr int kSlots = 4;  // one filling, up to kMaxInflight in flight
+    static constexpr uint32_t kMaxInflight = kSlots - 1;
     Slot slots[kSlots];
     int filling = 0;
     std::deque<int> inflight;
@@ -263,9 +267,19 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         Group g{kv.first.first, kv.first.second, t_off, (uint32_t)kv.second.size(),
                 lds_of[kv.first], 0};
         memcpy(ht + t_off, kv.second.data(), kv.second.size() * sizeof(BatchTile));
-        g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles,
-                                              (uint64_t)s->cus *
-                                                  occupancy(s, g.bw, g.threads, g.lds_bytes));
+        int per_cu = occupancy(s, g.bw, g.threads, g.lds_bytes);
+        if (s->cfg.wg_per_cu && (int)s->cfg.wg_per_cu < per_cu) {
+            // at most wg_per_cu groups per CU: ask for just over 1/(k+1) of the
+            // CU's LDS, so the dispatcher cannot stack more groups on one CU
+            // (long tiles then keep their SIMDs to themselves)
+            const uint32_t k = s->cfg.wg_per_cu;
+            const uint32_t pad = s->lds_per_cu / (k + 1) + 256;
+            if (pad <= s->lds_per_block) {
+                g.lds_bytes = std::max(g.lds_bytes, pad);
+                per_cu = (int)k;
+            }
+        }
+        g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles, (uint64_t)s->cus * per_cu);
         t_off += g.n_tiles;
         sl.groups.push_back(g);
     }
@@ -324,14 +338,21 @@ void scheduler(ext_server* s) {
             if (s->stop) break;
             continue;
         }
-        if (!s->stop && s->inflight.size() < (size_t)ext_server::kSlots - 1 && has_work(s)) {
+        if (!s->stop && s->inflight.size() < (size_t)s->cfg.max_inflight && has_work(s)) {
             launch_cycle(s, lk);
             s->cv.notify_all();
             continue;
         }
         if (!s->inflight.empty()) {
-            // a cycle is on the GPU: look again shortly (or when data arrive)
-            s->cv.wait_for(lk, std::chrono::microseconds(s->cfg.poll_us));
+            // a cycle is on the GPU: look again at once (a timed wait sleeps for
+            // tens of microseconds at least), or after poll_us if configured
+            if (s->cfg.poll_us > 1) {
+                s->cv.wait_for(lk, std::chrono::microseconds(s->cfg.poll_us));
+            } else {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            }
         } else {
             s->cv.wait_for(lk, std::chrono::milliseconds(2));
         }
@@ -351,8 +372,9 @@ void ext_server_config_init(ext_server_config* c) {
     c->stage_bytes = 64ull << 20;
     c->outbox_bytes = 32ull << 20;
     c->max_tiles = 1u << 17;
+    c->max_inflight = 1;
     c->max_descs = 1u << 16;
-    c->poll_us = 20;
+    c->poll_us = 0;
 }
 
 int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_server** out) {
@@ -366,12 +388,12 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
     if (!p) p = &dp;
     if (p->n_taps || cfg->max_channels == 0 || (cfg->ring_blocks == 0 && cfg->ring_bytes == 0) ||
         cfg->stage_bytes == 0 ||
-        cfg->outbox_bytes < 4 || cfg->max_tiles == 0 || cfg->max_descs < 4)
+        cfg->outbox_bytes < 4 || cfg->max_tiles == 0 || cfg->max_descs < 4 ||
+        cfg->max_inflight == 0 || cfg->max_inflight > ext_server::kMaxInflight)
         return EXT_EINVAL;
     ext_server* s = new (std::nothrow) ext_server;
     if (!s) return EXT_ENOMEM;
     s->cfg = *cfg;
-    if (!s->cfg.poll_us) s->cfg.poll_us = 20;
     s->params = *p;
     int dev = p->device;
     if ((dev < 0 && hipGetDevice(&dev) != hipSuccess) || hipSetDevice(dev) != hipSuccess) {
@@ -381,6 +403,15 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
     s->device = dev;
     if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         s->cus = 1;
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+                hipSuccess && v > 0)
+            s->lds_per_cu = (uint32_t)v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            s->lds_per_block = (uint32_t)v;
+    }
     if (p->use_hip_stream && p->hip_stream) {
         s->stream = (hipStream_t)p->hip_stream;
     } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
@@ -445,14 +476,6 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     ExtShape shape;
     if (!qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), knobs, &shape))
         return EXT_ENOTSUP;
-    // latency: a shape with more work items per pair than one 256-lane group
-    // has lanes runs on 1024-lane groups (one round instead of several)
-    if (!s->params.threads && (uint64_t)shape.np * shape.groups > (uint64_t)qext::kThreads) {
-        qext::PlanKnobs wide = knobs;
-        wide.threads = qext::kMaxThreads;
-        ExtShape ws;
-        if (qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), wide, &ws)) shape = ws;
-    }
     const uint64_t nb = n_bits / 8, qb = m_bits / 8;
     if (qb > s->cfg.outbox_bytes) return EXT_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);

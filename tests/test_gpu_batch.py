@@ -159,7 +159,8 @@ def test_autotuned_plan_is_bit_identical(dev):
 
 def test_wide_workgroups_large_field(dev):
     """1024-lane work-groups (one round for the 729 items of an m = 16384
-    pair) give the oracle's bytes, in the plain form and in a batch."""
+    pair) give the oracle's bytes in the plain form (the served-form tests
+    cover the persistent kernel, which uses them for m = 16384 channels)."""
     import torch
 
     w = inputs.plain_workload(65536, 16384, 3, 31, 32, kind="ar1")
