@@ -156,7 +156,8 @@ def batched_leg(dev, stream, steps: int, warmup: int):
 
 def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
                                                              "plain_at_1/16_load"),
-               wg_per_cu: int = 0, max_inflight: int = 0):
+               wg_per_cu: int = 0, max_inflight: int = 0, split_pairs: int = -1,
+               producers: int = 4):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
     1..64 blocks, 64 Gbps aggregate raw input; three quarters i.i.d. Gaussian
     with n from 2048..32768, one quarter AR(1) with n = 65536.  Served form
@@ -194,9 +195,11 @@ def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
         log("served leg: %s, %.1f Gbps raw, %.0f s window" % (name, r * 8 / 1e9, duration_s))
         res, _ = binding.simulate(chans, mode=mode, raw_bytes_per_s=r, warmup_s=warmup_s,
                                   duration_s=duration_s, grace_s=2.0, max_lag_s=lag, seed=4,
+                                  producer_threads=producers,
                                   config=binding.server_config(
                                       wg_per_cu=wg_per_cu,
-                                      **({"max_inflight": max_inflight} if max_inflight else {})))
+                                      **({"max_inflight": max_inflight} if max_inflight else {}),
+                                      **({"split_pairs": split_pairs} if split_pairs >= 0 else {})))
         log("served leg: %s: %s" % (name, json.dumps(res)))
         out[name] = {
             "output_gbps": round(res["out_gbps"], 3),
@@ -209,6 +212,9 @@ def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
             "blocks_missing": int(res["blocks_missing"]),
             "eagain": int(res["eagain"]),
             "max_submit_lag_ms": round(res["max_submit_lag_us"] / 1e3, 3),
+            "p99_submit_lag_ms": round(res["submit_lag_p99_us"] / 1e3, 4),
+            "p50_service_ms": round(res["service_p50_us"] / 1e3, 4),
+            "p99_service_ms": round(res["service_p99_us"] / 1e3, 4),
             "chunks_submitted": int(res["chunks"]),
             "cycles": int(res["cycles"]),
             "mean_cycle_ms": round(res["mean_cycle_us"] / 1e3, 4),
@@ -231,6 +237,11 @@ def main():
                     help="comma-separated subset of the served-leg runs")
     ap.add_argument("--serve-inflight", type=int, default=0,
                     help="server cycles queued on the GPU at once (0 = library default)")
+    ap.add_argument("--serve-split", type=int, default=-1,
+                    help="server split_pairs (1: slice large pairs over work-groups, 0: whole "
+                         "pairs; -1 = library default)")
+    ap.add_argument("--serve-producers", type=int, default=4,
+                    help="load generator threads submitting chunks")
     ap.add_argument("--serve-wg-per-cu", type=int, default=0,
                     help="persistent work-groups per CU in a served cycle (0 = as many as fit)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -316,7 +327,8 @@ def main():
     if not args.no_served:
         served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
                             modes=args.serve_modes.split(","), wg_per_cu=args.serve_wg_per_cu,
-                            max_inflight=args.serve_inflight)
+                            max_inflight=args.serve_inflight, split_pairs=args.serve_split,
+                            producers=args.serve_producers)
 
     sec = ms * 1e-3
     out_gbps = N_PAIRS * M_BITS / sec / 1e9

@@ -250,14 +250,25 @@ typedef struct {
     uint32_t max_inflight;  /* cycles queued on the GPU at once, 1..3: 1 gives the lowest
                                latency at light load, more overlap the host's launch work
                                with the GPU at heavy load (default 1) */
-    uint32_t reserved;
+    uint32_t split_pairs;   /* 1: plan channels for latency: one base product per lane
+                               item, and a pair with more items than a work-group has
+                               lanes is split over several work-groups whose partial sums
+                               a combine step adds and reduces; 0: whole pairs per
+                               work-group, with the plain form's plan (default 1) */
 } ext_server_config;
 typedef struct {
     uint64_t cycles, tiles, pairs, bytes_in;
     uint64_t eagain_ring;   /* submissions refused: channel ring full */
     uint64_t eagain_stage;  /* submissions refused: cycle staging full */
     uint64_t gpu_busy_ns;   /* sum over cycles of launch-to-harvest time */
-    uint64_t reserved[5];
+    uint64_t split_pairs;   /* pairs computed as slices over several work-groups */
+    uint64_t build_ns;      /* host time spent building cycles (tiles, metadata) */
+    uint64_t launch_ns;     /* host time spent queueing cycles' kernels and events */
+    uint64_t max_cycle_ns;  /* longest launch-to-harvest time of a cycle */
+    uint64_t gpu_ns;        /* sum over cycles of the GPU time from the first kernel's
+                               start to the end of the last */
+    uint64_t stage_ns;      /* of which: staging the cycle's input and metadata */
+    uint64_t extract_ns;    /* of which: the extraction launches (the rest: combine) */
 } ext_server_stats;
 
 void ext_server_config_init(ext_server_config *c);
@@ -330,7 +341,18 @@ typedef struct {
     uint64_t eagain_ring;           /* served mode: refusals because a channel ring was full */
     uint64_t eagain_stage;          /* served mode: refusals because a cycle was full */
     double mean_cycle_us;           /* served mode: mean launch-to-harvest time of a cycle */
-    uint64_t reserved[3];
+    double submit_lag_p99_us;       /* chunks arrived in the window: p99 of the time from the
+                                       scheduled arrival to the return of their submission */
+    double service_p50_us, service_p99_us;  /* blocks arrived in the window: from the return
+                                       of the submission that completed them to the poll */
+    double ready_p50_us, ready_p99_us;  /* served mode, same blocks: from that return to the
+                                       moment the server had their output in host memory */
+    double mean_build_us;           /* served mode: host time to build a cycle, mean */
+    double mean_launch_us;          /* served mode: host time to queue a cycle, mean */
+    double max_cycle_us;            /* served mode: longest launch-to-harvest time */
+    double mean_gpu_us;             /* served mode: GPU time of a cycle, mean */
+    double mean_tiles;              /* served mode: work-group tiles per cycle, mean */
+    double mean_stage_us, mean_extract_us;  /* served mode: parts of mean_gpu_us */
 } ext_sim_result;
 /* capture_len (may be NULL): per channel, bytes written to capture. */
 int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t *capture_len);

@@ -89,14 +89,15 @@ class ServerConfig(ctypes.Structure):
         ("wg_per_cu", ctypes.c_uint32),
         ("ring_bytes", ctypes.c_uint64),
         ("max_inflight", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("split_pairs", ctypes.c_uint32),
     ]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("cycles", "tiles", "pairs", "bytes_in", "eagain_ring", "eagain_stage",
-                 "gpu_busy_ns")] + [("reserved", ctypes.c_uint64 * 5)]
+                 "gpu_busy_ns", "split_pairs", "build_ns", "launch_ns", "max_cycle_ns",
+                 "gpu_ns", "stage_ns", "extract_ns")]
 
 
 class SimConfig(ctypes.Structure):
@@ -133,7 +134,13 @@ class SimResult(ctypes.Structure):
                                                "eagain")] + \
                [("max_submit_lag_us", ctypes.c_double), ("cycles", ctypes.c_uint64),
                 ("eagain_ring", ctypes.c_uint64), ("eagain_stage", ctypes.c_uint64),
-                ("mean_cycle_us", ctypes.c_double), ("reserved", ctypes.c_uint64 * 3)]
+                ("mean_cycle_us", ctypes.c_double), ("submit_lag_p99_us", ctypes.c_double),
+                ("service_p50_us", ctypes.c_double), ("service_p99_us", ctypes.c_double),
+                ("ready_p50_us", ctypes.c_double), ("ready_p99_us", ctypes.c_double),
+                ("mean_build_us", ctypes.c_double), ("mean_launch_us", ctypes.c_double),
+                ("max_cycle_us", ctypes.c_double), ("mean_gpu_us", ctypes.c_double),
+                ("mean_tiles", ctypes.c_double), ("mean_stage_us", ctypes.c_double),
+                ("mean_extract_us", ctypes.c_double)]
 
 
 _lib = None
@@ -411,7 +418,10 @@ def server_config(**kw) -> ServerConfig:
     lib = load()
     c = ServerConfig()
     lib.ext_server_config_init(ctypes.byref(c))
+    names = {f for f, _ in ServerConfig._fields_}
     for k, v in kw.items():
+        if k not in names or k == "reserved":
+            raise TypeError("ext_server_config has no field %r" % k)
         setattr(c, k, v)
     return c
 

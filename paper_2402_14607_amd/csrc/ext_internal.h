@@ -58,11 +58,26 @@ struct BatchStream {
 
 // One work-group's worth of a batch: npw consecutive pairs of a stream,
 // whose blocks start at pair slot in_pair0 of the stream's x and y, and
-// whose outputs go to word out_word0 of the stream's out.
+// whose outputs go to word out_word0 of the stream's out.  When n_items is
+// nonzero the tile is one slice of the single pair in_pair0: its items
+// [item0, item0 + n_items) in element-major order, whose partial unreduced
+// sum goes to word out_word0 of the launch's part buffer instead.
 struct BatchTile {
     uint32_t stream;
     uint32_t npw;
     uint64_t in_pair0;
+    uint64_t out_word0;
+    uint32_t item0;
+    uint32_t n_items;
+};
+
+// One sliced pair to finish: XOR n_parts consecutive parts (2qw words each)
+// starting at word part_word0 of the part buffer, reduce, and store the
+// output at word out_word0 of the stream's out.
+struct CombineJob {
+    uint32_t stream;
+    uint32_t n_parts;
+    uint64_t part_word0;
     uint64_t out_word0;
 };
 
@@ -100,10 +115,20 @@ hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n
                         const void* meta_src, void* meta_dst, uint32_t meta_bytes, uint32_t* heads,
                         uint32_t n_heads, hipStream_t stream);
 
-// As launch_batch without the queue-head reset (the caller clears the head).
+// As launch_batch without the queue-head reset (the caller clears the head);
+// part (device) receives the partial sums of sliced tiles (may be null when
+// the launch has none).
 hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
                                 const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
-                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream);
+                                uint32_t* part, uint32_t grid, uint32_t lds_bytes,
+                                hipStream_t stream);
+
+// Queue the combine step of n_jobs sliced pairs (after the batch launches
+// that wrote their parts, on the same stream).  lds_bytes: (2qw + dn) * 4 of
+// the largest shape among the jobs.  streams, jobs, part: device memory.
+hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, uint32_t n_jobs,
+                          const uint32_t* part, uint32_t grid, uint32_t lds_bytes,
+                          hipStream_t stream);
 
 // Resident work-groups per CU of the batched kernel at this LDS size.
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu);

@@ -110,87 +110,50 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
     }
 }
 
-// One work-group's share: npw consecutive block pairs of one stream with
-// shape sh (npw <= sh.ppw); xg, yg point at the first pair's blocks and out at
-// its output.  lds holds sh.lds_words words.  Ends after the last global
-// store, without a barrier.
+// Karatsuba path of sub-product p: one base-3 digit per level, 0 = low
+// halves, 1 = high halves, 2 = sum of halves.  Bit l of a mask describes the
+// level whose halves are B * 2^l bits (l = 0 is the lowest level).
+__device__ __forceinline__ void path_masks(uint32_t p, uint32_t levels, uint32_t& hi_mask,
+                                           uint32_t& mid_mask) {
+    uint32_t hm = 0, mm = 0, v = p;
+    for (uint32_t l = 0; l < levels; ++l) {
+        const uint32_t d = v % 3u;
+        v /= 3u;
+        hm |= (uint32_t)(d == 1u) << l;
+        mm |= (uint32_t)(d == 2u) << l;
+    }
+    hi_mask = hm;
+    mid_mask = mm;
+}
+
+// XOR a sub-product (2BW words) into the unreduced sum at cdst (LDS): a
+// low-halves product lands at offsets {0, h}, a high-halves product at
+// {h, 2h}, a sum-of-halves product at {h}, h = half size of that level; the
+// offsets of all levels add up.
 template <int BW>
-__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ xg,
-                                              const uint32_t* __restrict__ yg,
-                                              uint32_t* __restrict__ out, uint32_t npw,
-                                              uint32_t* lds) {
+__device__ __forceinline__ void scatter_acc(const uint32_t (&acc)[2 * BW], uint32_t hi_mask,
+                                            uint32_t mid_mask, uint32_t lmask, uint32_t* cdst) {
+    const uint32_t hm = hi_mask | mid_mask;
+    const uint32_t lh = lmask & ~mid_mask;
+    uint32_t sub = lh;
+    for (;;) {
+        const uint32_t off = BW * (hm + sub);
+#pragma unroll
+        for (int w = 0; w < 2 * BW; ++w) atomicXor(cdst + off + w, acc[w]);
+        if (sub == 0) break;
+        sub = (sub - 1u) & lh;
+    }
+}
+
+// Reduce the npw unreduced sums at cs (2qw words each, complete and visible
+// to the whole work-group) modulo P and store the q-bit results at out
+// (qw words per pair); ds holds npw * dn words of scratch.  Ends after the
+// last global store, without a barrier.
+__device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t* cs, uint32_t* ds,
+                                             uint32_t* __restrict__ out, uint32_t npw) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t nt = blockDim.x;  // sh.threads lanes
-    const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
-    uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
-    uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
-    uint32_t* cs = ys + (sh.stage ? sh.ppw * nw : 0); // [ppw][2qw]  unreduced sums
-    uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
-
-    for (uint32_t i = tid; i < npw * cw; i += nt) cs[i] = 0;
-    if (sh.stage) {
-        for (uint32_t i = tid; i < npw * nw; i += nt) {
-            xs[i] = xg[i];
-            ys[i] = yg[i];
-        }
-    }
-    __syncthreads();
-
-    // ---- sub-products ---------------------------------------------------
-    const uint32_t per_pair = sh.np * sh.groups;
-    const uint32_t items = npw * per_pair;
-    const uint32_t lmask = (1u << sh.levels) - 1u;
-    for (uint32_t it = tid; it < items; it += nt) {
-        const uint32_t j = it / per_pair;
-        const uint32_t rem = it - j * per_pair;
-        const uint32_t p = rem / sh.groups;
-        const uint32_t g = rem - p * sh.groups;
-        // Karatsuba path of p: one base-3 digit per level, 0 = low halves,
-        // 1 = high halves, 2 = sum of halves.  Bit l of a mask describes the
-        // level whose halves are B * 2^l bits (l = 0 is the lowest level).
-        uint32_t hi_mask = 0, mid_mask = 0;
-        {
-            uint32_t v = p;
-            for (uint32_t l = 0; l < sh.levels; ++l) {  // l = 0 is the lowest level
-                const uint32_t d = v % 3u;
-                v /= 3u;
-                if (d == 1u) hi_mask |= 1u << l;
-                if (d == 2u) mid_mask |= 1u << l;
-            }
-        }
-        uint32_t acc[2 * BW];
-#pragma unroll
-        for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
-
-        for (uint32_t e = g * sh.epg; e < (g + 1) * sh.epg; ++e) {
-            uint32_t xo[BW], yo[BW];
-            if (sh.stage) {  // operands from the LDS copy
-                form_operand<BW>(xo, xs + j * nw + e * qw, hi_mask, mid_mask);
-                form_operand<BW>(yo, ys + j * nw + e * qw, hi_mask, mid_mask);
-            } else {         // straight from HBM (one sub-product per element)
-                form_operand<BW>(xo, xg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
-                form_operand<BW>(yo, yg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
-            }
-            clmul_acc<BW>(xo, yo, acc);
-        }
-
-        // Scatter: a low-halves product lands at offsets {0, h}, a high-halves
-        // product at {h, 2h}, a sum-of-halves product at {h}, h = half size
-        // of that level; the offsets of all levels add up.
-        const uint32_t hm = hi_mask | mid_mask;
-        const uint32_t lh = lmask & ~mid_mask;
-        uint32_t* cdst = cs + j * cw;
-        uint32_t sub = lh;
-        for (;;) {
-            const uint32_t off = BW * (hm + sub);
-#pragma unroll
-            for (int w = 0; w < 2 * BW; ++w) atomicXor(cdst + off + w, acc[w]);
-            if (sub == 0) break;
-            sub = (sub - 1u) & lh;
-        }
-    }
-    __syncthreads();
-
+    const uint32_t nt = blockDim.x;
+    const uint32_t qw = sh.qw, cw = 2 * qw;
     // ---- reduction modulo P ----------------------------------------------
     // C = C_lo + t^q C_hi with deg C_hi <= q-2, and t^q = 1 + sum_e t^e.
     // First pass: C_hi (1 + sum t^e); its part of degree >= q is
@@ -235,6 +198,120 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
     }
 }
 
+// One work-group's share: npw consecutive block pairs of one stream with
+// shape sh (npw <= sh.ppw); xg, yg point at the first pair's blocks and out at
+// its output.  lds holds sh.lds_words words.  Ends after the last global
+// store, without a barrier.
+template <int BW>
+__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ xg,
+                                              const uint32_t* __restrict__ yg,
+                                              uint32_t* __restrict__ out, uint32_t npw,
+                                              uint32_t* lds) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = blockDim.x;  // sh.threads lanes
+    const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
+    uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
+    uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
+    uint32_t* cs = ys + (sh.stage ? sh.ppw * nw : 0); // [ppw][2qw]  unreduced sums
+    uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
+
+    for (uint32_t i = tid; i < npw * cw; i += nt) cs[i] = 0;
+    if (sh.stage) {
+        for (uint32_t i = tid; i < npw * nw; i += nt) {
+            xs[i] = xg[i];
+            ys[i] = yg[i];
+        }
+    }
+    __syncthreads();
+
+    // ---- sub-products ---------------------------------------------------
+    const uint32_t per_pair = sh.np * sh.groups;
+    const uint32_t items = npw * per_pair;
+    const uint32_t lmask = (1u << sh.levels) - 1u;
+    for (uint32_t it = tid; it < items; it += nt) {
+        const uint32_t j = it / per_pair;
+        const uint32_t rem = it - j * per_pair;
+        const uint32_t p = rem / sh.groups;
+        const uint32_t g = rem - p * sh.groups;
+        uint32_t hi_mask, mid_mask;
+        path_masks(p, sh.levels, hi_mask, mid_mask);
+        uint32_t acc[2 * BW];
+#pragma unroll
+        for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
+
+        for (uint32_t e = g * sh.epg; e < (g + 1) * sh.epg; ++e) {
+            uint32_t xo[BW], yo[BW];
+            if (sh.stage) {  // operands from the LDS copy
+                form_operand<BW>(xo, xs + j * nw + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(yo, ys + j * nw + e * qw, hi_mask, mid_mask);
+            } else {         // straight from HBM (one sub-product per element)
+                form_operand<BW>(xo, xg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(yo, yg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
+            }
+            clmul_acc<BW>(xo, yo, acc);
+        }
+
+        scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs + j * cw);
+    }
+    __syncthreads();
+    reduce_store(sh, cs, ds, out, npw);
+}
+
+// One slice of one block pair, for pairs with more sub-products than a
+// work-group has lanes: items [item0, item0 + n_items) of the pair's
+// n_e * 3^L (element, sub-product) items in element-major order, one base
+// product each.  The slice's part of the unreduced sum (2qw words, the other
+// slices' parts XOR to the rest) is stored at part; combine_kernel adds the
+// parts and reduces.  Only the elements the slice touches are staged.  Ends
+// after the last global store, without a barrier.
+template <int BW>
+__device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t* __restrict__ xg,
+                                              const uint32_t* __restrict__ yg,
+                                              uint32_t* __restrict__ part, uint32_t item0,
+                                              uint32_t n_items, uint32_t* lds) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = blockDim.x;
+    const uint32_t qw = sh.qw, cw = 2 * qw;
+    const uint32_t e0 = item0 / sh.np;
+    const uint32_t sw = ((item0 + n_items - 1) / sh.np - e0 + 1) * qw;  // staged words per side
+    uint32_t* xs = lds;                          // [sw] (staged X elements)
+    uint32_t* ys = xs + (sh.stage ? sw : 0);     // [sw] (staged Y elements)
+    uint32_t* cs = ys + (sh.stage ? sw : 0);     // [2qw] partial unreduced sum
+
+    for (uint32_t i = tid; i < cw; i += nt) cs[i] = 0;
+    if (sh.stage) {
+        for (uint32_t i = tid; i < sw; i += nt) {
+            xs[i] = xg[e0 * qw + i];
+            ys[i] = yg[e0 * qw + i];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t lmask = (1u << sh.levels) - 1u;
+    for (uint32_t it = tid; it < n_items; it += nt) {
+        const uint32_t gi = item0 + it;
+        const uint32_t e = gi / sh.np;
+        const uint32_t p = gi - e * sh.np;
+        uint32_t hi_mask, mid_mask;
+        path_masks(p, sh.levels, hi_mask, mid_mask);
+        uint32_t acc[2 * BW];
+#pragma unroll
+        for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
+        uint32_t xo[BW], yo[BW];
+        if (sh.stage) {
+            form_operand<BW>(xo, xs + (e - e0) * qw, hi_mask, mid_mask);
+            form_operand<BW>(yo, ys + (e - e0) * qw, hi_mask, mid_mask);
+        } else {
+            form_operand<BW>(xo, xg + e * qw, hi_mask, mid_mask);
+            form_operand<BW>(yo, yg + e * qw, hi_mask, mid_mask);
+        }
+        clmul_acc<BW>(xo, yo, acc);
+        scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cw; i += nt) part[i] = cs[i];
+}
+
 // Plain form: work-group g takes pairs [g*ppw, (g+1)*ppw) of one stream.
 template <int BW>
 __global__ void __launch_bounds__(kMaxThreads)
@@ -249,13 +326,13 @@ ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
 }
 
 // Batched form: a persistent grid drains a device work queue of tiles
-// (stream, first pair, pair count) shared by many streams of different
-// shapes.  Each work-group takes the next tile with one atomic add on the
+// (stream, first pair, pair count; or one slice of one pair) shared by many
+// streams of different shapes.  Each work-group takes the next tile with one atomic add on the
 // queue head and stops once the head passes n_tiles, so every wave exits.
 template <int BW>
 __global__ void __launch_bounds__(kMaxThreads)
 ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __restrict__ tiles,
-                 uint32_t n_tiles, uint32_t* __restrict__ head) {
+                 uint32_t n_tiles, uint32_t* __restrict__ head, uint32_t* __restrict__ part) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t next;
     for (;;) {
@@ -266,9 +343,69 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         const BatchTile tile = tiles[t];
         const BatchStream& st = streams[tile.stream];
         const ExtShape& sh = st.shape;  // read in place (a local copy would go to scratch)
-        extract_group<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
-                          st.out + tile.out_word0, tile.npw, lds);
+        if (tile.n_items)  // one slice of one pair; out_word0 locates its part
+            extract_slice<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
+                              part + tile.out_word0, tile.item0, tile.n_items, lds);
+        else
+            extract_group<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
+                              st.out + tile.out_word0, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
+    }
+}
+
+// Served cycles with sliced pairs: work-group b takes jobs b, b + grid, ...;
+// a job XORs the n_parts consecutive parts (2qw words each) of one pair,
+// reduces the sum modulo P and stores the pair's output.  lds holds
+// 2qw + dn words of the largest shape among the jobs.
+__global__ void __launch_bounds__(kThreads)
+combine_kernel(const BatchStream* __restrict__ streams, const CombineJob* __restrict__ jobs,
+               uint32_t n_jobs, const uint32_t* __restrict__ part) {
+    extern __shared__ uint32_t lds[];
+    for (uint32_t jb = blockIdx.x; jb < n_jobs; jb += gridDim.x) {
+        const CombineJob job = jobs[jb];
+        const BatchStream& st = streams[job.stream];
+        const ExtShape& sh = st.shape;
+        const uint32_t cw = 2 * sh.qw;
+        const uint32_t* src = part + job.part_word0;
+        if ((cw & 3u) == 0 && (job.part_word0 & 3u) == 0) {
+            // 16-byte loads, four parts' loads in flight before they are used
+            const uint4* s4 = reinterpret_cast<const uint4*>(src);
+            const uint32_t c4 = cw / 4;
+            for (uint32_t i = threadIdx.x; i < c4; i += blockDim.x) {
+                uint4 v = s4[i];
+                uint32_t k = 1;
+                for (; k + 4 <= job.n_parts; k += 4) {
+                    const uint4 a = s4[(uint64_t)k * c4 + i];
+                    const uint4 b = s4[(uint64_t)(k + 1) * c4 + i];
+                    const uint4 c = s4[(uint64_t)(k + 2) * c4 + i];
+                    const uint4 d = s4[(uint64_t)(k + 3) * c4 + i];
+                    v.x ^= a.x ^ b.x ^ c.x ^ d.x;
+                    v.y ^= a.y ^ b.y ^ c.y ^ d.y;
+                    v.z ^= a.z ^ b.z ^ c.z ^ d.z;
+                    v.w ^= a.w ^ b.w ^ c.w ^ d.w;
+                }
+                for (; k < job.n_parts; ++k) {
+                    const uint4 a = s4[(uint64_t)k * c4 + i];
+                    v.x ^= a.x;
+                    v.y ^= a.y;
+                    v.z ^= a.z;
+                    v.w ^= a.w;
+                }
+                lds[4 * i + 0] = v.x;
+                lds[4 * i + 1] = v.y;
+                lds[4 * i + 2] = v.z;
+                lds[4 * i + 3] = v.w;
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < cw; i += blockDim.x) {
+                uint32_t v = 0;
+                for (uint32_t k = 0; k < job.n_parts; ++k) v ^= src[(uint64_t)k * cw + i];
+                lds[i] = v;
+            }
+        }
+        __syncthreads();
+        reduce_store(sh, lds, lds + cw, st.out + job.out_word0, 1);
+        __syncthreads();  // lds is reused by the next job
     }
 }
 
@@ -291,9 +428,23 @@ stage_kernel(const uint8_t* __restrict__ src, const ScatterDesc* __restrict__ de
         const uint8_t* s = src + sd.src_off;
         uint8_t* t = sd.dst;
         if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 15u) == 0) {
+            // four 16-byte loads in flight per lane before their stores (a
+            // 16 KiB piece is one round trip over the bus)
             const uint4* s16 = reinterpret_cast<const uint4*>(s);
             uint4* t16 = reinterpret_cast<uint4*>(t);
-            for (uint32_t i = threadIdx.x; i < sd.len / 16; i += kThreads) t16[i] = s16[i];
+            const uint32_t n16 = sd.len / 16;
+            uint32_t i = threadIdx.x;
+            for (; i + 3 * kThreads < n16; i += 4 * kThreads) {
+                const uint4 a = s16[i];
+                const uint4 b = s16[i + kThreads];
+                const uint4 c = s16[i + 2 * kThreads];
+                const uint4 d = s16[i + 3 * kThreads];
+                t16[i] = a;
+                t16[i + kThreads] = b;
+                t16[i + 2 * kThreads] = c;
+                t16[i + 3 * kThreads] = d;
+            }
+            for (; i < n16; i += kThreads) t16[i] = s16[i];
         } else if ((((uintptr_t)s | (uintptr_t)t | sd.len) & 3u) == 0) {
             const uint32_t* s4 = reinterpret_cast<const uint32_t*>(s);
             uint32_t* t4 = reinterpret_cast<uint32_t*>(t);
@@ -326,16 +477,17 @@ hipError_t launch_batch_bw(uint32_t threads, const BatchStream* streams, const B
                            hipStream_t stream) {
     hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
     hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
-                       streams, tiles, n_tiles, head);
+                       streams, tiles, n_tiles, head, static_cast<uint32_t*>(nullptr));
     return hipGetLastError();
 }
 
 template <int BW>
 hipError_t launch_batch_only_bw(uint32_t threads, const BatchStream* streams,
                                 const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
-                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream) {
+                                uint32_t* part, uint32_t grid, uint32_t lds_bytes,
+                                hipStream_t stream) {
     hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
-                       streams, tiles, n_tiles, head);
+                       streams, tiles, n_tiles, head, part);
     return hipGetLastError();
 }
 
@@ -389,11 +541,22 @@ hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n
 
 hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
                                 const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
-                                uint32_t grid, uint32_t lds_bytes, hipStream_t stream) {
+                                uint32_t* part, uint32_t grid, uint32_t lds_bytes,
+                                hipStream_t stream) {
     if (n_tiles == 0) return hipSuccess;
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64) return hipErrorInvalidValue;
-    QEXT_BW_CASES(launch_batch_only_bw, threads, streams, tiles, n_tiles, head, grid, lds_bytes,
-                  stream)
+    QEXT_BW_CASES(launch_batch_only_bw, threads, streams, tiles, n_tiles, head, part, grid,
+                  lds_bytes, stream)
+}
+
+hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, uint32_t n_jobs,
+                          const uint32_t* part, uint32_t grid, uint32_t lds_bytes,
+                          hipStream_t stream) {
+    if (n_jobs == 0) return hipSuccess;
+    if (grid == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(combine_kernel, dim3(grid), dim3(kThreads), lds_bytes, stream, streams, jobs,
+                       n_jobs, part);
+    return hipGetLastError();
 }
 
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {

@@ -40,6 +40,7 @@
 
 using qext::BatchStream;
 using qext::BatchTile;
+using qext::CombineJob;
 using qext::ExtShape;
 using qext::ScatterDesc;
 
@@ -58,6 +59,8 @@ struct Channel {
     uint64_t n_bits = 0, nb = 0, qb = 0;
     uint32_t m_bits = 0;
     ExtShape shape{};
+    uint32_t slices = 1;          // work-groups per pair (> 1: split into slices)
+    uint32_t slice_items = 0;     // items per slice (the last one may hold fewer)
     uint64_t R = 0;               // ring blocks
     uint8_t* ring_x = nullptr;    // device, R * nb bytes
     uint8_t* ring_y = nullptr;
@@ -90,7 +93,11 @@ struct Slot {
     uint8_t* h_in = nullptr;   // pinned, read by the GPU: data | descs | streams | tiles
     uint8_t* d_in = nullptr;   // device: streams | tiles | queue heads (same offsets)
     uint8_t* h_out = nullptr;  // pinned outbox, written by the GPU
+    uint32_t* d_part = nullptr; // device: partial sums of sliced pairs
     hipEvent_t done = nullptr; // the cycle's outputs are in h_out
+    hipEvent_t start = nullptr; // before the cycle's first kernel (timing)
+    hipEvent_t staged = nullptr;    // after the staging kernel (timing)
+    hipEvent_t computed = nullptr;  // after the extraction launches (timing)
     uint64_t data_used = 0;
     uint32_t n_descs = 0;
     int pending = 0;            // submissions still copying into h_in
@@ -98,9 +105,16 @@ struct Slot {
     std::vector<Range> ranges;
     std::vector<Group> groups;
     uint32_t n_tiles = 0;
+    uint32_t n_jobs = 0;
+    uint32_t combine_lds = 0;
     uint64_t out_bytes = 0;
     uint64_t launched_ns = 0;
+    uint64_t table_version = 0;  // server table version last sent to this slot's device copy
 };
+
+// Device memory per slot for the partial sums of sliced pairs (a cycle takes
+// no more sliced pairs than fit; the rest wait for the next cycle).
+constexpr uint64_t kPartBytes = 32ull << 20;
 
 }  // namespace
 
@@ -116,6 +130,7 @@ struct ext_server {
     std::vector<Channel> ch;
     // slot layout
     size_t off_desc = 0, off_streams = 0, off_tiles = 0, off_heads = 0, in_bytes = 0;
+    uint32_t max_jobs = 0;  // combine jobs per cycle (each has at least two tiles)
     static constexpr int kSlots = 4;  // one filling, up to kMaxInflight in flight
     static constexpr uint32_t kMaxInflight = kSlots - 1;
     Slot slots[kSlots];
@@ -130,6 +145,8 @@ struct ext_server {
     bool stop = false;
     int sticky = EXT_OK;
     ext_server_stats stats{};
+    std::vector<CombineJob> jobs_tmp;  // launch_cycle's job list (kept to reuse its storage)
+    uint64_t table_version = 1;        // bumped whenever a channel opens or closes
 };
 
 namespace {
@@ -139,7 +156,11 @@ void server_free(ext_server* s) {
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
         (void)hipFree(sl.d_in);
+        (void)hipFree(sl.d_part);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.start) (void)hipEventDestroy(sl.start);
+        if (sl.staged) (void)hipEventDestroy(sl.staged);
+        if (sl.computed) (void)hipEventDestroy(sl.computed);
     }
     for (Channel& c : s->ch) {
         (void)hipFree(c.ring_x);
@@ -170,6 +191,14 @@ void harvest(ext_server* s) {
             c.completed += r.n;
         }
         s->stats.gpu_busy_ns += t - sl.launched_ns;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess)
+            s->stats.gpu_ns += (uint64_t)(ms * 1e6f);
+        if (hipEventElapsedTime(&ms, sl.start, sl.staged) == hipSuccess)
+            s->stats.stage_ns += (uint64_t)(ms * 1e6f);
+        if (hipEventElapsedTime(&ms, sl.staged, sl.computed) == hipSuccess)
+            s->stats.extract_ns += (uint64_t)(ms * 1e6f);
+        s->stats.max_cycle_ns = std::max(s->stats.max_cycle_ns, t - sl.launched_ns);
         if (s->ready_waiters && !sl.ranges.empty()) s->ready_cv.notify_all();
         sl.ranges.clear();
         sl.data_used = 0;
@@ -191,6 +220,7 @@ int occupancy(ext_server* s, uint32_t bw, uint32_t threads, uint32_t lds) {
 // Take the filling slot, add every ready block pair, and queue the cycle
 // (lock held on entry and exit; released around the HIP calls).
 int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
+    const uint64_t t_enter = now_ns();
     const int idx = s->filling;
     Slot& sl = s->slots[idx];
     // the next filling slot: one that is neither in flight nor this one
@@ -210,32 +240,61 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     }
     sl.resv.clear();
 
-    // tiles of every channel's ready pairs, grouped by base size
+    // tiles of every channel's ready pairs, grouped by base size; a sliced
+    // pair takes `slices` tiles, room for their parts and one combine job
     std::map<std::pair<uint32_t, uint32_t>, std::vector<BatchTile>> by_bw;  // (bw, threads)
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> lds_of;
-    uint64_t out_off = 0;
-    uint32_t n_tiles = 0;
+    std::vector<CombineJob>& jobs = s->jobs_tmp;
+    jobs.clear();
+    uint64_t out_off = 0, part_words = 0;
+    const uint64_t part_cap = kPartBytes / 4;
+    uint32_t n_tiles = 0, combine_lds = 0;
     sl.ranges.clear();
     for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
         Channel& c = s->ch[ci];
         if (!c.open) continue;
         uint64_t ready = std::min(c.x_ok, c.y_ok) / c.nb - c.launched;
+        const uint64_t cw = 2ull * c.shape.qw;
         while (ready) {
             const uint64_t slot0 = c.launched % c.R;
             uint64_t k = std::min<uint64_t>(ready, c.R - slot0);            // no ring wrap
             k = std::min<uint64_t>(k, (s->cfg.outbox_bytes - out_off) / c.qb);  // outbox room
-            const uint64_t tiles_needed = (k + c.shape.ppw - 1) / c.shape.ppw;
-            if (n_tiles + tiles_needed > s->cfg.max_tiles)
-                k = std::min<uint64_t>(k, (uint64_t)(s->cfg.max_tiles - n_tiles) * c.shape.ppw);
+            if (c.slices > 1) {
+                k = std::min<uint64_t>(k, (s->cfg.max_tiles - n_tiles) / c.slices);
+                k = std::min<uint64_t>(k, s->max_jobs - (uint32_t)jobs.size());
+                const uint64_t pw = align_up(part_words, 4);
+                k = std::min<uint64_t>(k, pw < part_cap ? (part_cap - pw) / (c.slices * cw) : 0);
+            } else {
+                const uint64_t tiles_needed = (k + c.shape.ppw - 1) / c.shape.ppw;
+                if (n_tiles + tiles_needed > s->cfg.max_tiles)
+                    k = std::min<uint64_t>(k, (uint64_t)(s->cfg.max_tiles - n_tiles) * c.shape.ppw);
+            }
             if (k == 0) break;
             sl.ranges.push_back(Range{ci, (uint32_t)k, c.launched, out_off});
             const auto key = std::make_pair(c.shape.bw, c.shape.threads);
             auto& vec = by_bw[key];
             lds_of[key] = std::max(lds_of[key], c.shape.lds_words * 4);
-            for (uint64_t p = 0; p < k; p += c.shape.ppw) {
-                const uint32_t n = (uint32_t)std::min<uint64_t>(c.shape.ppw, k - p);
-                vec.push_back(BatchTile{ci, n, slot0 + p, (out_off + p * c.qb) / 4});
-                ++n_tiles;
+            if (c.slices > 1) {
+                const uint32_t items = c.shape.np * c.shape.n_e;
+                part_words = align_up(part_words, 4);  // 16-byte aligned parts
+                for (uint64_t p = 0; p < k; ++p) {
+                    jobs.push_back(CombineJob{ci, c.slices, part_words, (out_off + p * c.qb) / 4});
+                    for (uint32_t sidx = 0; sidx < c.slices; ++sidx) {
+                        const uint32_t i0 = sidx * c.slice_items;
+                        const uint32_t ni = std::min(c.slice_items, items - i0);
+                        vec.push_back(BatchTile{ci, 1, slot0 + p, part_words, i0, ni});
+                        part_words += cw;
+                        ++n_tiles;
+                    }
+                }
+                combine_lds = std::max<uint32_t>(combine_lds, (uint32_t)(cw + c.shape.dn) * 4);
+                s->stats.split_pairs += k;
+            } else {
+                for (uint64_t p = 0; p < k; p += c.shape.ppw) {
+                    const uint32_t n = (uint32_t)std::min<uint64_t>(c.shape.ppw, k - p);
+                    vec.push_back(BatchTile{ci, n, slot0 + p, (out_off + p * c.qb) / 4, 0, 0});
+                    ++n_tiles;
+                }
             }
             out_off += k * c.qb;
             c.launched += k;
@@ -244,12 +303,17 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     }
     if (sl.data_used == 0 && n_tiles == 0) return EXT_OK;  // (the slot stays free)
 
-    // metadata into the slot's pinned area
-    BatchStream* hs = reinterpret_cast<BatchStream*>(sl.h_in + s->off_streams);
-    for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
-        const Channel& c = s->ch[ci];
-        hs[ci] = BatchStream{(const uint32_t*)c.ring_x, (const uint32_t*)c.ring_y,
-                             (uint32_t*)sl.h_out, 0, c.shape};
+    // metadata into the slot's pinned area; the stream table only when a
+    // channel opened or closed since this slot last sent it
+    const bool send_table = sl.table_version != s->table_version;
+    if (send_table) {
+        BatchStream* hs = reinterpret_cast<BatchStream*>(sl.h_in + s->off_streams);
+        for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
+            const Channel& c = s->ch[ci];
+            hs[ci] = BatchStream{(const uint32_t*)c.ring_x, (const uint32_t*)c.ring_y,
+                                 (uint32_t*)sl.h_out, 0, c.shape};
+        }
+        sl.table_version = s->table_version;
     }
     BatchTile* ht = reinterpret_cast<BatchTile*>(sl.h_in + s->off_tiles);
     sl.groups.clear();
@@ -259,6 +323,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         // base products per item
         auto cost = [&](const BatchTile& t) {
             const ExtShape& sh = s->ch[t.stream].shape;
+            if (t.n_items) return (uint64_t)(t.n_items + sh.threads - 1) / sh.threads;
             const uint64_t items = (uint64_t)t.npw * sh.np * sh.groups;
             return ((items + sh.threads - 1) / sh.threads) * sh.epg;
         };
@@ -283,7 +348,13 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         t_off += g.n_tiles;
         sl.groups.push_back(g);
     }
+    // combine jobs right after the used tiles (one metadata copy covers both)
+    const size_t off_jobs = align_up(s->off_tiles + (size_t)n_tiles * sizeof(BatchTile), 16);
+    if (!jobs.empty())
+        memcpy(sl.h_in + off_jobs, jobs.data(), jobs.size() * sizeof(CombineJob));
     sl.n_tiles = n_tiles;
+    sl.n_jobs = (uint32_t)jobs.size();
+    sl.combine_lds = combine_lds;
     sl.out_bytes = out_off;
     s->inflight.push_back(idx);
     s->stats.cycles += 1;
@@ -296,22 +367,38 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     // one stream, two kernels: staging (reads the pinned area over the bus),
     // then one persistent launch per base size writing outputs straight into
     // the pinned outbox
+    const size_t meta_off = send_table ? s->off_streams : s->off_tiles;
     const size_t meta_bytes =
-        (s->off_tiles + (size_t)n_tiles * sizeof(BatchTile) - s->off_streams + 15) / 16 * 16;
+        (off_jobs + (size_t)sl.n_jobs * sizeof(CombineJob) - meta_off + 15) / 16 * 16;
     sl.launched_ns = now_ns();
-    e = qext::launch_stage(sl.h_in, reinterpret_cast<const ScatterDesc*>(sl.h_in + s->off_desc),
-                           sl.n_descs, sl.h_in + s->off_streams, sl.d_in + s->off_streams,
+    const uint64_t t_built = sl.launched_ns;
+    e = hipEventRecord(sl.start, s->stream);
+    if (e == hipSuccess)
+        e = qext::launch_stage(sl.h_in, reinterpret_cast<const ScatterDesc*>(sl.h_in + s->off_desc),
+                           sl.n_descs, sl.h_in + meta_off, sl.d_in + meta_off,
                            (uint32_t)meta_bytes, reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads),
                            (uint32_t)sl.groups.size(), s->stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.staged, s->stream);
     for (size_t gi = 0; gi < sl.groups.size() && e == hipSuccess; ++gi) {
         const Group& g = sl.groups[gi];
         e = qext::launch_batch_noreset(
             g.bw, g.threads, reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
             reinterpret_cast<const BatchTile*>(sl.d_in + s->off_tiles) + g.tile_off, g.n_tiles,
-            reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi, g.grid, g.lds_bytes, s->stream);
+            reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi, sl.d_part, g.grid,
+            g.lds_bytes, s->stream);
     }
+    if (e == hipSuccess) e = hipEventRecord(sl.computed, s->stream);
+    if (e == hipSuccess && sl.n_jobs)
+        e = qext::launch_combine(
+            reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
+            reinterpret_cast<const CombineJob*>(sl.d_in + off_jobs), sl.n_jobs, sl.d_part,
+            (uint32_t)std::min<uint64_t>(sl.n_jobs, (uint64_t)s->cus * 4), sl.combine_lds,
+            s->stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, s->stream);
+    const uint64_t t_queued = now_ns();
     lk.lock();
+    s->stats.build_ns += t_built - t_enter;
+    s->stats.launch_ns += t_queued - t_built;
     if (e != hipSuccess) {
         s->sticky = EXT_EDEVICE;
         return EXT_EDEVICE;
@@ -373,6 +460,7 @@ void ext_server_config_init(ext_server_config* c) {
     c->outbox_bytes = 32ull << 20;
     c->max_tiles = 1u << 17;
     c->max_inflight = 1;
+    c->split_pairs = 1;
     c->max_descs = 1u << 16;
     c->poll_us = 0;
 }
@@ -423,8 +511,12 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
     s->off_desc = align_up(cfg->stage_bytes, 256);
     s->off_streams = align_up(s->off_desc + (size_t)cfg->max_descs * sizeof(ScatterDesc), 256);
     s->off_tiles = align_up(s->off_streams + (size_t)cfg->max_channels * sizeof(BatchStream), 256);
-    // (+16: the metadata copy is rounded up to 16 bytes)
-    s->off_heads = align_up(s->off_tiles + (size_t)cfg->max_tiles * sizeof(BatchTile) + 16, 256);
+    s->max_jobs = cfg->max_tiles / 2;
+    // tiles, then (16-byte aligned) combine jobs; +16: the metadata copy is
+    // rounded up to 16 bytes
+    s->off_heads = align_up(s->off_tiles + (size_t)cfg->max_tiles * sizeof(BatchTile) + 16 +
+                                (size_t)s->max_jobs * sizeof(CombineJob) + 16,
+                            256);
     s->in_bytes = s->off_heads + 64 * sizeof(uint32_t);
     bool ok = true;
     for (Slot& sl : s->slots) {
@@ -434,7 +526,11 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
         ok = ok && hipHostMalloc((void**)&sl.h_out, cfg->outbox_bytes, hipHostMallocCoherent) ==
                        hipSuccess;
         ok = ok && hipMalloc((void**)&sl.d_in, s->in_bytes) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.d_part, kPartBytes) == hipSuccess;
+        ok = ok && hipEventCreate(&sl.done) == hipSuccess;
+        ok = ok && hipEventCreate(&sl.start) == hipSuccess;
+        ok = ok && hipEventCreate(&sl.staged) == hipSuccess;
+        ok = ok && hipEventCreate(&sl.computed) == hipSuccess;
     }
     try {
         s->ch.resize(cfg->max_channels);
@@ -469,6 +565,9 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     const uint32_t n_e = (uint32_t)(n_bits / m_bits);
     qext::PlanKnobs knobs{s->params.base_bits / 32, s->params.groups, s->params.pairs_per_group,
                           s->params.threads};
+    // latency plan: one base product per item (every element its own group),
+    // so no lane runs a chain of n_e products
+    if (s->cfg.split_pairs && !knobs.groups && !s->params.autotune) knobs.groups = n_e;
     if (s->params.autotune &&
         qext::autotune_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), s->stream, &knobs,
                              nullptr) != hipSuccess)
@@ -478,6 +577,24 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
         return EXT_ENOTSUP;
     const uint64_t nb = n_bits / 8, qb = m_bits / 8;
     if (qb > s->cfg.outbox_bytes) return EXT_EINVAL;
+    // pairs with more (element, sub-product) items than lanes: split over
+    // ceil(items / threads) work-groups
+    uint32_t slices = 1, slice_items = 0;
+    {
+        const uint64_t items = (uint64_t)shape.np * n_e;
+        if (s->cfg.split_pairs && items > shape.threads) {
+            // per <= threads items per slice; every slice but the last holds
+            // exactly per, the last at least one
+            const uint64_t per = (items + (items + shape.threads - 1) / shape.threads - 1) /
+                                 ((items + shape.threads - 1) / shape.threads);
+            const uint64_t sl = (items + per - 1) / per;
+            if (items > 0xffffffffull || sl * 2ull * shape.qw * 4 > kPartBytes ||
+                sl > s->cfg.max_tiles / 2 || (2ull * shape.qw + shape.dn) * 4 > 65536)
+                return EXT_ENOTSUP;
+            slices = (uint32_t)sl;
+            slice_items = (uint32_t)per;
+        }
+    }
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->sticky) return s->sticky;
     uint32_t ci = 0;
@@ -490,6 +607,8 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     c.nb = nb;
     c.qb = qb;
     c.shape = shape;
+    c.slices = slices;
+    c.slice_items = slice_items;
     c.R = s->cfg.ring_blocks ? s->cfg.ring_blocks
                              : std::max<uint64_t>(128, s->cfg.ring_bytes / nb);
     try {
@@ -507,6 +626,7 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
         return EXT_ENOMEM;
     }
     c.open = true;
+    s->table_version += 1;
     *channel = ci;
     return EXT_OK;
 }
@@ -629,6 +749,7 @@ int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
     const uint64_t full = std::min(c.x_recv, c.y_recv) / c.nb;
     if (dropped_bits) *dropped_bits = 8 * (std::max(c.x_recv, c.y_recv) - full * c.nb);
     c.open = false;
+    s->table_version += 1;
     // bytes of this channel still waiting in the filling cycle must not be
     // scattered into rings that are about to be freed
     {

@@ -44,7 +44,12 @@ struct Event {
 struct Chan {
     std::mutex mu;  // guards the bookkeeping below and, in plain mode, the ext_stream
     uint64_t nb = 0, qb = 0;
-    std::deque<std::pair<uint64_t, uint64_t>> chunks;  // (end block, arrival ns)
+    struct Rec {
+        uint64_t end;        // blocks submitted after this chunk
+        uint64_t arrival;    // scheduled arrival, ns
+        uint64_t submitted;  // when its submission returned, ns
+    };
+    std::deque<Rec> chunks;
     uint64_t submitted = 0;  // blocks submitted (per side)
     uint64_t returned = 0;   // blocks returned by polls
     uint64_t pool_pos = 0;
@@ -145,6 +150,12 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     const uint32_t n_prod = cfg->producer_threads ? cfg->producer_threads : 4;
     std::atomic<uint32_t> producers_left{n_prod};
 
+    // latencies in 1 us bins up to ~1 s (a fixed histogram never reallocates,
+    // so the bookkeeping never stalls the threads that share a channel's lock)
+    constexpr uint64_t kBins = 1u << 20;
+    std::vector<std::vector<uint32_t>> lag_hist(n_prod, std::vector<uint32_t>(kBins, 0));
+    std::vector<uint64_t> lag_n(n_prod, 0);
+
     // producer p submits the chunks of channels c with c % n_prod == p, in time order
     auto produce = [&](uint32_t pid) {
         size_t next = 0;
@@ -187,7 +198,12 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
                 break;
             }
             if (fail.load()) break;
-            const uint64_t lag = now_ns() - target;
+            const uint64_t t_sub = now_ns();
+            const uint64_t lag = t_sub - target;
+            if (target >= win_lo && target < win_hi) {
+                lag_hist[pid][std::min<uint64_t>(lag / 1000, kBins - 1)] += 1;
+                lag_n[pid] += 1;
+            }
             uint64_t prev = max_lag.load();
             while (lag > prev && !max_lag.compare_exchange_weak(prev, lag)) {
             }
@@ -195,7 +211,7 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             {
                 std::lock_guard<std::mutex> g(c.mu);
                 c.submitted += e.k;
-                c.chunks.emplace_back(c.submitted, target);
+                c.chunks.push_back(Chan::Rec{c.submitted, target, t_sub});
             }
             chunks_done++;
         }
@@ -211,11 +227,9 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     std::vector<std::thread> producers;
     for (uint32_t pidx = 0; pidx < n_prod; ++pidx) producers.emplace_back(produce, pidx);
 
-    // latencies of blocks arrived in the window: 1 us bins up to ~1 s, exact
-    // maximum and sum kept aside (a fixed histogram never reallocates, so the
-    // bookkeeping never stalls the threads that share a channel's lock)
-    constexpr uint64_t kBins = 1u << 20;
-    std::vector<uint32_t> hist(kBins, 0);
+    // latencies of blocks arrived in the window (exact maximum and sum kept
+    // aside), and their service part: from the submission's return to the poll
+    std::vector<uint32_t> hist(kBins, 0), svc_hist(kBins, 0), rdy_hist(kBins, 0);
     uint64_t lat_n = 0, lat_max = 0;
     double lat_sum = 0;
     double out_bits = 0, in_bits = 0;
@@ -226,8 +240,9 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
         const uint64_t deadline_after = (uint64_t)(cfg->grace_s * 1e9);
         uint64_t producer_end = 0;
         std::vector<uint32_t> ready(nc);
-        std::vector<uint64_t> arrivals;
+        std::vector<std::pair<uint64_t, uint64_t>> arrivals;  // (arrival, submitted)
         arrivals.reserve(buf.size());
+        std::vector<uint64_t> ready_at(buf.size(), 0);  // served mode: when each block was ready
         for (;;) {
             bool progress = false;
             uint32_t n_ready = nc;
@@ -248,7 +263,8 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
                 int r;
                 const size_t cap = buf.size() / c.qb * c.qb;
                 if (srv) {
-                    r = ext_server_poll(srv, c.sid, buf.data(), cap, &len, nullptr, nullptr);
+                    r = ext_server_poll(srv, c.sid, buf.data(), cap, &len, ready_at.data(),
+                                        nullptr);
                 } else {
                     std::lock_guard<std::mutex> g(c.mu);
                     r = ext_poll(c.st, buf.data(), cap, &len, nullptr);
@@ -267,16 +283,22 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
                     std::lock_guard<std::mutex> g(c.mu);
                     for (uint64_t i = 0; i < nblk; ++i) {
                         const uint64_t blk = c.returned + i;
-                        while (!c.chunks.empty() && c.chunks.front().first <= blk)
+                        while (!c.chunks.empty() && c.chunks.front().end <= blk)
                             c.chunks.pop_front();
                         if (c.chunks.empty()) break;  // cannot happen: outputs follow submissions
-                        arrivals.push_back(c.chunks.front().second);
+                        arrivals.emplace_back(c.chunks.front().arrival, c.chunks.front().submitted);
                     }
                 }
-                for (uint64_t arr : arrivals) {
+                for (size_t ai = 0; ai < arrivals.size(); ++ai) {
+                    const uint64_t arr = arrivals[ai].first, sub = arrivals[ai].second;
                     if (arr < win_lo || arr >= win_hi) continue;
                     const uint64_t l = t - arr;
                     hist[std::min<uint64_t>(l / 1000, kBins - 1)] += 1;
+                    svc_hist[std::min<uint64_t>((t - std::min(t, sub)) / 1000, kBins - 1)] += 1;
+                    if (srv) {
+                        const uint64_t rd = ready_at[ai];
+                        rdy_hist[std::min<uint64_t>((rd - std::min(rd, sub)) / 1000, kBins - 1)] += 1;
+                    }
                     lat_n += 1;
                     lat_sum += (double)l;
                     lat_max = std::max(lat_max, l);
@@ -318,9 +340,9 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
         uint64_t prev_end = 0;
         for (auto& ck : c->chunks) {
             const uint64_t first = std::max(prev_end, c->returned);
-            if (ck.second >= win_lo && ck.second < win_hi && ck.first > first)
-                missing += ck.first - first;
-            prev_end = ck.first;
+            if (ck.arrival >= win_lo && ck.arrival < win_hi && ck.end > first)
+                missing += ck.end - first;
+            prev_end = ck.end;
         }
     }
     if (srv) {
@@ -330,6 +352,13 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             res->eagain_ring = st.eagain_ring;
             res->eagain_stage = st.eagain_stage;
             res->mean_cycle_us = st.cycles ? st.gpu_busy_ns / 1e3 / st.cycles : 0.0;
+            res->mean_build_us = st.cycles ? st.build_ns / 1e3 / st.cycles : 0.0;
+            res->mean_launch_us = st.cycles ? st.launch_ns / 1e3 / st.cycles : 0.0;
+            res->max_cycle_us = st.max_cycle_ns / 1e3;
+            res->mean_gpu_us = st.cycles ? st.gpu_ns / 1e3 / st.cycles : 0.0;
+            res->mean_tiles = st.cycles ? (double)st.tiles / st.cycles : 0.0;
+            res->mean_stage_us = st.cycles ? st.stage_ns / 1e3 / st.cycles : 0.0;
+            res->mean_extract_us = st.cycles ? st.extract_ns / 1e3 / st.cycles : 0.0;
         }
     }
     if (capture_len)
@@ -347,21 +376,37 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
     res->chunks = chunks_done.load();
     res->eagain = eagain.load();
     res->max_submit_lag_us = max_lag.load() / 1e3;
+    // percentile = upper edge of the 1 us bin holding the rank-th value (the
+    // last bin also holds everything longer)
+    auto pct = [&](const std::vector<uint32_t>& h, uint64_t n, double q) {
+        const uint64_t rank = (uint64_t)(q * (double)(n - 1)) + 1;
+        uint64_t acc = 0;
+        for (uint64_t b = 0; b < kBins; ++b) {
+            acc += h[b];
+            if (acc >= rank) return (double)(b + 1);
+        }
+        return (double)kBins;
+    };
     if (lat_n) {
-        // percentile = upper edge of the 1 us bin holding the rank-th latency
-        auto pct = [&](double q) {
-            const uint64_t rank = (uint64_t)(q * (double)(lat_n - 1)) + 1;
-            uint64_t acc = 0;
-            for (uint64_t b = 0; b < kBins; ++b) {
-                acc += hist[b];
-                if (acc >= rank) return b + 1 >= kBins ? lat_max / 1e3 : (double)(b + 1);
-            }
-            return lat_max / 1e3;
-        };
-        res->lat_p50_us = pct(0.50);
-        res->lat_p99_us = pct(0.99);
+        res->lat_p50_us = std::min(pct(hist, lat_n, 0.50), lat_max / 1e3);
+        res->lat_p99_us = std::min(pct(hist, lat_n, 0.99), lat_max / 1e3);
         res->lat_max_us = lat_max / 1e3;
         res->lat_mean_us = lat_sum / lat_n / 1e3;
+        res->service_p50_us = pct(svc_hist, lat_n, 0.50);
+        res->service_p99_us = pct(svc_hist, lat_n, 0.99);
+        if (srv) {
+            res->ready_p50_us = pct(rdy_hist, lat_n, 0.50);
+            res->ready_p99_us = pct(rdy_hist, lat_n, 0.99);
+        }
+    }
+    {
+        std::vector<uint32_t> all(kBins, 0);
+        uint64_t n = 0;
+        for (uint32_t pidx = 0; pidx < n_prod; ++pidx) {
+            n += lag_n[pidx];
+            for (uint64_t b = 0; b < kBins; ++b) all[b] += lag_hist[pidx][b];
+        }
+        if (n) res->submit_lag_p99_us = pct(all, n, 0.99);
     }
     return f == EXT_EAGAIN ? EXT_EAGAIN : EXT_OK;
 }

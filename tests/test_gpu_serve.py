@@ -109,11 +109,16 @@ def test_server_interleaved_random_chunks(dev):
                 (w.n_bits, w.m_bits)
 
 
-def test_server_outputs_equal_plain_form_any_chunking(dev):
+@pytest.mark.parametrize("split", [1, 0])
+def test_server_outputs_equal_plain_form_any_chunking(dev, split):
+    """Random chunking of six channels; outputs equal the plain form's.  With
+    split = 1 (the default) pairs of the m = 4096 .. 16384 channels are cut
+    into slices over several work-groups and combined; with 0 every pair is
+    one work-group's."""
     rng = np.random.Generator(np.random.PCG64(22))
     streams = [inputs.plain_workload(n, m, 40 if n < 32768 else 4, 400 + i, 500 + i, kind=kind)
                for i, (n, m, kind) in enumerate(SHAPES)]
-    with binding.Server() as srv:
+    with binding.Server(config=binding.server_config(split_pairs=split)) as srv:
         chans = [srv.open(w.n_bits, w.m_bits) for w in streams]
         for c, w in zip(chans, streams):
             px = py = 0
@@ -127,7 +132,10 @@ def test_server_outputs_equal_plain_form_any_chunking(dev):
         for c, w in zip(chans, streams):
             assert np.array_equal(outs[c], plain(w.n_bits, w.m_bits, w.x, w.y)), w.n_bits
         st = srv.stats()
+        say("server stats: %s" % st)
         assert st["pairs"] == sum(w.n_pairs for w in streams)
+        sliced = sum(w.n_pairs for w in streams if w.n_bits >= 32768)
+        assert st["split_pairs"] == (sliced if split else 0)
 
 
 def test_server_admission_and_close(dev):
