@@ -28,6 +28,7 @@ N_PAIRS = 65536
 PEAK_BITMAC_T = 256 * 64 * 2.4e9 * 32 / 1e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_14607_amd", "csrc", "ext_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ext_ip_kernel_paper_block_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "ext_ip_kernel_paper_block_valu.txt")
 
 
 def log(msg):
@@ -39,13 +40,13 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def profile_value(path: str, key: str):
+    """A key=value figure of a committed rocprofv3 counter summary, if the
+    summary was taken on the current kernel source."""
+    if not os.path.exists(path):
         return None
     rec = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.startswith("#"):
                 k, v = line.strip().split("=", 1)
@@ -53,9 +54,14 @@ def measured_traffic():
     if rec.get("kernel_source_sha256_16") != kernel_hash():
         return None
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)."""
+    return profile_value(TRAFFIC_FILE, "hbm_bytes_per_launch")
 
 
 def cpu_baseline(w, target_s: float = 12.0):
@@ -157,7 +163,7 @@ def batched_leg(dev, stream, steps: int, warmup: int):
 def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
                                                              "plain_at_1/16_load"),
                wg_per_cu: int = 0, max_inflight: int = 0, split_pairs: int = -1,
-               producers: int = 4):
+               producers: int = 4, timing: int = 0):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
     1..64 blocks, 64 Gbps aggregate raw input; three quarters i.i.d. Gaussian
     with n from 2048..32768, one quarter AR(1) with n = 65536.  Served form
@@ -197,7 +203,7 @@ def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
                                   duration_s=duration_s, grace_s=2.0, max_lag_s=lag, seed=4,
                                   producer_threads=producers,
                                   config=binding.server_config(
-                                      wg_per_cu=wg_per_cu,
+                                      wg_per_cu=wg_per_cu, timing=timing,
                                       **({"max_inflight": max_inflight} if max_inflight else {}),
                                       **({"split_pairs": split_pairs} if split_pairs >= 0 else {})))
         log("served leg: %s: %s" % (name, json.dumps(res)))
@@ -242,6 +248,8 @@ def main():
                          "pairs; -1 = library default)")
     ap.add_argument("--serve-producers", type=int, default=4,
                     help="load generator threads submitting chunks")
+    ap.add_argument("--serve-timing", type=int, default=0,
+                    help="1: time every server cycle's phases with GPU events (diagnostic)")
     ap.add_argument("--serve-wg-per-cu", type=int, default=0,
                     help="persistent work-groups per CU in a served cycle (0 = as many as fit)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -328,7 +336,7 @@ def main():
         served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
                             modes=args.serve_modes.split(","), wg_per_cu=args.serve_wg_per_cu,
                             max_inflight=args.serve_inflight, split_pairs=args.serve_split,
-                            producers=args.serve_producers)
+                            producers=args.serve_producers, timing=args.serve_timing)
 
     sec = ms * 1e-3
     out_gbps = N_PAIRS * M_BITS / sec / 1e9
@@ -365,9 +373,12 @@ def main():
             "unit": "Tbit-MAC/s",
             "frac": round(achieved / PEAK_BITMAC_T, 4),
             "traffic": traffic,
+            "valu_issue_frac": profile_value(VALU_FILE, "valu_issue_frac_measured_peak"),
             "note": "achieved counts the schoolbook n*m bit-MACs per pair; peak is one "
                     "32-bit AND-XOR (v_bitop3_b32) per lane per clock on every lane; the "
-                    "kernel uses Karatsuba, so frac above 1 is possible",
+                    "kernel uses Karatsuba, so frac above 1 is possible; valu_issue_frac is "
+                    "the executed VALU instructions' issue time (rocprofv3 SQ_INSTS_VALU at "
+                    "the chip's measured v_bitop3_b32 rate) over the launch time",
         },
         "cpu_baseline": cpu,
         "batched": batched,

@@ -247,14 +247,18 @@ typedef struct {
                                device allows it); 0 = as many as fit (default 0) */
     uint64_t ring_bytes;    /* when ring_blocks == 0: ring per channel side in bytes, rounded
                                down to whole blocks, at least 128 blocks (default 4 MiB) */
-    uint32_t max_inflight;  /* cycles queued on the GPU at once, 1..3: 1 gives the lowest
-                               latency at light load, more overlap the host's launch work
-                               with the GPU at heavy load (default 1) */
+    uint32_t max_inflight;  /* cycles on the GPU at once, 1..3; a cycle's staging runs on
+                               its own stream and may overlap the previous cycle's
+                               extraction, and a new cycle starts only once the previous
+                               one is staged (default 2) */
     uint32_t split_pairs;   /* 1: plan channels for latency: one base product per lane
                                item, and a pair with more items than a work-group has
                                lanes is split over several work-groups whose partial sums
                                a combine step adds and reduces; 0: whole pairs per
                                work-group, with the plain form's plan (default 1) */
+    uint32_t timing;        /* 1: time every cycle's phases on the GPU with events (the
+                               gpu_ns, stage_ns and extract_ns stats); default 0 */
+    uint32_t reserved;
 } ext_server_config;
 typedef struct {
     uint64_t cycles, tiles, pairs, bytes_in;
@@ -265,8 +269,8 @@ typedef struct {
     uint64_t build_ns;      /* host time spent building cycles (tiles, metadata) */
     uint64_t launch_ns;     /* host time spent queueing cycles' kernels and events */
     uint64_t max_cycle_ns;  /* longest launch-to-harvest time of a cycle */
-    uint64_t gpu_ns;        /* sum over cycles of the GPU time from the first kernel's
-                               start to the end of the last */
+    uint64_t gpu_ns;        /* with timing: sum over cycles of the GPU time from the first
+                               kernel's start to the end of the last */
     uint64_t stage_ns;      /* of which: staging the cycle's input and metadata */
     uint64_t extract_ns;    /* of which: the extraction launches (the rest: combine) */
 } ext_server_stats;

@@ -90,6 +90,8 @@ class ServerConfig(ctypes.Structure):
         ("ring_bytes", ctypes.c_uint64),
         ("max_inflight", ctypes.c_uint32),
         ("split_pairs", ctypes.c_uint32),
+        ("timing", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 

@@ -75,7 +75,15 @@ struct Range {
     uint32_t ch;
     uint32_t n;
     uint64_t first_pair;
-    uint64_t out_off;  // byte offset in the outbox
+    uint64_t out_off;     // byte offset in the outbox
+    uint64_t part_word0;  // sliced channels: first word of the range's parts
+};
+
+// Tiles of one (base size, work-group size) launch while a cycle is built,
+// each with its cost (rounds times base products per item).
+struct GroupBuild {
+    uint32_t bw, threads, lds;
+    std::vector<std::pair<uint32_t, BatchTile>> tiles;
 };
 
 struct Group {
@@ -120,7 +128,8 @@ constexpr uint64_t kPartBytes = 32ull << 20;
 
 struct ext_server {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // extraction and combine launches
+    hipStream_t stage_stream = nullptr;  // staging kernels (library-owned)
     bool own_stream = false;
     int cus = 1;
     uint32_t lds_per_cu = 65536;     // LDS bytes per CU
@@ -146,6 +155,7 @@ struct ext_server {
     int sticky = EXT_OK;
     ext_server_stats stats{};
     std::vector<CombineJob> jobs_tmp;  // launch_cycle's job list (kept to reuse its storage)
+    std::vector<GroupBuild> group_build;  // launch_cycle's tile lists (likewise)
     uint64_t table_version = 1;        // bumped whenever a channel opens or closes
 };
 
@@ -167,6 +177,7 @@ void server_free(ext_server* s) {
         (void)hipFree(c.ring_y);
     }
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->stage_stream) (void)hipStreamDestroy(s->stage_stream);
     delete s;
 }
 
@@ -191,13 +202,15 @@ void harvest(ext_server* s) {
             c.completed += r.n;
         }
         s->stats.gpu_busy_ns += t - sl.launched_ns;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess)
-            s->stats.gpu_ns += (uint64_t)(ms * 1e6f);
-        if (hipEventElapsedTime(&ms, sl.start, sl.staged) == hipSuccess)
-            s->stats.stage_ns += (uint64_t)(ms * 1e6f);
-        if (hipEventElapsedTime(&ms, sl.staged, sl.computed) == hipSuccess)
-            s->stats.extract_ns += (uint64_t)(ms * 1e6f);
+        if (s->cfg.timing) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess)
+                s->stats.gpu_ns += (uint64_t)(ms * 1e6f);
+            if (hipEventElapsedTime(&ms, sl.start, sl.staged) == hipSuccess)
+                s->stats.stage_ns += (uint64_t)(ms * 1e6f);
+            if (hipEventElapsedTime(&ms, sl.staged, sl.computed) == hipSuccess)
+                s->stats.extract_ns += (uint64_t)(ms * 1e6f);
+        }
         s->stats.max_cycle_ns = std::max(s->stats.max_cycle_ns, t - sl.launched_ns);
         if (s->ready_waiters && !sl.ranges.empty()) s->ready_cv.notify_all();
         sl.ranges.clear();
@@ -240,15 +253,13 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     }
     sl.resv.clear();
 
-    // tiles of every channel's ready pairs, grouped by base size; a sliced
-    // pair takes `slices` tiles, room for their parts and one combine job
-    std::map<std::pair<uint32_t, uint32_t>, std::vector<BatchTile>> by_bw;  // (bw, threads)
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> lds_of;
-    std::vector<CombineJob>& jobs = s->jobs_tmp;
-    jobs.clear();
+    // Under the lock: every channel's ready pairs as ranges (at most one per
+    // ring pass), within the cycle's outbox, tile, job and part limits.  A
+    // sliced pair takes `slices` tiles, room for their parts and one combine
+    // job; other pairs go ppw to a tile.
     uint64_t out_off = 0, part_words = 0;
     const uint64_t part_cap = kPartBytes / 4;
-    uint32_t n_tiles = 0, combine_lds = 0;
+    uint32_t n_tiles = 0, n_jobs = 0;
     sl.ranges.clear();
     for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
         Channel& c = s->ch[ci];
@@ -259,42 +270,26 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
             const uint64_t slot0 = c.launched % c.R;
             uint64_t k = std::min<uint64_t>(ready, c.R - slot0);            // no ring wrap
             k = std::min<uint64_t>(k, (s->cfg.outbox_bytes - out_off) / c.qb);  // outbox room
+            uint64_t part0 = 0;
             if (c.slices > 1) {
                 k = std::min<uint64_t>(k, (s->cfg.max_tiles - n_tiles) / c.slices);
-                k = std::min<uint64_t>(k, s->max_jobs - (uint32_t)jobs.size());
-                const uint64_t pw = align_up(part_words, 4);
-                k = std::min<uint64_t>(k, pw < part_cap ? (part_cap - pw) / (c.slices * cw) : 0);
+                k = std::min<uint64_t>(k, s->max_jobs - n_jobs);
+                part0 = align_up(part_words, 4);  // 16-byte aligned parts
+                k = std::min<uint64_t>(k, part0 < part_cap ? (part_cap - part0) / (c.slices * cw) : 0);
             } else {
                 const uint64_t tiles_needed = (k + c.shape.ppw - 1) / c.shape.ppw;
                 if (n_tiles + tiles_needed > s->cfg.max_tiles)
                     k = std::min<uint64_t>(k, (uint64_t)(s->cfg.max_tiles - n_tiles) * c.shape.ppw);
             }
             if (k == 0) break;
-            sl.ranges.push_back(Range{ci, (uint32_t)k, c.launched, out_off});
-            const auto key = std::make_pair(c.shape.bw, c.shape.threads);
-            auto& vec = by_bw[key];
-            lds_of[key] = std::max(lds_of[key], c.shape.lds_words * 4);
+            sl.ranges.push_back(Range{ci, (uint32_t)k, c.launched, out_off, part0});
             if (c.slices > 1) {
-                const uint32_t items = c.shape.np * c.shape.n_e;
-                part_words = align_up(part_words, 4);  // 16-byte aligned parts
-                for (uint64_t p = 0; p < k; ++p) {
-                    jobs.push_back(CombineJob{ci, c.slices, part_words, (out_off + p * c.qb) / 4});
-                    for (uint32_t sidx = 0; sidx < c.slices; ++sidx) {
-                        const uint32_t i0 = sidx * c.slice_items;
-                        const uint32_t ni = std::min(c.slice_items, items - i0);
-                        vec.push_back(BatchTile{ci, 1, slot0 + p, part_words, i0, ni});
-                        part_words += cw;
-                        ++n_tiles;
-                    }
-                }
-                combine_lds = std::max<uint32_t>(combine_lds, (uint32_t)(cw + c.shape.dn) * 4);
+                n_tiles += (uint32_t)k * c.slices;
+                n_jobs += (uint32_t)k;
+                part_words = part0 + k * c.slices * cw;
                 s->stats.split_pairs += k;
             } else {
-                for (uint64_t p = 0; p < k; p += c.shape.ppw) {
-                    const uint32_t n = (uint32_t)std::min<uint64_t>(c.shape.ppw, k - p);
-                    vec.push_back(BatchTile{ci, n, slot0 + p, (out_off + p * c.qb) / 4, 0, 0});
-                    ++n_tiles;
-                }
+                n_tiles += (uint32_t)((k + c.shape.ppw - 1) / c.shape.ppw);
             }
             out_off += k * c.qb;
             c.launched += k;
@@ -303,8 +298,8 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     }
     if (sl.data_used == 0 && n_tiles == 0) return EXT_OK;  // (the slot stays free)
 
-    // metadata into the slot's pinned area; the stream table only when a
-    // channel opened or closed since this slot last sent it
+    // the stream table only when a channel opened or closed since this slot
+    // last sent it (written under the lock: open() changes the channels)
     const bool send_table = sl.table_version != s->table_version;
     if (send_table) {
         BatchStream* hs = reinterpret_cast<BatchStream*>(sl.h_in + s->off_streams);
@@ -315,23 +310,69 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         }
         sl.table_version = s->table_version;
     }
+    s->inflight.push_back(idx);
+    s->stats.cycles += 1;
+    s->stats.tiles += n_tiles;
+    for (const Range& r : sl.ranges) s->stats.pairs += r.n;
+
+    // Without the lock (submit() fills `next`, poll() reads harvested cycles;
+    // the channels of these ranges stay open until their pairs complete):
+    // tiles grouped by (base size, work-group size), longest first, since a
+    // lane's critical path is its rounds times the base products per item.
+    lk.unlock();
+    std::vector<GroupBuild>& gb = s->group_build;
+    for (GroupBuild& g : gb) g.tiles.clear();
+    std::vector<CombineJob>& jobs = s->jobs_tmp;
+    jobs.clear();
+    uint32_t combine_lds = 0;
+    for (const Range& r : sl.ranges) {
+        const Channel& c = s->ch[r.ch];
+        const ExtShape& sh = c.shape;
+        GroupBuild* g = nullptr;
+        for (GroupBuild& x : gb)
+            if (x.bw == sh.bw && x.threads == sh.threads) g = &x;
+        if (!g) {
+            gb.push_back(GroupBuild{sh.bw, sh.threads, 0, {}});
+            g = &gb.back();
+        }
+        if (g->tiles.empty()) g->lds = 0;
+        g->lds = std::max(g->lds, sh.lds_words * 4);
+        const uint64_t slot0 = r.first_pair % c.R;
+        if (c.slices > 1) {
+            const uint32_t items = sh.np * sh.n_e;
+            const uint64_t cw = 2ull * sh.qw;
+            uint64_t pw = r.part_word0;
+            for (uint64_t p = 0; p < r.n; ++p) {
+                jobs.push_back(CombineJob{r.ch, c.slices, pw, (r.out_off + p * c.qb) / 4});
+                for (uint32_t sidx = 0; sidx < c.slices; ++sidx) {
+                    const uint32_t i0 = sidx * c.slice_items;
+                    const uint32_t ni = std::min(c.slice_items, items - i0);
+                    g->tiles.push_back({(ni + sh.threads - 1) / sh.threads,
+                                        BatchTile{r.ch, 1, slot0 + p, pw, i0, ni}});
+                    pw += cw;
+                }
+            }
+            combine_lds = std::max<uint32_t>(combine_lds, (uint32_t)(cw + sh.dn) * 4);
+        } else {
+            for (uint64_t p = 0; p < r.n; p += sh.ppw) {
+                const uint32_t n = (uint32_t)std::min<uint64_t>(sh.ppw, r.n - p);
+                const uint64_t items = (uint64_t)n * sh.np * sh.groups;
+                const uint32_t cost = (uint32_t)(((items + sh.threads - 1) / sh.threads) * sh.epg);
+                g->tiles.push_back(
+                    {cost, BatchTile{r.ch, n, slot0 + p, (r.out_off + p * c.qb) / 4, 0, 0}});
+            }
+        }
+    }
     BatchTile* ht = reinterpret_cast<BatchTile*>(sl.h_in + s->off_tiles);
     sl.groups.clear();
     uint32_t t_off = 0;
-    for (auto& kv : by_bw) {
-        // longest tiles first: a lane's critical path is its rounds times the
-        // base products per item
-        auto cost = [&](const BatchTile& t) {
-            const ExtShape& sh = s->ch[t.stream].shape;
-            if (t.n_items) return (uint64_t)(t.n_items + sh.threads - 1) / sh.threads;
-            const uint64_t items = (uint64_t)t.npw * sh.np * sh.groups;
-            return ((items + sh.threads - 1) / sh.threads) * sh.epg;
-        };
-        std::stable_sort(kv.second.begin(), kv.second.end(),
-                         [&](const BatchTile& a, const BatchTile& b) { return cost(a) > cost(b); });
-        Group g{kv.first.first, kv.first.second, t_off, (uint32_t)kv.second.size(),
-                lds_of[kv.first], 0};
-        memcpy(ht + t_off, kv.second.data(), kv.second.size() * sizeof(BatchTile));
+    for (GroupBuild& gr : gb) {
+        if (gr.tiles.empty()) continue;
+        std::stable_sort(gr.tiles.begin(), gr.tiles.end(),
+                         [](const std::pair<uint32_t, BatchTile>& a,
+                            const std::pair<uint32_t, BatchTile>& b) { return a.first > b.first; });
+        Group g{gr.bw, gr.threads, t_off, (uint32_t)gr.tiles.size(), gr.lds, 0};
+        for (size_t i = 0; i < gr.tiles.size(); ++i) ht[t_off + i] = gr.tiles[i].second;
         int per_cu = occupancy(s, g.bw, g.threads, g.lds_bytes);
         if (s->cfg.wg_per_cu && (int)s->cfg.wg_per_cu < per_cu) {
             // at most wg_per_cu groups per CU: ask for just over 1/(k+1) of the
@@ -356,29 +397,26 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     sl.n_jobs = (uint32_t)jobs.size();
     sl.combine_lds = combine_lds;
     sl.out_bytes = out_off;
-    s->inflight.push_back(idx);
-    s->stats.cycles += 1;
-    s->stats.tiles += n_tiles;
-    for (const Range& r : sl.ranges) s->stats.pairs += r.n;
 
-    // queue the cycle without holding the lock (submit() now fills `next`)
-    lk.unlock();
     hipError_t e = hipSuccess;
-    // one stream, two kernels: staging (reads the pinned area over the bus),
-    // then one persistent launch per base size writing outputs straight into
-    // the pinned outbox
+    // staging (reads the pinned area over the bus), then one persistent launch
+    // per base size writing outputs straight into the pinned outbox, then the
+    // combine step of sliced pairs
     const size_t meta_off = send_table ? s->off_streams : s->off_tiles;
     const size_t meta_bytes =
         (off_jobs + (size_t)sl.n_jobs * sizeof(CombineJob) - meta_off + 15) / 16 * 16;
     sl.launched_ns = now_ns();
     const uint64_t t_built = sl.launched_ns;
-    e = hipEventRecord(sl.start, s->stream);
+    // staging on its own stream, so that it overlaps the previous cycle's
+    // extraction; the compute stream waits for it on the GPU
+    if (s->cfg.timing) e = hipEventRecord(sl.start, s->stage_stream);
     if (e == hipSuccess)
         e = qext::launch_stage(sl.h_in, reinterpret_cast<const ScatterDesc*>(sl.h_in + s->off_desc),
                            sl.n_descs, sl.h_in + meta_off, sl.d_in + meta_off,
                            (uint32_t)meta_bytes, reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads),
-                           (uint32_t)sl.groups.size(), s->stream);
-    if (e == hipSuccess) e = hipEventRecord(sl.staged, s->stream);
+                           (uint32_t)sl.groups.size(), s->stage_stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.staged, s->stage_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, sl.staged, 0);
     for (size_t gi = 0; gi < sl.groups.size() && e == hipSuccess; ++gi) {
         const Group& g = sl.groups[gi];
         e = qext::launch_batch_noreset(
@@ -387,7 +425,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
             reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi, sl.d_part, g.grid,
             g.lds_bytes, s->stream);
     }
-    if (e == hipSuccess) e = hipEventRecord(sl.computed, s->stream);
+    if (e == hipSuccess && s->cfg.timing) e = hipEventRecord(sl.computed, s->stream);
     if (e == hipSuccess && sl.n_jobs)
         e = qext::launch_combine(
             reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
@@ -404,6 +442,13 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         return EXT_EDEVICE;
     }
     return EXT_OK;
+}
+
+// A new cycle may start once the newest cycle in flight has been staged (its
+// staging kernel then no longer holds the staging stream).
+bool stage_free(ext_server* s) {
+    if (s->inflight.empty()) return true;
+    return hipEventQuery(s->slots[s->inflight.back()].staged) == hipSuccess;
 }
 
 bool has_work(ext_server* s) {
@@ -425,7 +470,8 @@ void scheduler(ext_server* s) {
             if (s->stop) break;
             continue;
         }
-        if (!s->stop && s->inflight.size() < (size_t)s->cfg.max_inflight && has_work(s)) {
+        if (!s->stop && s->inflight.size() < (size_t)s->cfg.max_inflight && has_work(s) &&
+            stage_free(s)) {
             launch_cycle(s, lk);
             s->cv.notify_all();
             continue;
@@ -459,7 +505,7 @@ void ext_server_config_init(ext_server_config* c) {
     c->stage_bytes = 64ull << 20;
     c->outbox_bytes = 32ull << 20;
     c->max_tiles = 1u << 17;
-    c->max_inflight = 1;
+    c->max_inflight = 2;
     c->split_pairs = 1;
     c->max_descs = 1u << 16;
     c->poll_us = 0;
@@ -508,6 +554,11 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
         delete s;
         return EXT_EDEVICE;
     }
+    if (hipStreamCreateWithFlags(&s->stage_stream, hipStreamNonBlocking) != hipSuccess) {
+        s->stage_stream = nullptr;
+        server_free(s);
+        return EXT_EDEVICE;
+    }
     s->off_desc = align_up(cfg->stage_bytes, 256);
     s->off_streams = align_up(s->off_desc + (size_t)cfg->max_descs * sizeof(ScatterDesc), 256);
     s->off_tiles = align_up(s->off_streams + (size_t)cfg->max_channels * sizeof(BatchStream), 256);
@@ -527,10 +578,13 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
                        hipSuccess;
         ok = ok && hipMalloc((void**)&sl.d_in, s->in_bytes) == hipSuccess;
         ok = ok && hipMalloc((void**)&sl.d_part, kPartBytes) == hipSuccess;
-        ok = ok && hipEventCreate(&sl.done) == hipSuccess;
-        ok = ok && hipEventCreate(&sl.start) == hipSuccess;
-        ok = ok && hipEventCreate(&sl.staged) == hipSuccess;
-        ok = ok && hipEventCreate(&sl.computed) == hipSuccess;
+        const unsigned ev_flags = cfg->timing ? hipEventDefault : hipEventDisableTiming;
+        ok = ok && hipEventCreateWithFlags(&sl.done, ev_flags) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.staged, ev_flags) == hipSuccess;
+        if (cfg->timing) {
+            ok = ok && hipEventCreate(&sl.start) == hipSuccess;
+            ok = ok && hipEventCreate(&sl.computed) == hipSuccess;
+        }
     }
     try {
         s->ch.resize(cfg->max_channels);
@@ -765,6 +819,7 @@ int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
     // pairs received but not yet launched are dropped with the channel; wait
     // for the stream before freeing the rings
     lk.unlock();
+    (void)hipStreamSynchronize(s->stage_stream);
     (void)hipStreamSynchronize(s->stream);
     lk.lock();
     (void)hipFree(c.ring_x);
