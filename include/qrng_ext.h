@@ -122,6 +122,36 @@ int ext_default_modulus(uint32_t m_bits, uint32_t *exps, uint32_t cap, uint32_t 
 int ext_is_irreducible(uint32_t m_bits, const uint32_t *taps, uint32_t n_taps);
 
 /*
+ * Parameters and security bounds (host only, no GPU work).
+ *
+ * ext_choose_params: Algorithm 1's rule for two (b, N, delta) forward block
+ * sources and a total error eps: n_e = ceil(24 / (2 delta - 1)) elements per
+ * block (integer arithmetic on delta = delta_num / delta_den, which must lie
+ * in (1/2, 1]) and q = b * ceil(log2(N / (eps n_e)) / b) bits per element
+ * (double precision; N given as log2 of the number of b-bit samples per source,
+ * eps as log2 of the error, which must be negative).  EXT_EINVAL when the
+ * inputs are outside those ranges or q would not be positive.
+ */
+int ext_choose_params(uint32_t sample_bits, uint64_t delta_num, uint64_t delta_den,
+                      double log2_n_samples, double log2_eps, uint32_t *n_e, uint32_t *q);
+/* Theorem 3.3: log2 of sqrt(3) * 2^(-1/4 - (delta/4 - 1/8) q n_e + 2q), the
+ * distance from uniform of one block's output for sources of min-entropy rate
+ * delta (a value >= 0 means the bound says nothing).  NaN on a bad argument. */
+double ext_block_error_log2(uint32_t n_e, uint32_t q, double delta);
+/* Theorem 3.6, for Algorithm 2 with q_l = q1 + (l-1) * delta_steps * b
+ * (delta_steps = 0 is Algorithm 1): *log2_sum = log2 of the sum of the k
+ * per-block bounds (a geometric series, evaluated in closed form), and
+ * *log2_closed = log2 of sqrt(3) 2^(-1/4 - q1) / (1 - 2^(-delta_steps b)), the
+ * bound on the whole infinite output (+inf when delta_steps = 0).  Either
+ * pointer may be NULL. */
+int ext_stream_error_log2(uint32_t n_e, uint32_t q1, uint32_t delta_steps, uint32_t sample_bits,
+                          double delta, uint64_t k, double *log2_sum, double *log2_closed);
+/* Theorem 3.6: m_k = k q1 + k (k-1) delta_steps b / 2 output bits of the
+ * first k blocks; EXT_EINVAL if it does not fit in 64 bits. */
+int ext_output_bits(uint32_t q1, uint32_t delta_steps, uint32_t sample_bits, uint64_t k,
+                    uint64_t *m_k);
+
+/*
  * Plain form (Algorithm 1 over n_pairs whole block pairs).
  *   x, y : n_pairs * n/8 bytes each (block l at byte offset l*n/8),
  *          4-byte aligned; 16-byte aligned device memory when m is 128

@@ -34,6 +34,7 @@ EXPORTED = (
     "ext_batch_destroy", "ext_server_config_init", "ext_server_create", "ext_server_open",
     "ext_server_submit", "ext_server_poll", "ext_server_close", "ext_server_stats_get",
     "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
+    "ext_choose_params", "ext_block_error_log2", "ext_stream_error_log2", "ext_output_bits",
 )
 
 EXT_SIM_SERVED = 0
@@ -191,6 +192,13 @@ def load() -> ctypes.CDLL:
         "ext_server_poll": (ctypes.c_int, [vp, u32, vp, sz, szp, u64p, u64p]),
         "ext_server_close": (ctypes.c_int, [vp, u32, u64p]),
         "ext_server_ready": (ctypes.c_int, [vp, ctypes.POINTER(u32), u32, ctypes.POINTER(u32), u32]),
+        "ext_choose_params": (ctypes.c_int, [u32, u64, u64, ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+        "ext_block_error_log2": (ctypes.c_double, [u32, u32, ctypes.c_double]),
+        "ext_stream_error_log2": (ctypes.c_int, [u32, u32, u32, u32, ctypes.c_double, u64,
+                                                 ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_double)]),
+        "ext_output_bits": (ctypes.c_int, [u32, u32, u32, u64, u64p]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
         "ext_server_destroy": (ctypes.c_int, [vp]),
         "ext_serve_simulate": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult),
@@ -545,3 +553,40 @@ def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max
     out["admission_gave_up"] = rc == EXT_EAGAIN
     captured = [b[: clen[i]] for i, b in enumerate(caps)] if caps is not None else None
     return out, captured
+
+
+# ---------------------------------------------------------------------------
+# parameters and security bounds (host only)
+# ---------------------------------------------------------------------------
+def choose_params(sample_bits: int, delta_num: int, delta_den: int, log2_n_samples: float,
+                  log2_eps: float) -> tuple[int, int]:
+    """Algorithm 1's (n_e, q) for min-entropy rate delta_num/delta_den."""
+    lib = load()
+    n_e, q = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib.ext_choose_params(sample_bits, delta_num, delta_den, float(log2_n_samples),
+                                 float(log2_eps), ctypes.byref(n_e), ctypes.byref(q)),
+           "ext_choose_params")
+    return n_e.value, q.value
+
+
+def block_error_log2(n_e: int, q: int, delta: float) -> float:
+    """log2 of Theorem 3.3's bound for one block."""
+    return load().ext_block_error_log2(n_e, q, float(delta))
+
+
+def stream_error_log2(n_e: int, q1: int, delta_steps: int, sample_bits: int, delta: float,
+                      k: int) -> tuple[float, float]:
+    """(log2 of Theorem 3.6's sum over k blocks, log2 of its closed bound)."""
+    lib = load()
+    s, c = ctypes.c_double(), ctypes.c_double()
+    _check(lib.ext_stream_error_log2(n_e, q1, delta_steps, sample_bits, float(delta), k,
+                                     ctypes.byref(s), ctypes.byref(c)), "ext_stream_error_log2")
+    return s.value, c.value
+
+
+def output_bits(q1: int, delta_steps: int, sample_bits: int, k: int) -> int:
+    """m_k of Theorem 3.6."""
+    lib = load()
+    m = ctypes.c_uint64()
+    _check(lib.ext_output_bits(q1, delta_steps, sample_bits, k, ctypes.byref(m)), "ext_output_bits")
+    return m.value
