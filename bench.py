@@ -160,6 +160,60 @@ def batched_leg(dev, stream, steps: int, warmup: int):
     return res
 
 
+def paper_point_leg(dev, stream, steps: int, warmup: int):
+    """The paper's own parameter point (Sec. 4.2): n_e = 71 elements of F_2^80
+    per block, 16-bit Gaussian samples, 262144 block pairs in one launch per
+    step; sampled pairs checked against the oracle.  The paper's simulated
+    FPGA rate for this shape is 64 Gbps of output (context only)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2402_14607_amd import binding, inputs
+
+    log("paper-point leg: generating 262144 pairs of 16-bit samples")
+    w = inputs.paper_point()
+    n, m, pairs = w.n_bits, w.m_bits, w.n_pairs
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    out = torch.empty(pairs * m // 8, dtype=torch.uint8, device=dev)
+    ex = binding.Extractor(n, m, device_memory=True, sample_bits=16, stream=stream.cuda_stream)
+    plan = json.loads(ex.describe())
+    for _ in range(warmup):
+        ex.extract(x, y, out, pairs)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        ex.extract(x, y, out, pairs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    got = out.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.unique(np.concatenate([[0, pairs - 1], rng.integers(0, pairs, 14)])).astype(np.uint64)
+    want = oracle.ext_sampled(w.x, w.y, idx, n, m)
+    qb = m // 8
+    g = np.concatenate([got[int(i) * qb:(int(i) + 1) * qb] for i in idx])
+    parity = "bit-exact on %d sampled pairs" % idx.size if np.array_equal(g, want) else "MISMATCH"
+    out_gbps = pairs * m / (ms * 1e-3) / 1e9
+    log("paper-point leg: %.4f ms per launch, %.2f Gbps output, %s" % (ms, out_gbps, parity))
+    ex.close()
+    return {
+        "workload": "paper parameter point: n_e=71 elements of F_2^80 per block (n=5680 bits, "
+                    "355 16-bit samples), 262144 block pairs, iid round(N(32768, 682^2)) "
+                    "16-bit samples, seeds 31/32",
+        "ms_per_launch": round(ms, 5),
+        "output_gbps": round(out_gbps, 3),
+        "input_gbps": round(2 * pairs * n / (ms * 1e-3) / 1e9, 3),
+        "roofline_frac": round(pairs * n * m / (ms * 1e-3) / 1e12 / PEAK_BITMAC_T, 4),
+        "parity": parity,
+        "kernel_plan": plan,
+        "context_fpga_output_gbps": 64.0,
+    }
+
+
 def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
                                                              "plain_at_1/16_load"),
                wg_per_cu: int = 0, max_inflight: int = 0, split_pairs: int = -1,
@@ -236,6 +290,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-point", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -331,6 +386,11 @@ def main():
     if not args.no_batched:
         batched = batched_leg(dev, stream, steps=max(3, min(20, args.steps // 10)), warmup=2)
 
+    paper_point = None
+    if not args.no_paper_point:
+        paper_point = paper_point_leg(dev, stream, steps=max(5, min(50, args.steps // 4)),
+                                      warmup=3)
+
     served = None
     if not args.no_served:
         served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
@@ -382,6 +442,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched": batched,
+        "paper_point": paper_point,
         "served": served,
         "context": "paper's simulated FPGA rate: 64 Gbps output (Xilinx Kintex-7 XC7K480T, "
                    "200 MHz, n=71 elements of F_2^80); a different shape, not a target",

@@ -14,12 +14,11 @@ import time
 
 import oracle
 
-DEFAULT_DEGREES = (
+DEFAULT_DEGREES = sorted(set(
     list(range(2, 65))
-    + [80, 96, 128, 160, 192, 224]
-    + list(range(256, 1025, 64))
+    + list(range(8, 1025, 8))
     + [1536, 2048, 3072, 4096, 8192, 16384]
-)
+))
 
 
 def main(argv):

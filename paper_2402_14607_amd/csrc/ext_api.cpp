@@ -27,10 +27,14 @@ bool base_instantiated(uint32_t bw) {
 
 bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                 const PlanKnobs& knobs, ExtShape* s) {
-    if (q == 0 || q % 32 || n_e == 0 || (n_taps != 1 && n_taps != 3)) return false;
+    if (q == 0 || q % 8 || n_e == 0 || (n_taps != 1 && n_taps != 3)) return false;
+    if ((uint64_t)n_e * q / 8 > 0xffffffffull) return false;
     const uint32_t target = knobs.base_words ? knobs.base_words : 8u;
     if (target > (uint32_t)kMaxBaseWords) return false;
-    const uint32_t qw = q / 32;
+    // a degree that is not a multiple of 32 is computed in qw-word slots,
+    // zero above bit q (the product of padded operands is the same polynomial)
+    const bool padded = (q % 32) != 0;
+    const uint32_t qw = (q + 31) / 32;
     const uint32_t v = (uint32_t)__builtin_ctz(qw);
     const uint32_t odd = qw >> v;
     if (odd > 15) return false;
@@ -52,7 +56,10 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
         max_tap = std::max(max_tap, taps[t]);
     }
     if (2 * max_tap > q) return false;  // two folding passes suffice only below q/2
-    if (knobs.groups && n_e % knobs.groups) return false;
+    // element groups: g groups of ceil(n_e / g) elements (the last may hold
+    // fewer), for every g that this partition realises exactly
+    auto realised = [&](uint32_t g) { return (n_e + (n_e + g - 1) / g - 1) / ((n_e + g - 1) / g) == g; };
+    if (knobs.groups && (knobs.groups > n_e || !realised(knobs.groups))) return false;
     const uint32_t threads = knobs.threads ? knobs.threads : (uint32_t)kThreads;
     if (threads % 64 || threads > (uint32_t)kMaxThreads) return false;
 
@@ -61,6 +68,9 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     r.qw = qw;
     r.n_e = n_e;
     r.nw = qw * n_e;
+    r.padded = padded ? 1u : 0u;
+    r.qbytes = q / 8;
+    r.nbytes = (uint32_t)((uint64_t)n_e * q / 8);
     r.bw = bw;
     r.levels = levels;
     r.np = 1;
@@ -72,33 +82,38 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     // Element grouping and pairs per work-group: keep the most lanes busy
     // with the LDS footprint under kMaxLdsBytes (unless fixed by the knobs).
     double best_util = -1.0;
-    for (uint32_t stage_try = levels > 0 ? 1u : 0u;; stage_try = 0) {
+    for (uint32_t stage_try = (levels > 0 || padded) ? 1u : 0u;; stage_try = 0) {
         for (uint32_t g = 1; g <= n_e; ++g) {
-            if (n_e % g || (knobs.groups && g != knobs.groups)) continue;
+            if (!realised(g) || (knobs.groups && g != knobs.groups)) continue;
             const uint32_t per_pair = r.np * g;
             uint32_t ppw = per_pair >= threads ? 1u : threads / per_pair;
             if (knobs.ppw) ppw = knobs.ppw;
-            auto lds_words = [&](uint32_t pp) {
-                return pp * ((stage_try ? 2 * r.nw : 0) + 2 * qw + r.dn);
+            auto lds_words = [&](uint32_t pp) {  // padded shapes add C >> q per pair
+                return pp * ((stage_try ? 2 * r.nw : 0) + 2 * qw + r.dn + (padded ? qw : 0)) +
+                       (padded ? 2 * kPadSlack : 0);
             };
-            while (ppw > 1 && lds_words(ppw) * 4 > kMaxLdsBytes) --ppw;
-            if (lds_words(ppw) * 4 > 65536) continue;
+            // padded staging holds at most kPadRegs slot words per lane
+            auto regs_ok = [&](uint32_t pp) {
+                return !padded || (uint64_t)pp * r.nw <= (uint64_t)kPadRegs * threads;
+            };
+            while (ppw > 1 && (lds_words(ppw) * 4 > kMaxLdsBytes || !regs_ok(ppw))) --ppw;
+            if (lds_words(ppw) * 4 > 65536 || !regs_ok(ppw)) continue;
             const uint64_t items = (uint64_t)ppw * per_pair;
             const uint64_t rounds = (items + threads - 1) / threads;
             const double util = (double)items / (double)(rounds * threads);
             if (util > best_util + 1e-9) {
                 best_util = util;
                 r.groups = g;
-                r.epg = n_e / g;
+                r.epg = (n_e + g - 1) / g;
                 r.ppw = ppw;
                 r.stage = stage_try;
                 r.lds_words = lds_words(ppw);
             }
         }
-        if (best_util >= 0 || stage_try == 0) break;
+        if (best_util >= 0 || stage_try == 0 || padded) break;  // padded shapes are staged
     }
     if (best_util < 0) return false;
-    r.align = (!r.stage && bw % 4 == 0) ? 16u : 4u;
+    r.align = padded ? 1u : (!r.stage && bw % 4 == 0) ? 16u : 4u;
     r.threads = threads;
     *s = r;
     return true;
@@ -195,8 +210,8 @@ int enter(ext_ctx* c) {
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
 int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
-    HIP_TRY(c, qext::launch_extract(c->shape, (const uint32_t*)x, (const uint32_t*)y,
-                                    (uint32_t*)out, n_pairs, c->stream));
+    HIP_TRY(c, qext::launch_extract(c->shape, (const uint8_t*)x, (const uint8_t*)y, (uint8_t*)out,
+                                    n_pairs, c->stream));
     return EXT_OK;
 }
 

@@ -63,7 +63,7 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
     for (uint32_t nt : {(uint32_t)kThreads, (uint32_t)kMaxThreads})
     for (uint32_t bwt : {4u, 8u, 16u})
         for (uint32_t g = 1; g <= n_e; ++g) {
-            if (n_e % g) continue;
+            // (plan_shape rejects a group count that ceil-sized groups do not realise)
             PlanKnobs k{bwt, g, 0, nt};
             ExtShape s;
             if (!plan_shape(q, n_e, taps, n_taps, k, &s)) continue;
@@ -108,8 +108,8 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
         for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
             const ExtShape& s = cands[i].second;
             auto run = [&] {
-                return launch_extract(s, (const uint32_t*)dx, (const uint32_t*)dy,
-                                      (uint32_t*)dout, pairs, stream);
+                return launch_extract(s, (const uint8_t*)dx, (const uint8_t*)dy, (uint8_t*)dout,
+                                      pairs, stream);
             };
             if ((e = run()) != hipSuccess) break;
             if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
@@ -154,7 +154,7 @@ struct ext_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     struct Group {
-        uint32_t bw, threads, tile_off, n_tiles, lds_bytes, grid;
+        uint32_t bw, threads, padded, tile_off, n_tiles, lds_bytes, grid;
     };
     std::vector<Group> groups;
     std::vector<BatchStream> streams;  // host copy (device pointers inside)
@@ -185,7 +185,8 @@ void batch_free(ext_batch* b) {
 int enqueue(ext_batch* b) {
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto& g = b->groups[gi];
-        hipError_t e = qext::launch_batch(g.bw, g.threads, b->d_streams, b->d_tiles + g.tile_off,
+        hipError_t e = qext::launch_batch(g.bw, g.threads, g.padded != 0, b->d_streams,
+                                          b->d_tiles + g.tile_off,
                                           g.n_tiles,
                                           b->d_heads + gi, g.grid, g.lds_bytes, b->stream);
         if (e != hipSuccess) return EXT_EDEVICE;
@@ -230,8 +231,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
     int rc = EXT_OK;
     try {
         // plan every stream
-        // launches: one per (base size, work-group size) -> stream indices
-        std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_bw;
+        // launches: one per (base size, work-group size, padded) -> stream indices
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<uint32_t>> by_bw;
         for (uint32_t i = 0; i < n_items && rc == EXT_OK; ++i) {
             const ext_batch_item& it = items[i];
             if (it.n_bits == 0 || it.m_bits == 0 || it.n_bits % it.m_bits ||
@@ -263,10 +264,10 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 rc = EXT_EINVAL;
                 break;
             }
-            BatchStream st{(const uint32_t*)it.x, (const uint32_t*)it.y, (uint32_t*)it.out,
+            BatchStream st{(const uint8_t*)it.x, (const uint8_t*)it.y, (uint8_t*)it.out,
                            it.n_pairs, s};
             b->streams.push_back(st);
-            by_bw[{s.bw, s.threads}].push_back(i);
+            by_bw[std::make_tuple(s.bw, s.threads, s.padded)].push_back(i);
             b->total_pairs += it.n_pairs;
             b->total_bitmacs += (double)it.n_pairs * (double)it.n_bits * (double)it.m_bits;
         }
@@ -277,8 +278,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 rc = EXT_EDEVICE;
             for (auto& kv : by_bw) {
                 if (rc != EXT_OK) break;
-                ext_batch::Group g{kv.first.first, kv.first.second, (uint32_t)b->tiles.size(), 0, 0,
-                                   0};
+                ext_batch::Group g{std::get<0>(kv.first), std::get<1>(kv.first),
+                                   std::get<2>(kv.first), (uint32_t)b->tiles.size(), 0, 0, 0};
                 std::vector<std::pair<double, BatchTile>> tl;
                 for (uint32_t si : kv.second) {
                     const BatchStream& st = b->streams[si];
@@ -287,7 +288,7 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                     const double per_pair = (double)st.shape.np * st.shape.n_e;
                     for (uint64_t p0 = 0; p0 < st.n_pairs; p0 += st.shape.ppw) {
                         const uint32_t k = (uint32_t)std::min<uint64_t>(st.shape.ppw, st.n_pairs - p0);
-                        tl.push_back({per_pair * k, BatchTile{si, k, p0, p0 * st.shape.qw}});
+                        tl.push_back({per_pair * k, BatchTile{si, k, p0, p0 * st.shape.qbytes, 0, 0}});
                     }
                 }
                 // longest tiles first, so the queue ends with short ones
@@ -296,7 +297,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 for (auto& t : tl) b->tiles.push_back(t.second);
                 g.n_tiles = (uint32_t)tl.size();
                 int occ = 0;
-                if (qext::batch_occupancy(g.bw, g.threads, g.lds_bytes, &occ) != hipSuccess ||
+                if (qext::batch_occupancy(g.bw, g.threads, g.padded != 0, g.lds_bytes, &occ) !=
+                        hipSuccess ||
                     occ <= 0)
                     occ = 1;
                 g.grid = (uint32_t)std::min<uint64_t>(g.n_tiles, (uint64_t)cus * occ);

@@ -10,14 +10,16 @@ constexpr int kThreads = 256;           // default work-group size of the extrac
 constexpr int kMaxThreads = 1024;       // largest work-group size of the extraction kernels
 constexpr int kMaxBaseWords = 16;       // largest base-product size, 32-bit words
 constexpr uint32_t kMaxLdsBytes = 32768;
+constexpr uint32_t kPadRegs = 16;       // slot words per lane in padded staging
+constexpr uint32_t kPadSlack = 8;       // words after each staged area of a padded shape
 
 // Launch shape of one (n, m, P) configuration; computed on the host by
 // plan_shape() and passed to the kernel by value.
 struct ExtShape {
     uint32_t q;        // m, field degree = output bits per block pair
-    uint32_t qw;       // q / 32
+    uint32_t qw;       // ceil(q / 32), words per element (padded when q % 32 != 0)
     uint32_t n_e;      // elements per block (n / m)
-    uint32_t nw;       // n / 32, words per block
+    uint32_t nw;       // qw * n_e, words per block (in its padded LDS layout if padded)
     uint32_t bw;       // base-product size in words (B = 32*bw bits)
     uint32_t levels;   // Karatsuba levels L, q = B * 2^L
     uint32_t np;       // 3^L sub-products per element product
@@ -32,6 +34,11 @@ struct ExtShape {
     uint32_t align;    // required byte alignment of x and y (16 when operands are
                        // read from HBM with 16-byte loads, else 4)
     uint32_t threads;  // work-group size (a multiple of 64, at most kMaxThreads)
+    uint32_t padded;   // 1: q is not a multiple of 32; elements are re-laid out
+                       // in LDS as qw-word slots (qw = ceil(q/32)) and outputs
+                       // stored as bytes
+    uint32_t qbytes;   // q / 8, output bytes per pair
+    uint32_t nbytes;   // n / 8, bytes per block
 };
 
 // Tuning choices for one shape; 0 in a field means "planner's choice".
@@ -47,50 +54,52 @@ struct PlanKnobs {
 bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                 const PlanKnobs& knobs, ExtShape* s);
 
-// One stream of a batch, as the batched kernel reads it from device memory.
+// One stream of a batch, as the batched kernel reads it from device memory:
+// blocks shape.nbytes apart in x and y, outputs shape.qbytes apart in out.
 struct BatchStream {
-    const uint32_t* x;
-    const uint32_t* y;
-    uint32_t* out;
+    const uint8_t* x;
+    const uint8_t* y;
+    uint8_t* out;
     uint64_t n_pairs;
     ExtShape shape;
 };
 
 // One work-group's worth of a batch: npw consecutive pairs of a stream,
 // whose blocks start at pair slot in_pair0 of the stream's x and y, and
-// whose outputs go to word out_word0 of the stream's out.  When n_items is
+// whose outputs go to byte out_off of the stream's out.  When n_items is
 // nonzero the tile is one slice of the single pair in_pair0: its items
 // [item0, item0 + n_items) in element-major order, whose partial unreduced
-// sum goes to word out_word0 of the launch's part buffer instead.
+// sum goes to word out_off of the launch's part buffer instead.
 struct BatchTile {
     uint32_t stream;
     uint32_t npw;
     uint64_t in_pair0;
-    uint64_t out_word0;
+    uint64_t out_off;
     uint32_t item0;
     uint32_t n_items;
 };
 
 // One sliced pair to finish: XOR n_parts consecutive parts (2qw words each)
 // starting at word part_word0 of the part buffer, reduce, and store the
-// output at word out_word0 of the stream's out.
+// output at byte out_byte0 (a multiple of 4) of the stream's out.
 struct CombineJob {
     uint32_t stream;
     uint32_t n_parts;
     uint64_t part_word0;
-    uint64_t out_word0;
+    uint64_t out_byte0;
 };
 
 // Queue the extraction of n_pairs consecutive block pairs on `stream`.
-// x, y: device, n_pairs*nw words each; out: device, n_pairs*qw words.
-hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
-                          uint32_t* out, uint64_t n_pairs, hipStream_t stream);
+// x, y: device, n_pairs*nbytes bytes each; out: device, n_pairs*qbytes bytes
+// (4-byte aligned unless the shape is padded).
+hipError_t launch_extract(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
+                          uint64_t n_pairs, hipStream_t stream);
 
 // Queue the queue-head reset and one persistent launch of `grid` work-groups
 // of `threads` lanes over n_tiles tiles (all streams of the launch share base
-// size bw and work-group size).
+// size bw, work-group size and whether their shape is padded).
 // streams, tiles, head: device memory.
-hipError_t launch_batch(uint32_t bw, uint32_t threads, const BatchStream* streams,
+hipError_t launch_batch(uint32_t bw, uint32_t threads, bool padded, const BatchStream* streams,
                         const BatchTile* tiles, uint32_t n_tiles, uint32_t* head, uint32_t grid,
                         uint32_t lds_bytes, hipStream_t stream);
 
@@ -118,10 +127,10 @@ hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n
 // As launch_batch without the queue-head reset (the caller clears the head);
 // part (device) receives the partial sums of sliced tiles (may be null when
 // the launch has none).
-hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
-                                const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
-                                uint32_t* part, uint32_t grid, uint32_t lds_bytes,
-                                hipStream_t stream);
+hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, bool padded,
+                                const BatchStream* streams, const BatchTile* tiles,
+                                uint32_t n_tiles, uint32_t* head, uint32_t* part, uint32_t grid,
+                                uint32_t lds_bytes, hipStream_t stream);
 
 // Queue the combine step of n_jobs sliced pairs (after the batch launches
 // that wrote their parts, on the same stream).  lds_bytes: (2qw + dn) * 4 of
@@ -131,6 +140,7 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
                           hipStream_t stream);
 
 // Resident work-groups per CU of the batched kernel at this LDS size.
-hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,
+                           int* blocks_per_cu);
 
 }  // namespace qext

@@ -49,6 +49,24 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
+// acc[a + w] ^= mask(bit s of x[a]) & (y << s)[w]: one bit position s of
+// every word of x, 0 < s < 32.
+template <int BW>
+__device__ __forceinline__ void clmul_shift(const uint32_t (&x)[BW], const uint32_t (&y)[BW],
+                                            uint32_t (&acc)[2 * BW], uint32_t s) {
+    uint32_t ys[BW + 1];
+    ys[0] = y[0] << s;
+#pragma unroll
+    for (int w = 1; w < BW; ++w) ys[w] = funnel(y[w], y[w - 1], 32u - s);
+    ys[BW] = y[BW - 1] >> (32u - s);
+#pragma unroll
+    for (int a = 0; a < BW; ++a) {
+        const uint32_t m = bit_mask(x[a], s);
+#pragma unroll
+        for (int w = 0; w <= BW; ++w) acc[a + w] = and_xor(m, ys[w], acc[a + w]);
+    }
+}
+
 // acc[0 .. 2BW) ^= x(t) * y(t) over GF(2), x and y BW words each.
 template <int BW>
 __device__ __forceinline__ void clmul_acc(const uint32_t (&x)[BW], const uint32_t (&y)[BW],
@@ -60,19 +78,13 @@ __device__ __forceinline__ void clmul_acc(const uint32_t (&x)[BW], const uint32_
 #pragma unroll
         for (int w = 0; w < BW; ++w) acc[a + w] = and_xor(m, y[w], acc[a + w]);
     }
+    if constexpr (BW <= 4) {
+        // short bodies: unrolled, so loop control does not take issue slots
+#pragma unroll
+        for (uint32_t s = 1; s < 32; ++s) clmul_shift<BW>(x, y, acc, s);
+    } else {
 #pragma unroll 1
-    for (uint32_t s = 1; s < 32; ++s) {
-        uint32_t ys[BW + 1];
-        ys[0] = y[0] << s;
-#pragma unroll
-        for (int w = 1; w < BW; ++w) ys[w] = funnel(y[w], y[w - 1], 32u - s);
-        ys[BW] = y[BW - 1] >> (32u - s);
-#pragma unroll
-        for (int a = 0; a < BW; ++a) {
-            const uint32_t m = bit_mask(x[a], s);
-#pragma unroll
-            for (int w = 0; w <= BW; ++w) acc[a + w] = and_xor(m, ys[w], acc[a + w]);
-        }
+        for (uint32_t s = 1; s < 32; ++s) clmul_shift<BW>(x, y, acc, s);
     }
 }
 
@@ -198,25 +210,185 @@ __device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t*
     }
 }
 
+// 16 bytes [16k - lead, 16k - lead + 16) of the region [src, src + len)
+// (lead = src & 15), zero outside it: one aligned 16-byte load when the chunk
+// lies inside the region, single bytes otherwise, so no access leaves it.
+__device__ __forceinline__ uint4 region_chunk(const uint8_t* __restrict__ src, uint32_t len,
+                                              uint32_t lead, uint32_t k) {
+    const uint32_t first = 16u * k;  // raw byte index of the chunk's first byte
+    if (first >= lead && first + 16u <= lead + len)
+        return reinterpret_cast<const uint4*>(src - lead)[k];
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t b = 0; b < 16u; ++b) {
+        const uint32_t rb = first + b;
+        if (rb >= lead && rb < lead + len) v[b >> 2] |= (uint32_t)src[rb - lead] << (8u * (b & 3u));
+    }
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// Padded layout of npw blocks in LDS for fields whose degree q is not a
+// multiple of 32: element e of pair j occupies words [j*nw + e*qw, +qw), its
+// q bits from the block's bytes [e*q/8, (e+1)*q/8) (blocks nbytes apart, no
+// alignment assumed), zero above bit q.
+//   1. Both sides' npw*nbytes bytes are copied as they are, X into the ys
+//      area and Y into the xs area (raw byte lead + i = source byte i, lead =
+//      src & 15), with 16-byte loads, all of a lane's loads in flight
+//      together; each area has kPadSlack words of slack for the rounding.
+//   2. Every lane gathers its slot words of both sides into registers with
+//      funnel shifts; after a barrier it writes them to xs and ys.
+// Ends with a barrier.
+__device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* __restrict__ xb,
+                                             const uint8_t* __restrict__ yb, uint32_t* xs,
+                                             uint32_t* ys, uint32_t npw) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t nw = sh.nw, qw = sh.qw, qb = sh.qbytes, n_e = sh.n_e;
+    const uint32_t len = npw * sh.nbytes, total = npw * nw;
+    const uint32_t lead_x = (uint32_t)((uintptr_t)xb & 15u), lead_y = (uint32_t)((uintptr_t)yb & 15u);
+    const uint32_t nx = (lead_x + len + 15u) >> 4, ny = (lead_y + len + 15u) >> 4;
+    uint32_t* raw_x = ys;  // X's raw bytes, in the ys area
+    uint32_t* raw_y = xs;  // Y's raw bytes, in the xs area
+    const uint32_t nc = nx > ny ? nx : ny;
+#pragma unroll 4
+    for (uint32_t k = tid; k < nc; k += nt) {
+        const uint4 vx = region_chunk(xb, len, lead_x, k < nx ? k : 0);
+        const uint4 vy = region_chunk(yb, len, lead_y, k < ny ? k : 0);
+        if (k < nx) {
+            raw_x[4 * k + 0] = vx.x;
+            raw_x[4 * k + 1] = vx.y;
+            raw_x[4 * k + 2] = vx.z;
+            raw_x[4 * k + 3] = vx.w;
+        }
+        if (k < ny) {
+            raw_y[4 * k + 0] = vy.x;
+            raw_y[4 * k + 1] = vy.y;
+            raw_y[4 * k + 2] = vy.z;
+            raw_y[4 * k + 3] = vy.w;
+        }
+    }
+    __syncthreads();
+    // (pair, element, word) of slot word i = tid, and the step per nt words
+    const uint32_t j0 = tid / nw, r0 = tid - j0 * nw, e0 = r0 / qw, w0 = r0 - e0 * qw;
+    const uint32_t dj = nt / nw, rs = nt - dj * nw, de = rs / qw, dw = rs - de * qw;
+    uint32_t hx[kPadRegs], hy[kPadRegs];
+    uint32_t j = j0, e = e0, w = w0;
+#pragma unroll
+    for (uint32_t r = 0; r < kPadRegs; ++r) {
+        if (tid + r * nt < total) {
+            const uint32_t o = j * sh.nbytes + e * qb + 4u * w;  // byte in the region
+            const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
+            const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
+            const uint32_t ox = o + lead_x, oy = o + lead_y;
+            const uint32_t ax = ox >> 2, sx = (ox & 3u) * 8u, ay = oy >> 2, sy = (oy & 3u) * 8u;
+            hx[r] = (sx ? funnel(raw_x[ax + 1], raw_x[ax], sx) : raw_x[ax]) & keep;
+            hy[r] = (sy ? funnel(raw_y[ay + 1], raw_y[ay], sy) : raw_y[ay]) & keep;
+        }
+        j += dj;
+        e += de;
+        w += dw;
+        if (w >= qw) {
+            w -= qw;
+            e += 1;
+        }
+        if (e >= n_e) {
+            e -= n_e;
+            j += 1;
+        }
+    }
+    __syncthreads();  // every read of the raw copies precedes every write
+#pragma unroll
+    for (uint32_t r = 0; r < kPadRegs; ++r) {
+        const uint32_t i = tid + r * nt;
+        if (i < total) {
+            xs[i] = hx[r];
+            ys[i] = hy[r];
+        }
+    }
+    __syncthreads();
+}
+
+// reduce_store for q not a multiple of 32: C_hi = C >> q is first gathered
+// into hs (qw words per pair) with funnel shifts, the folding passes are the
+// same, the result is masked to q bits and stored as q/8 bytes per pair at
+// outb (any alignment).  Ends after the last global store, without a barrier.
+__device__ __forceinline__ void reduce_store_padded(const ExtShape& sh, const uint32_t* cs,
+                                                    uint32_t* hs, uint32_t* ds,
+                                                    uint8_t* __restrict__ outb, uint32_t npw) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = blockDim.x;
+    const uint32_t qw = sh.qw, cw = 2 * qw, q0 = sh.q >> 5, r = sh.q & 31u;
+    for (uint32_t i = tid; i < npw * qw; i += nt) {
+        const uint32_t j = i / qw, w = i - j * qw;
+        const uint32_t* c = cs + j * cw;
+        hs[i] = funnel(c[q0 + w + 1], c[q0 + w], r);  // q0 + w + 1 <= 2qw - 1
+    }
+    __syncthreads();
+    const uint32_t dn = sh.dn;
+    for (uint32_t i = tid; i < npw * dn; i += nt) {
+        const uint32_t j = i / dn, k = i - j * dn;
+        const uint32_t* hi = hs + j * qw;
+        uint32_t d = 0;
+        for (uint32_t t = 0; t < sh.n_taps; ++t) {
+            const uint32_t rr = sh.q - sh.taps[t];
+            const uint32_t rw = rr >> 5, rb = rr & 31u;
+            const uint32_t lo_i = k + rw, hi_i = k + rw + 1;
+            const uint32_t lo = lo_i < qw ? hi[lo_i] : 0u;
+            const uint32_t up = hi_i < qw ? hi[hi_i] : 0u;
+            d ^= rb ? funnel(up, lo, rb) : lo;
+        }
+        ds[j * dn + k] = d;
+    }
+    __syncthreads();
+    const uint32_t last_mask = (1u << r) - 1u;  // r != 0 on this path
+    for (uint32_t i = tid; i < npw * qw; i += nt) {
+        const uint32_t j = i / qw, w = i - j * qw;
+        const uint32_t* hi = hs + j * qw;
+        const uint32_t* dd = ds + j * dn;
+        uint32_t z = cs[j * cw + w] ^ hi[w] ^ (w < dn ? dd[w] : 0u);
+        for (uint32_t t = 0; t < sh.n_taps; ++t) {
+            const uint32_t e = sh.taps[t];
+            const int32_t src = (int32_t)w - (int32_t)(e >> 5);
+            const uint32_t eb = e & 31u;
+            const uint32_t h1 = src >= 0 ? hi[src] : 0u;
+            const uint32_t h0 = src >= 1 ? hi[src - 1] : 0u;
+            z ^= eb ? funnel(h1, h0, 32u - eb) : h1;
+            const uint32_t d1 = (src >= 0 && (uint32_t)src < dn) ? dd[src] : 0u;
+            const uint32_t d0 = (src >= 1 && (uint32_t)(src - 1) < dn) ? dd[src - 1] : 0u;
+            z ^= eb ? funnel(d1, d0, 32u - eb) : d1;
+        }
+        if (w == qw - 1) z &= last_mask;
+        uint8_t* o = outb + (uint64_t)j * sh.qbytes + 4u * w;
+        const uint32_t cnt = sh.qbytes - 4u * w < 4u ? sh.qbytes - 4u * w : 4u;
+        for (uint32_t b = 0; b < cnt; ++b) o[b] = (uint8_t)(z >> (8u * b));
+    }
+}
+
 // One work-group's share: npw consecutive block pairs of one stream with
-// shape sh (npw <= sh.ppw); xg, yg point at the first pair's blocks and out at
-// its output.  lds holds sh.lds_words words.  Ends after the last global
-// store, without a barrier.
-template <int BW>
-__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t* __restrict__ xg,
-                                              const uint32_t* __restrict__ yg,
-                                              uint32_t* __restrict__ out, uint32_t npw,
+// shape sh (npw <= sh.ppw); xb, yb point at the first pair's blocks and outb
+// at its output (bytes; 4-byte aligned unless the shape is padded).  lds
+// holds sh.lds_words words.  Ends after the last global store, without a
+// barrier.
+template <int BW, bool PAD>
+__device__ __forceinline__ void extract_group(const ExtShape& sh, const uint8_t* __restrict__ xb,
+                                              const uint8_t* __restrict__ yb,
+                                              uint8_t* __restrict__ outb, uint32_t npw,
                                               uint32_t* lds) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nt = blockDim.x;  // sh.threads lanes
     const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
+    const uint32_t* xg = reinterpret_cast<const uint32_t*>(xb);
+    const uint32_t* yg = reinterpret_cast<const uint32_t*>(yb);
+    // padded shapes: kPadSlack words after each staged area (raw copies)
+    const uint32_t area = (sh.stage ? sh.ppw * nw : 0) + (PAD ? kPadSlack : 0);
     uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
-    uint32_t* ys = xs + (sh.stage ? sh.ppw * nw : 0); // [ppw][nw]   (staged Y)
-    uint32_t* cs = ys + (sh.stage ? sh.ppw * nw : 0); // [ppw][2qw]  unreduced sums
+    uint32_t* ys = xs + area;                         // [ppw][nw]   (staged Y)
+    uint32_t* cs = ys + area;                         // [ppw][2qw]  unreduced sums
     uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
+    uint32_t* hs = ds + sh.ppw * sh.dn;               // [ppw][qw]   C >> q (padded shapes)
 
     for (uint32_t i = tid; i < npw * cw; i += nt) cs[i] = 0;
-    if (sh.stage) {
+    if constexpr (PAD) {
+        stage_padded(sh, xb, yb, xs, ys, npw);  // padded shapes are always staged
+    } else if (sh.stage) {
         for (uint32_t i = tid; i < npw * nw; i += nt) {
             xs[i] = xg[i];
             ys[i] = yg[i];
@@ -239,7 +411,9 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
 #pragma unroll
         for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
 
-        for (uint32_t e = g * sh.epg; e < (g + 1) * sh.epg; ++e) {
+        // elements of group g (the last group may hold fewer)
+        const uint32_t e_end = (g + 1) * sh.epg < sh.n_e ? (g + 1) * sh.epg : sh.n_e;
+        for (uint32_t e = g * sh.epg; e < e_end; ++e) {
             uint32_t xo[BW], yo[BW];
             if (sh.stage) {  // operands from the LDS copy
                 form_operand<BW>(xo, xs + j * nw + e * qw, hi_mask, mid_mask);
@@ -254,7 +428,10 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint32_t
         scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs + j * cw);
     }
     __syncthreads();
-    reduce_store(sh, cs, ds, out, npw);
+    if constexpr (PAD)
+        reduce_store_padded(sh, cs, hs, ds, outb, npw);
+    else
+        reduce_store(sh, cs, ds, reinterpret_cast<uint32_t*>(outb), npw);
 }
 
 // One slice of one block pair, for pairs with more sub-products than a
@@ -313,23 +490,26 @@ __device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t
 }
 
 // Plain form: work-group g takes pairs [g*ppw, (g+1)*ppw) of one stream.
-template <int BW>
+// PAD: the shape is padded (q not a multiple of 32).
+template <int BW, bool PAD>
 __global__ void __launch_bounds__(kMaxThreads)
-ext_ip_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
-              uint32_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
+ext_ip_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
+              uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
     extern __shared__ uint32_t lds[];
     const uint64_t pair0 = (uint64_t)blockIdx.x * sh.ppw;
     if (pair0 >= n_pairs) return;
     const uint64_t left = n_pairs - pair0;
     const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;
-    extract_group<BW>(sh, x + pair0 * sh.nw, y + pair0 * sh.nw, out + pair0 * sh.qw, npw, lds);
+    extract_group<BW, PAD>(sh, x + pair0 * sh.nbytes, y + pair0 * sh.nbytes,
+                           out + pair0 * sh.qbytes, npw, lds);
 }
 
 // Batched form: a persistent grid drains a device work queue of tiles
 // (stream, first pair, pair count; or one slice of one pair) shared by many
 // streams of different shapes.  Each work-group takes the next tile with one atomic add on the
 // queue head and stops once the head passes n_tiles, so every wave exits.
-template <int BW>
+// PAD: every stream of the launch has a padded shape (no slices then).
+template <int BW, bool PAD>
 __global__ void __launch_bounds__(kMaxThreads)
 ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __restrict__ tiles,
                  uint32_t n_tiles, uint32_t* __restrict__ head, uint32_t* __restrict__ part) {
@@ -343,12 +523,14 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         const BatchTile tile = tiles[t];
         const BatchStream& st = streams[tile.stream];
         const ExtShape& sh = st.shape;  // read in place (a local copy would go to scratch)
-        if (tile.n_items)  // one slice of one pair; out_word0 locates its part
-            extract_slice<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
-                              part + tile.out_word0, tile.item0, tile.n_items, lds);
+        const uint8_t* xb = st.x + tile.in_pair0 * sh.nbytes;
+        const uint8_t* yb = st.y + tile.in_pair0 * sh.nbytes;
+        if (!PAD && tile.n_items)  // one slice of one pair; out_off is its part's word offset
+            extract_slice<BW>(sh, reinterpret_cast<const uint32_t*>(xb),
+                              reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
+                              tile.item0, tile.n_items, lds);
         else
-            extract_group<BW>(sh, st.x + tile.in_pair0 * sh.nw, st.y + tile.in_pair0 * sh.nw,
-                              st.out + tile.out_word0, tile.npw, lds);
+            extract_group<BW, PAD>(sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
 }
@@ -404,7 +586,7 @@ combine_kernel(const BatchStream* __restrict__ streams, const CombineJob* __rest
             }
         }
         __syncthreads();
-        reduce_store(sh, lds, lds + cw, st.out + job.out_word0, 1);
+        reduce_store(sh, lds, lds + cw, reinterpret_cast<uint32_t*>(st.out + job.out_byte0), 1);
         __syncthreads();  // lds is reused by the next job
     }
 }
@@ -462,38 +644,48 @@ __global__ void reset_head_kernel(uint32_t* head) {
 }
 
 template <int BW>
-hipError_t launch_bw(const ExtShape& s, const uint32_t* x, const uint32_t* y, uint32_t* out,
+hipError_t launch_bw(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
                      uint64_t n_pairs, hipStream_t stream) {
     const uint64_t groups = (n_pairs + s.ppw - 1) / s.ppw;
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ext_ip_kernel<BW>, dim3((uint32_t)groups), dim3(s.threads),
-                       s.lds_words * 4u, stream, x, y, out, n_pairs, s);
+    if (s.padded)
+        hipLaunchKernelGGL((ext_ip_kernel<BW, true>), dim3((uint32_t)groups), dim3(s.threads),
+                           s.lds_words * 4u, stream, x, y, out, n_pairs, s);
+    else
+        hipLaunchKernelGGL((ext_ip_kernel<BW, false>), dim3((uint32_t)groups), dim3(s.threads),
+                           s.lds_words * 4u, stream, x, y, out, n_pairs, s);
     return hipGetLastError();
 }
 
 template <int BW>
-hipError_t launch_batch_bw(uint32_t threads, const BatchStream* streams, const BatchTile* tiles,
-                           uint32_t n_tiles, uint32_t* head, uint32_t grid, uint32_t lds_bytes,
-                           hipStream_t stream) {
-    hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
-    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
-                       streams, tiles, n_tiles, head, static_cast<uint32_t*>(nullptr));
-    return hipGetLastError();
-}
-
-template <int BW>
-hipError_t launch_batch_only_bw(uint32_t threads, const BatchStream* streams,
+hipError_t launch_batch_only_bw(uint32_t threads, bool padded, const BatchStream* streams,
                                 const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
                                 uint32_t* part, uint32_t grid, uint32_t lds_bytes,
                                 hipStream_t stream) {
-    hipLaunchKernelGGL(ext_batch_kernel<BW>, dim3(grid), dim3(threads), lds_bytes, stream,
-                       streams, tiles, n_tiles, head, part);
+    if (padded)
+        hipLaunchKernelGGL((ext_batch_kernel<BW, true>), dim3(grid), dim3(threads), lds_bytes,
+                           stream, streams, tiles, n_tiles, head, part);
+    else
+        hipLaunchKernelGGL((ext_batch_kernel<BW, false>), dim3(grid), dim3(threads), lds_bytes,
+                           stream, streams, tiles, n_tiles, head, part);
     return hipGetLastError();
 }
 
 template <int BW>
-hipError_t occupancy_bw(uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ext_batch_kernel<BW>,
+hipError_t launch_batch_bw(uint32_t threads, bool padded, const BatchStream* streams,
+                           const BatchTile* tiles, uint32_t n_tiles, uint32_t* head, uint32_t grid,
+                           uint32_t lds_bytes, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
+    return launch_batch_only_bw<BW>(threads, padded, streams, tiles, n_tiles, head,
+                                    static_cast<uint32_t*>(nullptr), grid, lds_bytes, stream);
+}
+
+template <int BW>
+hipError_t occupancy_bw(uint32_t threads, bool padded, uint32_t lds_bytes, int* blocks_per_cu) {
+    if (padded)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks_per_cu, ext_batch_kernel<BW, true>, threads, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ext_batch_kernel<BW, false>,
                                                         threads, lds_bytes);
 }
 
@@ -517,12 +709,13 @@ hipError_t occupancy_bw(uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu
         default: return hipErrorInvalidValue;      \
     }
 
-hipError_t launch_batch(uint32_t bw, uint32_t threads, const BatchStream* streams,
+hipError_t launch_batch(uint32_t bw, uint32_t threads, bool padded, const BatchStream* streams,
                         const BatchTile* tiles, uint32_t n_tiles, uint32_t* head, uint32_t grid,
                         uint32_t lds_bytes, hipStream_t stream) {
     if (n_tiles == 0) return hipSuccess;
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64) return hipErrorInvalidValue;
-    QEXT_BW_CASES(launch_batch_bw, threads, streams, tiles, n_tiles, head, grid, lds_bytes, stream)
+    QEXT_BW_CASES(launch_batch_bw, threads, padded, streams, tiles, n_tiles, head, grid, lds_bytes,
+                  stream)
 }
 
 hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
@@ -539,13 +732,13 @@ hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n
     return hipGetLastError();
 }
 
-hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, const BatchStream* streams,
-                                const BatchTile* tiles, uint32_t n_tiles, uint32_t* head,
-                                uint32_t* part, uint32_t grid, uint32_t lds_bytes,
-                                hipStream_t stream) {
+hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, bool padded,
+                                const BatchStream* streams, const BatchTile* tiles,
+                                uint32_t n_tiles, uint32_t* head, uint32_t* part, uint32_t grid,
+                                uint32_t lds_bytes, hipStream_t stream) {
     if (n_tiles == 0) return hipSuccess;
     if (threads == 0 || threads > (uint32_t)kMaxThreads || threads % 64) return hipErrorInvalidValue;
-    QEXT_BW_CASES(launch_batch_only_bw, threads, streams, tiles, n_tiles, head, part, grid,
+    QEXT_BW_CASES(launch_batch_only_bw, threads, padded, streams, tiles, n_tiles, head, part, grid,
                   lds_bytes, stream)
 }
 
@@ -559,12 +752,13 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(uint32_t bw, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {
-    QEXT_BW_CASES(occupancy_bw, threads, lds_bytes, blocks_per_cu)
+hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,
+                           int* blocks_per_cu) {
+    QEXT_BW_CASES(occupancy_bw, threads, padded, lds_bytes, blocks_per_cu)
 }
 
-hipError_t launch_extract(const ExtShape& s, const uint32_t* x, const uint32_t* y,
-                          uint32_t* out, uint64_t n_pairs, hipStream_t stream) {
+hipError_t launch_extract(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
+                          uint64_t n_pairs, hipStream_t stream) {
     if (n_pairs == 0) return hipSuccess;
     if (s.threads == 0 || s.threads > (uint32_t)kMaxThreads || s.threads % 64)
         return hipErrorInvalidValue;

@@ -79,15 +79,15 @@ struct Range {
     uint64_t part_word0;  // sliced channels: first word of the range's parts
 };
 
-// Tiles of one (base size, work-group size) launch while a cycle is built,
+// Tiles of one (base size, work-group size, padded) launch while a cycle is built,
 // each with its cost (rounds times base products per item).
 struct GroupBuild {
-    uint32_t bw, threads, lds;
+    uint32_t bw, threads, padded, lds;
     std::vector<std::pair<uint32_t, BatchTile>> tiles;
 };
 
 struct Group {
-    uint32_t bw, threads, tile_off, n_tiles, lds_bytes, grid;
+    uint32_t bw, threads, padded, tile_off, n_tiles, lds_bytes, grid;
 };
 
 // A submission's end position on one side, recorded in the cycle that holds it.
@@ -220,12 +220,13 @@ void harvest(ext_server* s) {
     }
 }
 
-int occupancy(ext_server* s, uint32_t bw, uint32_t threads, uint32_t lds) {
-    auto key = std::make_tuple(bw, threads, lds);
+int occupancy(ext_server* s, uint32_t bw, uint32_t threads, uint32_t padded, uint32_t lds) {
+    auto key = std::make_tuple(bw, threads * 2 + padded, lds);
     auto it = s->occ_cache.find(key);
     if (it != s->occ_cache.end()) return it->second;
     int occ = 0;
-    if (qext::batch_occupancy(bw, threads, lds, &occ) != hipSuccess || occ <= 0) occ = 1;
+    if (qext::batch_occupancy(bw, threads, padded != 0, lds, &occ) != hipSuccess || occ <= 0)
+        occ = 1;
     s->occ_cache[key] = occ;
     return occ;
 }
@@ -268,8 +269,11 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         const uint64_t cw = 2ull * c.shape.qw;
         while (ready) {
             const uint64_t slot0 = c.launched % c.R;
+            out_off = align_up(out_off, 4);  // word stores for 32-bit multiple degrees
             uint64_t k = std::min<uint64_t>(ready, c.R - slot0);            // no ring wrap
-            k = std::min<uint64_t>(k, (s->cfg.outbox_bytes - out_off) / c.qb);  // outbox room
+            k = std::min<uint64_t>(k, out_off < s->cfg.outbox_bytes
+                                          ? (s->cfg.outbox_bytes - out_off) / c.qb
+                                          : 0);  // outbox room
             uint64_t part0 = 0;
             if (c.slices > 1) {
                 k = std::min<uint64_t>(k, (s->cfg.max_tiles - n_tiles) / c.slices);
@@ -305,8 +309,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         BatchStream* hs = reinterpret_cast<BatchStream*>(sl.h_in + s->off_streams);
         for (uint32_t ci = 0; ci < s->ch.size(); ++ci) {
             const Channel& c = s->ch[ci];
-            hs[ci] = BatchStream{(const uint32_t*)c.ring_x, (const uint32_t*)c.ring_y,
-                                 (uint32_t*)sl.h_out, 0, c.shape};
+            hs[ci] = BatchStream{c.ring_x, c.ring_y, sl.h_out, 0, c.shape};
         }
         sl.table_version = s->table_version;
     }
@@ -330,9 +333,9 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         const ExtShape& sh = c.shape;
         GroupBuild* g = nullptr;
         for (GroupBuild& x : gb)
-            if (x.bw == sh.bw && x.threads == sh.threads) g = &x;
+            if (x.bw == sh.bw && x.threads == sh.threads && x.padded == sh.padded) g = &x;
         if (!g) {
-            gb.push_back(GroupBuild{sh.bw, sh.threads, 0, {}});
+            gb.push_back(GroupBuild{sh.bw, sh.threads, sh.padded, 0, {}});
             g = &gb.back();
         }
         if (g->tiles.empty()) g->lds = 0;
@@ -343,7 +346,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
             const uint64_t cw = 2ull * sh.qw;
             uint64_t pw = r.part_word0;
             for (uint64_t p = 0; p < r.n; ++p) {
-                jobs.push_back(CombineJob{r.ch, c.slices, pw, (r.out_off + p * c.qb) / 4});
+                jobs.push_back(CombineJob{r.ch, c.slices, pw, r.out_off + p * c.qb});
                 for (uint32_t sidx = 0; sidx < c.slices; ++sidx) {
                     const uint32_t i0 = sidx * c.slice_items;
                     const uint32_t ni = std::min(c.slice_items, items - i0);
@@ -359,7 +362,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
                 const uint64_t items = (uint64_t)n * sh.np * sh.groups;
                 const uint32_t cost = (uint32_t)(((items + sh.threads - 1) / sh.threads) * sh.epg);
                 g->tiles.push_back(
-                    {cost, BatchTile{r.ch, n, slot0 + p, (r.out_off + p * c.qb) / 4, 0, 0}});
+                    {cost, BatchTile{r.ch, n, slot0 + p, r.out_off + p * c.qb, 0, 0}});
             }
         }
     }
@@ -371,9 +374,9 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
         std::stable_sort(gr.tiles.begin(), gr.tiles.end(),
                          [](const std::pair<uint32_t, BatchTile>& a,
                             const std::pair<uint32_t, BatchTile>& b) { return a.first > b.first; });
-        Group g{gr.bw, gr.threads, t_off, (uint32_t)gr.tiles.size(), gr.lds, 0};
+        Group g{gr.bw, gr.threads, gr.padded, t_off, (uint32_t)gr.tiles.size(), gr.lds, 0};
         for (size_t i = 0; i < gr.tiles.size(); ++i) ht[t_off + i] = gr.tiles[i].second;
-        int per_cu = occupancy(s, g.bw, g.threads, g.lds_bytes);
+        int per_cu = occupancy(s, g.bw, g.threads, g.padded, g.lds_bytes);
         if (s->cfg.wg_per_cu && (int)s->cfg.wg_per_cu < per_cu) {
             // at most wg_per_cu groups per CU: ask for just over 1/(k+1) of the
             // CU's LDS, so the dispatcher cannot stack more groups on one CU
@@ -420,7 +423,8 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     for (size_t gi = 0; gi < sl.groups.size() && e == hipSuccess; ++gi) {
         const Group& g = sl.groups[gi];
         e = qext::launch_batch_noreset(
-            g.bw, g.threads, reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
+            g.bw, g.threads, g.padded != 0,
+            reinterpret_cast<const BatchStream*>(sl.d_in + s->off_streams),
             reinterpret_cast<const BatchTile*>(sl.d_in + s->off_tiles) + g.tile_off, g.n_tiles,
             reinterpret_cast<uint32_t*>(sl.d_in + s->off_heads) + gi, sl.d_part, g.grid,
             g.lds_bytes, s->stream);
@@ -636,7 +640,7 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     uint32_t slices = 1, slice_items = 0;
     {
         const uint64_t items = (uint64_t)shape.np * n_e;
-        if (s->cfg.split_pairs && items > shape.threads) {
+        if (s->cfg.split_pairs && items > shape.threads && !shape.padded) {
             // per <= threads items per slice; every slice but the last holds
             // exactly per, the last at least one
             const uint64_t per = (items + (items + shape.threads - 1) / shape.threads - 1) /

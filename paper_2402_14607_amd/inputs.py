@@ -9,7 +9,8 @@ Distributions (the paper's raw data come from a homodyne QRNG, Sec. 4.2;
 none ships with the paper, so these stand in for it):
 
 * i.i.d. discretised Gaussian: round(N(mean, sigma^2)), half-to-even, clipped
-  to [0, 255] -- an i.i.d. source is a forward block source (Sec. 3.1).
+  to [0, 255] -- an i.i.d. source is a forward block source (Sec. 3.1); and
+  the same with 16-bit samples for the paper's own parameter point.
 * AR(1): u_t = phi * u_{t-1} + e_t with e_t ~ N(0, sigma^2) and u_0 drawn from
   the stationary law N(0, sigma^2 / (1 - phi^2)); sample = clip(round(offset +
   u_t)).  Successive samples, hence successive blocks, are correlated.
@@ -63,6 +64,23 @@ def ar1_adc(n_samples: int, seed: int, phi: float = 0.1, sigma: float = 20.0,
     return out
 
 
+def gaussian_adc16(n_samples: int, seed: int, mean: float = 32768.0, sigma: float = 682.0,
+                   chunk: int = 1 << 23) -> np.ndarray:
+    """n_samples 16-bit samples round(N(mean, sigma^2)) clipped to [0, 65535],
+    as their little-endian bytes (2 * n_samples uint8).  sigma = 682 gives a
+    min-entropy of about 10.74 bits per sample, the rate of the paper's
+    homodyne source (Sec. 4.2): -log2 of the most likely value's probability,
+    1 / (sigma * sqrt(2 pi))."""
+    rng = _rng(seed)
+    out = np.empty(n_samples, dtype="<u2")
+    for s in range(0, n_samples, chunk):
+        k = min(chunk, n_samples - s)
+        v = rng.normal(mean, sigma, k)
+        np.clip(np.rint(v), 0, 65535, out=v)
+        out[s:s + k] = v.astype("<u2")
+    return out.view(np.uint8)
+
+
 @dataclass
 class StreamPair:
     """One (X, Y) source pair with its block shape."""
@@ -105,6 +123,15 @@ def forward_block_stress(n_pairs: int = 16384) -> StreamPair:
     """n = 65536, m = 16384, 16384 pairs (128 MiB per source), AR(1) with
     phi = 0.1, seeds 21 and 22."""
     return plain_workload(65536, 16384, n_pairs, 21, 22, kind="ar1")
+
+
+def paper_point(n_pairs: int = 262144) -> StreamPair:
+    """The paper's own parameter point (Sec. 4.2): n_e = 71 elements of
+    F_2^80 per block (n = 5680 bits = 355 samples of b = 16 bits), m = 80;
+    16-bit Gaussian samples as in gaussian_adc16, seeds 31 and 32."""
+    n, m = 71 * 80, 80
+    samples = n_pairs * n // 16
+    return StreamPair(n, m, gaussian_adc16(samples, 31), gaussian_adc16(samples, 32))
 
 
 BATCHED_N_CHOICES = (2048, 4096, 8192, 16384, 32768)

@@ -35,6 +35,12 @@ def say(msg):
     print(msg, flush=True)
 
 
+def to_dev(dev, arr):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+
+
 def gpu_extract(dev, x_np, y_np, n_bits, m_bits, n_pairs=None, taps=None, ex=None):
     import torch
 
@@ -157,6 +163,86 @@ def test_shapes_full(dev, m, n_e):
     assert np.array_equal(got, oracle.ext_blocks(x, y, n, m))
 
 
+# degrees that are not multiples of 32: elements sit at byte (not word)
+# offsets, are re-laid out in zero-padded 32-bit slots, and outputs are
+# q/8 bytes per pair at byte offsets
+PADDED_SHAPES = [(8, 4), (24, 3), (40, 7), (80, 4), (80, 71), (88, 5), (104, 9), (200, 3),
+                 (1000, 4), (1016, 2)]
+
+
+@pytest.mark.parametrize("m,n_e", PADDED_SHAPES, ids=lambda v: str(v))
+def test_padded_shapes_full(dev, m, n_e):
+    """Full compare against the oracle, with canary bytes after the output
+    (no store may pass the last pair's q/8 bytes)."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(3000 + m + n_e))
+    n = m * n_e
+    pairs = int(rng.integers(1, 40)) if m < 1000 else 3
+    x = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    y = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    say("padded shape m=%d n_e=%d, %d pairs, full compare" % (m, n_e, pairs))
+    qb = m // 8
+    out = torch.full((pairs * qb + 64,), 0xA5, dtype=torch.uint8, device=dev)
+    with binding.Extractor(n, m, device_memory=True,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        say(ex.describe())
+        ex.extract(to_dev(dev, x), to_dev(dev, y), out, pairs)
+        ex.sync()
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:pairs * qb], oracle.ext_blocks(x, y, n, m))
+    assert np.all(got[pairs * qb:] == 0xA5)
+
+
+def test_paper_point_sampled(dev):
+    """The paper's parameter point, n_e = 71 elements of F_2^80 over 16-bit
+    Gaussian samples, 262144 pairs in one launch: sampled pairs against the
+    oracle, plus the first 300 pairs in full."""
+    import torch
+
+    w = inputs.paper_point()
+    say("paper point n=5680 m=80, %d pairs" % w.n_pairs)
+    x, y = to_dev(dev, w.x), to_dev(dev, w.y)
+    out = torch.zeros(w.n_pairs * 10, dtype=torch.uint8, device=dev)
+    with binding.Extractor(5680, 80, device_memory=True, sample_bits=16,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        say(ex.describe())
+        ex.extract(x, y, out, w.n_pairs)
+        ex.sync()
+    got = out.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(71))
+    idx = np.unique(np.concatenate([[0, w.n_pairs - 1],
+                                    rng.integers(0, w.n_pairs, 30)])).astype(np.uint64)
+    want = oracle.ext_sampled(w.x, w.y, idx, 5680, 80)
+    g = np.concatenate([got[int(i) * 10:(int(i) + 1) * 10] for i in idx])
+    assert np.array_equal(g, want)
+    assert np.array_equal(got[:3000], oracle.ext_blocks(w.x[:300 * 710], w.y[:300 * 710], 5680, 80))
+
+
+def test_paper_point_streaming_chunks(dev):
+    """Streaming form at q = 80 (710-byte blocks) with chunk lengths that
+    split samples and blocks anywhere, host and device memory: equal to the
+    oracle over the whole stream."""
+    w = inputs.plain_workload(5680, 80, 60, 41, 42)
+    want = oracle.ext_blocks(w.x, w.y, 5680, 80)
+    rng = np.random.Generator(np.random.PCG64(8))
+
+    def split(total, maxc):
+        out = []
+        while total:
+            c = int(min(total, rng.integers(1, maxc)))
+            out.append(c)
+            total -= c
+        return out
+
+    for device_memory in (False, True):
+        say("paper-point stream, device_memory=%s" % device_memory)
+        got, dropped, _ = run_stream(dev, w, split(w.x.size, 1500), split(w.y.size, 4000),
+                                     device_memory=device_memory)
+        assert np.array_equal(got, want)
+        assert dropped == 0
+
+
 def test_custom_taps(dev):
     # another irreducible pentanomial of degree 256 (checked by the oracle)
     m, n_e = 256, 4
@@ -219,7 +305,7 @@ def test_zero_pairs_and_errors(dev):
             ex.extract(x[1:], x, out, 1)  # misaligned
         assert e.value.code == binding.EXT_EINVAL
     with pytest.raises(binding.ExtError) as e:
-        binding.Extractor(5680, 80)       # m not a multiple of 32: not on this path
+        binding.Extractor(48, 12, sample_bits=4)  # m not a multiple of 8: not on this path
     assert e.value.code == binding.EXT_ENOTSUP
     with pytest.raises(binding.ExtError) as e:
         binding.Extractor(1000, 256)      # n not a multiple of m

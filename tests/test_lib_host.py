@@ -33,6 +33,15 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(binding.EXPORTED)
 
 
+def test_default_modulus_every_byte_multiple_degree():
+    """Degrees 8, 16, ..., 1024 (the byte-granular fields of the paper's
+    parameter rule with b = 8 or 16): the library's own search agrees with
+    the oracle's table."""
+    table = oracle._read_table()
+    for m in range(8, 1025, 8):
+        assert binding.default_modulus(m) == table[m], m
+
+
 def test_default_modulus_matches_oracle_table():
     table = oracle._read_table()
     for m in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384):
