@@ -122,6 +122,32 @@ int ext_default_modulus(uint32_t m_bits, uint32_t *exps, uint32_t cap, uint32_t 
 int ext_is_irreducible(uint32_t m_bits, const uint32_t *taps, uint32_t n_taps);
 
 /*
+ * Growing blocks (Algorithm 2): block l (from 0) holds q_l * n_e bits of each
+ * source, right after block l-1, with q_l = q1 + l * delta_steps * b (b =
+ * p->sample_bits), and yields Ext_IP^{n_e, q_l} of the two blocks, q_l bits,
+ * outputs concatenated (block l's q_l/8 bytes right after block l-1's).
+ * delta_steps = 0 is Algorithm 1.  Each degree uses the conventional modulus
+ * (p->n_taps must be 0); q1 and delta_steps * b must be multiples of 8, and
+ * q1 a multiple of b.
+ */
+typedef struct ext_growing ext_growing;
+int ext_growing_create(uint32_t n_e, uint32_t q1, uint32_t delta_steps, const ext_params *p,
+                       ext_growing **out);
+/* How many whole blocks the first n_bytes of each source hold, and their
+ * input bytes (per source) and output bytes (any pointer may be NULL). */
+int ext_growing_blocks(const ext_growing *g, uint64_t n_bytes, uint64_t *k_blocks,
+                       uint64_t *in_bytes, uint64_t *out_bytes);
+/* Blocks 0 .. k-1 of the streams x and y (n_bytes each, from block 0; k =
+ * the whole blocks they hold, at most max_blocks) into out (out_cap bytes, at
+ * least the k blocks' output bytes, else EXT_EINVAL); *n_blocks = k.  Memory
+ * kind and stream as for ext_extract; returns after the outputs are written.
+ * EXT_ENOTSUP if some q_l has no conventional modulus in reach (q_l > 4096
+ * outside the built-in table) or no launch plan. */
+int ext_growing_extract(ext_growing *g, const void *x, const void *y, uint64_t n_bytes,
+                        uint64_t max_blocks, void *out, uint64_t out_cap, uint64_t *n_blocks);
+int ext_growing_destroy(ext_growing *g);
+
+/*
  * Parameters and security bounds (host only, no GPU work).
  *
  * ext_choose_params: Algorithm 1's rule for two (b, N, delta) forward block

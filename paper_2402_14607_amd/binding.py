@@ -35,6 +35,7 @@ EXPORTED = (
     "ext_server_submit", "ext_server_poll", "ext_server_close", "ext_server_stats_get",
     "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
     "ext_choose_params", "ext_block_error_log2", "ext_stream_error_log2", "ext_output_bits",
+    "ext_growing_create", "ext_growing_blocks", "ext_growing_extract", "ext_growing_destroy",
 )
 
 EXT_SIM_SERVED = 0
@@ -199,6 +200,11 @@ def load() -> ctypes.CDLL:
                                                  ctypes.POINTER(ctypes.c_double),
                                                  ctypes.POINTER(ctypes.c_double)]),
         "ext_output_bits": (ctypes.c_int, [u32, u32, u32, u64, u64p]),
+        "ext_growing_create": (ctypes.c_int, [u32, u32, u32, ctypes.POINTER(ExtParams),
+                                              ctypes.POINTER(vp)]),
+        "ext_growing_blocks": (ctypes.c_int, [vp, u64, u64p, u64p, u64p]),
+        "ext_growing_extract": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
+        "ext_growing_destroy": (ctypes.c_int, [vp]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
         "ext_server_destroy": (ctypes.c_int, [vp]),
         "ext_serve_simulate": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult),
@@ -590,3 +596,41 @@ def output_bits(q1: int, delta_steps: int, sample_bits: int, k: int) -> int:
     m = ctypes.c_uint64()
     _check(lib.ext_output_bits(q1, delta_steps, sample_bits, k, ctypes.byref(m)), "ext_output_bits")
     return m.value
+
+
+class Growing:
+    """One ext_growing: Algorithm 2's growing blocks (q_l = q1 + l * delta_steps * b)."""
+
+    def __init__(self, n_e: int, q1: int, delta_steps: int, *, sample_bits: int = 8,
+                 device_memory: bool = True, stream=None, device: int = -1):
+        self.lib = load()
+        p = make_params(self.lib, device_memory=device_memory, stream=stream,
+                        sample_bits=sample_bits, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_growing_create(n_e, q1, delta_steps, ctypes.byref(p),
+                                           ctypes.byref(self.handle)), "ext_growing_create")
+
+    def blocks(self, n_bytes: int) -> tuple[int, int, int]:
+        """(whole blocks in n_bytes per source, their input bytes, output bytes)."""
+        k, i, o = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.ext_growing_blocks(self.handle, n_bytes, ctypes.byref(k), ctypes.byref(i),
+                                           ctypes.byref(o)), "ext_growing_blocks")
+        return k.value, i.value, o.value
+
+    def extract(self, x, y, n_bytes: int, out, out_cap: int, max_blocks: int = 2 ** 64 - 1) -> int:
+        k = ctypes.c_uint64()
+        _check(self.lib.ext_growing_extract(self.handle, _ptr(x), _ptr(y), n_bytes, max_blocks,
+                                            _ptr(out), out_cap, ctypes.byref(k)),
+               "ext_growing_extract")
+        return k.value
+
+    def close(self):
+        if self.handle:
+            self.lib.ext_growing_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

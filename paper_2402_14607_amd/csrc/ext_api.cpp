@@ -31,13 +31,18 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     if ((uint64_t)n_e * q / 8 > 0xffffffffull) return false;
     const uint32_t target = knobs.base_words ? knobs.base_words : 8u;
     if (target > (uint32_t)kMaxBaseWords) return false;
-    // a degree that is not a multiple of 32 is computed in qw-word slots,
-    // zero above bit q (the product of padded operands is the same polynomial)
-    const bool padded = (q % 32) != 0;
-    const uint32_t qw = (q + 31) / 32;
+    // Word-aligned elements are multiplied in place when their word count has
+    // an odd part the base products cover (<= 15).  Otherwise (q not a
+    // multiple of 32, or such a word count, or asked for) elements are
+    // computed in zero-padded slots of qw words, the least count >= q/32
+    // whose odd part is covered: the product of padded operands is the same
+    // polynomial.
+    auto odd_ok = [](uint32_t w) { return (w >> __builtin_ctz(w)) <= 15u; };
+    uint32_t qw = (q + 31) / 32;
+    const bool padded = (q % 32) != 0 || knobs.padded != 0 || !odd_ok(qw);
+    while (!odd_ok(qw)) ++qw;
     const uint32_t v = (uint32_t)__builtin_ctz(qw);
     const uint32_t odd = qw >> v;
-    if (odd > 15) return false;
     // base size: odd * 2^k words, the largest instantiated one not above the
     // target (or the odd part itself when that is already larger)
     uint32_t bw = odd, levels = v;

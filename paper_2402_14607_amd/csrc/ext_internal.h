@@ -47,6 +47,8 @@ struct PlanKnobs {
     uint32_t groups;      // element groups per work item (divides n_e)
     uint32_t ppw;         // block pairs per work-group
     uint32_t threads;     // work-group size (256 or 1024)
+    uint32_t padded;      // 1: use the padded layout even when q is a multiple of 32
+                          // (byte-granular blocks and outputs)
 };
 
 // Fills *s for q, n_e and the taps; returns false if the shape is outside

@@ -274,13 +274,18 @@ __device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* 
 #pragma unroll
     for (uint32_t r = 0; r < kPadRegs; ++r) {
         if (tid + r * nt < total) {
-            const uint32_t o = j * sh.nbytes + e * qb + 4u * w;  // byte in the region
-            const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
-            const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
-            const uint32_t ox = o + lead_x, oy = o + lead_y;
-            const uint32_t ax = ox >> 2, sx = (ox & 3u) * 8u, ay = oy >> 2, sy = (oy & 3u) * 8u;
-            hx[r] = (sx ? funnel(raw_x[ax + 1], raw_x[ax], sx) : raw_x[ax]) & keep;
-            hy[r] = (sy ? funnel(raw_y[ay + 1], raw_y[ay], sy) : raw_y[ay]) & keep;
+            if (4u * w < qb) {
+                const uint32_t o = j * sh.nbytes + e * qb + 4u * w;  // byte in the region
+                const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
+                const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
+                const uint32_t ox = o + lead_x, oy = o + lead_y;
+                const uint32_t ax = ox >> 2, sx = (ox & 3u) * 8u, ay = oy >> 2, sy = (oy & 3u) * 8u;
+                hx[r] = (sx ? funnel(raw_x[ax + 1], raw_x[ax], sx) : raw_x[ax]) & keep;
+                hy[r] = (sy ? funnel(raw_y[ay + 1], raw_y[ay], sy) : raw_y[ay]) & keep;
+            } else {  // a slot word above the element's bytes
+                hx[r] = 0u;
+                hy[r] = 0u;
+            }
         }
         j += dj;
         e += de;
@@ -306,7 +311,7 @@ __device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* 
     __syncthreads();
 }
 
-// reduce_store for q not a multiple of 32: C_hi = C >> q is first gathered
+// reduce_store for padded shapes (q need not be a multiple of 32): C_hi = C >> q is first gathered
 // into hs (qw words per pair) with funnel shifts, the folding passes are the
 // same, the result is masked to q bits and stored as q/8 bytes per pair at
 // outb (any alignment).  Ends after the last global store, without a barrier.
@@ -338,9 +343,13 @@ __device__ __forceinline__ void reduce_store_padded(const ExtShape& sh, const ui
         ds[j * dn + k] = d;
     }
     __syncthreads();
-    const uint32_t last_mask = (1u << r) - 1u;  // r != 0 on this path
+    // words at or above bit q are not stored; the word holding bit q-1 is
+    // masked to it
+    const uint32_t q_words = (sh.q + 31u) >> 5;
+    const uint32_t last_mask = r ? (1u << r) - 1u : ~0u;
     for (uint32_t i = tid; i < npw * qw; i += nt) {
         const uint32_t j = i / qw, w = i - j * qw;
+        if (w >= q_words) continue;
         const uint32_t* hi = hs + j * qw;
         const uint32_t* dd = ds + j * dn;
         uint32_t z = cs[j * cw + w] ^ hi[w] ^ (w < dn ? dd[w] : 0u);
@@ -355,7 +364,7 @@ __device__ __forceinline__ void reduce_store_padded(const ExtShape& sh, const ui
             const uint32_t d0 = (src >= 1 && (uint32_t)(src - 1) < dn) ? dd[src - 1] : 0u;
             z ^= eb ? funnel(d1, d0, 32u - eb) : d1;
         }
-        if (w == qw - 1) z &= last_mask;
+        if (w == q_words - 1) z &= last_mask;
         uint8_t* o = outb + (uint64_t)j * sh.qbytes + 4u * w;
         const uint32_t cnt = sh.qbytes - 4u * w < 4u ? sh.qbytes - 4u * w : 4u;
         for (uint32_t b = 0; b < cnt; ++b) o[b] = (uint8_t)(z >> (8u * b));

@@ -165,9 +165,11 @@ def test_shapes_full(dev, m, n_e):
 
 # degrees that are not multiples of 32: elements sit at byte (not word)
 # offsets, are re-laid out in zero-padded 32-bit slots, and outputs are
-# q/8 bytes per pair at byte offsets
+# q/8 bytes per pair at byte offsets; and multiples of 32 whose word count
+# has an odd part above 15 (544 = 17 words, 1056 = 33 words), computed in
+# wider zero-padded slots (18 and 36 words)
 PADDED_SHAPES = [(8, 4), (24, 3), (40, 7), (80, 4), (80, 71), (88, 5), (104, 9), (200, 3),
-                 (1000, 4), (1016, 2)]
+                 (1000, 4), (1016, 2), (544, 3), (1056, 2)]
 
 
 @pytest.mark.parametrize("m,n_e", PADDED_SHAPES, ids=lambda v: str(v))
