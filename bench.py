@@ -214,6 +214,55 @@ def paper_point_leg(dev, stream, steps: int, warmup: int):
     }
 
 
+def growing_leg(dev, stream, steps: int, warmup: int):
+    """Algorithm 2 at the paper's rate point: n_e = 71 elements per block,
+    q_l = 80 + 16 l (Delta = 1, b = 16), the first 64 blocks (q up to 1088) of
+    16-bit Gaussian streams per call; every block checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import params as orc_params
+    from paper_2402_14607_amd import binding, inputs
+
+    n_e, q1, dsteps, b, k = 71, 80, 1, 16, 64
+    sched = orc_params.schedule(q1, dsteps, b, n_e, k)
+    n_bytes = (sched[-1][0] + sched[-1][1]) * b // 8
+    xh = inputs.gaussian_adc16(n_bytes // 2, 33)
+    yh = inputs.gaussian_adc16(n_bytes // 2, 34)
+    x = torch.from_numpy(xh).to(dev)
+    y = torch.from_numpy(yh).to(dev)
+    with binding.Growing(n_e, q1, dsteps, sample_bits=b, stream=stream.cuda_stream) as g:
+        kk, nin, nout = g.blocks(n_bytes)
+        out = torch.empty(nout, dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            g.extract(x, y, n_bytes, out, nout)
+        torch.cuda.synchronize()
+        import time
+
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.extract(x, y, n_bytes, out, nout)  # returns after the outputs are written
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+    got = out.cpu().numpy()
+    want = np.concatenate([oracle.ext_blocks(xh[s * 2:(s + z) * 2], yh[s * 2:(s + z) * 2],
+                                             q * n_e, q) for s, z, q in sched])
+    parity = "bit-exact on all %d blocks" % kk if np.array_equal(got, want) else "MISMATCH"
+    bitmacs = sum(n_e * q * q for _, _, q in sched)
+    log("growing leg: %.3f ms per call, %s" % (ms, parity))
+    return {
+        "workload": "Algorithm 2: n_e=71, q_l = 80 + 16 l for the first 64 blocks (q up to 1088), "
+                    "16-bit Gaussian samples, seeds 33/34",
+        "ms_per_call": round(ms, 4),
+        "output_gbps": round(nout * 8 / (ms * 1e-3) / 1e9, 4),
+        "input_gbps": round(2 * nin * 8 / (ms * 1e-3) / 1e9, 4),
+        "roofline_frac": round(bitmacs / (ms * 1e-3) / 1e12 / PEAK_BITMAC_T, 5),
+        "timing": "host wall clock per call (planning, copies of the launch tables, launches, "
+                  "wait for the outputs)",
+        "parity": parity,
+    }
+
+
 def served_leg(w, duration_s: float, warmup_s: float, modes=("served", "plain",
                                                              "plain_at_1/16_load"),
                wg_per_cu: int = 0, max_inflight: int = 0, split_pairs: int = -1,
@@ -291,6 +340,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-point", action="store_true")
+    ap.add_argument("--no-growing", action="store_true", help="skip the Algorithm 2 leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -391,6 +441,10 @@ def main():
         paper_point = paper_point_leg(dev, stream, steps=max(5, min(50, args.steps // 4)),
                                       warmup=3)
 
+    growing = None
+    if not args.no_growing:
+        growing = growing_leg(dev, stream, steps=10, warmup=2)
+
     served = None
     if not args.no_served:
         served = served_leg(w, duration_s=args.serve_seconds, warmup_s=1.0,
@@ -443,6 +497,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "paper_point": paper_point,
+        "growing": growing,
         "served": served,
         "context": "paper's simulated FPGA rate: 64 Gbps output (Xilinx Kintex-7 XC7K480T, "
                    "200 MHz, n=71 elements of F_2^80); a different shape, not a target",
