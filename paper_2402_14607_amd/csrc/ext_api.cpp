@@ -377,9 +377,10 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
     snprintf(buf, cap,
              "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"base_bits\": %u, \"karatsuba_levels\": %u, "
              "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
-             "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d}",
+             "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d, \"padded\": %u, "
+             "\"slot_words\": %u}",
              (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
-             s.groups, s.stage, s.lds_words * 4, s.threads);
+             s.groups, s.stage, s.lds_words * 4, s.threads, s.padded, s.qw);
     return EXT_OK;
 }
 

@@ -383,9 +383,10 @@ int ext_batch_describe(const ext_batch* b, char* buf, size_t cap) {
     for (size_t i = 0; i < b->groups.size() && n < cap; ++i) {
         const auto& g = b->groups[i];
         n += (size_t)snprintf(buf + n, cap - n,
-                              "%s{\"base_bits\": %u, \"threads\": %u, \"tiles\": %u, \"grid\": %u, "
-                              "\"lds_bytes\": %u}",
-                              i ? ", " : "", g.bw * 32, g.threads, g.n_tiles, g.grid, g.lds_bytes);
+                              "%s{\"base_bits\": %u, \"threads\": %u, \"padded\": %u, "
+                              "\"tiles\": %u, \"grid\": %u, \"lds_bytes\": %u}",
+                              i ? ", " : "", g.bw * 32, g.threads, g.padded, g.n_tiles, g.grid,
+                              g.lds_bytes);
     }
     if (n < cap) snprintf(buf + n, cap - n, "]}");
     return EXT_OK;

@@ -67,7 +67,9 @@ def make_items(dev, specs, seed):
 
 MIXED = [(2048, 512, 17), (4096, 1024, 5), (8192, 2048, 9), (16384, 4096, 3), (32768, 8192, 2),
          (1024, 256, 40), (384, 96, 33), (96 * 5, 96, 7), (2048, 2048, 4), (8192, 512, 6),
-         (2048, 512, 0), (65536, 16384, 1)]
+         (2048, 512, 0), (65536, 16384, 1),
+         # padded fields (byte-granular blocks): the paper's point and two more
+         (71 * 80, 80, 23), (3 * 40, 40, 50), (2 * 544, 544, 3)]
 
 
 def test_mixed_batch_against_oracle(dev):
@@ -76,7 +78,7 @@ def test_mixed_batch_against_oracle(dev):
     with binding.Batch(items) as b:
         desc = json.loads(b.describe())
         assert desc["graph"] is True
-        assert len(desc["launches"]) >= 2  # 256-bit base and the 96-bit stream's own base
+        assert len(desc["launches"]) >= 3  # 256-bit base, the 96-bit base, padded launches
         b.run()
         b.sync()
         for (n, m, x, y, out, pairs), (xh, yh) in zip(items, host):

@@ -57,7 +57,8 @@ def drain(srv, chans, expect_bytes, timeout_s=30.0):
 
 
 SHAPES = [(1024, 256, "gaussian"), (8192, 2048, "gaussian"), (2048, 512, "gaussian"),
-          (65536, 16384, "ar1"), (480, 96, "gaussian"), (32768, 8192, "gaussian")]
+          (65536, 16384, "ar1"), (480, 96, "gaussian"), (32768, 8192, "gaussian"),
+          (5680, 80, "gaussian")]  # the paper's point: 710-byte blocks, 10-byte outputs
 
 
 def test_server_interleaved_random_chunks(dev):
