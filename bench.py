@@ -177,8 +177,10 @@ def paper_point_leg(dev, stream, steps: int, warmup: int):
     x = torch.from_numpy(w.x).to(dev)
     y = torch.from_numpy(w.y).to(dev)
     out = torch.empty(pairs * m // 8, dtype=torch.uint8, device=dev)
-    ex = binding.Extractor(n, m, device_memory=True, sample_bits=16, stream=stream.cuda_stream)
+    ex = binding.Extractor(n, m, device_memory=True, sample_bits=16, stream=stream.cuda_stream,
+                           autotune=True)
     plan = json.loads(ex.describe())
+    log("paper-point leg: autotuned plan %s" % json.dumps(plan))
     for _ in range(warmup):
         ex.extract(x, y, out, pairs)
     torch.cuda.synchronize()
