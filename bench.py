@@ -460,6 +460,13 @@ def main():
     bitmacs = N_PAIRS * N_BITS * M_BITS  # n*m bit-MACs per pair, schoolbook count
     achieved = bitmacs / sec / 1e12
     traffic = measured_traffic()
+    # VALU issue utilisation: the launch's VALU instructions (rocprofv3
+    # summary of this kernel source) against the rate the chip delivers now
+    valu_rate = binding.probe_valu_rate()
+    valu_insts = profile_value(VALU_FILE, "valu_insts_per_launch")
+    valu_frac = (round(valu_insts * 64 / (valu_rate * sec), 4)
+                 if valu_insts and valu_rate > 0 else None)
+    log("VALU probe: %.4e lane-ops/s; issue utilisation %s" % (valu_rate, valu_frac))
     res = {
         "metric": "extracted output Gbps at n=8192 (bit-exact); p99 per-block latency when "
                   "streaming",
@@ -489,12 +496,14 @@ def main():
             "unit": "Tbit-MAC/s",
             "frac": round(achieved / PEAK_BITMAC_T, 4),
             "traffic": traffic,
-            "valu_issue_frac": profile_value(VALU_FILE, "valu_issue_frac_measured_peak"),
+            "valu_issue_frac": valu_frac,
+            "valu_probe_lane_ops_per_s": round(valu_rate, -9),
             "note": "achieved counts the schoolbook n*m bit-MACs per pair; peak is one "
                     "32-bit AND-XOR (v_bitop3_b32) per lane per clock on every lane; the "
                     "kernel uses Karatsuba, so frac above 1 is possible; valu_issue_frac is "
-                    "the executed VALU instructions' issue time (rocprofv3 SQ_INSTS_VALU at "
-                    "the chip's measured v_bitop3_b32 rate) over the launch time",
+                    "the launch's VALU instructions (rocprofv3 SQ_INSTS_VALU, 64 lanes each) "
+                    "over what the chip's v_bitop3_b32 rate, probed in this run, issues in "
+                    "the launch time",
         },
         "cpu_baseline": cpu,
         "batched": batched,

@@ -421,6 +421,13 @@ int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t 
  * product size, Karatsuba levels, work-group shape) into buf. */
 int ext_describe(const ext_ctx *c, char *buf, size_t cap);
 
+/* Diagnostic: the device's measured issue rate of the extraction kernel's
+ * AND-XOR (v_bitop3_b32), in 32-bit lane operations per second, from a
+ * ~10 ms probe kernel of independent chains on every CU (device < 0: the
+ * current device).  Used to state a kernel's VALU issue utilisation against
+ * what the chip delivers at that moment. */
+int ext_probe_valu_rate(int device, double *lane_ops_per_s);
+
 /* Static description of a status code. */
 const char *ext_strerror(int code);
 

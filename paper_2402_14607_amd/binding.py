@@ -36,6 +36,7 @@ EXPORTED = (
     "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
     "ext_choose_params", "ext_block_error_log2", "ext_stream_error_log2", "ext_output_bits",
     "ext_growing_create", "ext_growing_blocks", "ext_growing_extract", "ext_growing_destroy",
+    "ext_probe_valu_rate",
 )
 
 EXT_SIM_SERVED = 0
@@ -205,6 +206,7 @@ def load() -> ctypes.CDLL:
         "ext_growing_blocks": (ctypes.c_int, [vp, u64, u64p, u64p, u64p]),
         "ext_growing_extract": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
         "ext_growing_destroy": (ctypes.c_int, [vp]),
+        "ext_probe_valu_rate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
         "ext_server_destroy": (ctypes.c_int, [vp]),
         "ext_serve_simulate": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult),
@@ -634,3 +636,11 @@ class Growing:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def probe_valu_rate(device: int = -1) -> float:
+    """The device's measured v_bitop3_b32 issue rate, lane-ops per second."""
+    lib = load()
+    r = ctypes.c_double()
+    _check(lib.ext_probe_valu_rate(device, ctypes.byref(r)), "ext_probe_valu_rate")
+    return r.value

@@ -384,6 +384,50 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
     return EXT_OK;
 }
 
+int ext_probe_valu_rate(int device, double* lane_ops_per_s) {
+    if (!lane_ops_per_s) return EXT_EINVAL;
+    *lane_ops_per_s = 0.0;
+    int dev = device;
+    if ((dev < 0 && hipGetDevice(&dev) != hipSuccess) || hipSetDevice(dev) != hipSuccess)
+        return EXT_EDEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return EXT_EDEVICE;
+    const uint32_t blocks = (uint32_t)cus * 32u, iters = 1000u;
+    uint32_t* out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = EXT_OK;
+    float best_ms = 0.f;
+    if (hipMalloc((void**)&out, (size_t)blocks * qext::kThreads * 4) != hipSuccess ||
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = EXT_EDEVICE;
+    }
+    // one warm-up run, then the fastest of three
+    for (int rep = 0; rep < 4 && rc == EXT_OK; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess ||
+            qext::launch_valu_probe(out, blocks, iters, st) != hipSuccess ||
+            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = EXT_EDEVICE;
+            break;
+        }
+        if (rep > 0 && (best_ms == 0.f || ms < best_ms)) best_ms = ms;
+    }
+    if (rc == EXT_OK && best_ms > 0.f)
+        *lane_ops_per_s = (double)blocks * qext::kThreads * iters * qext::kProbeOpsPerIter /
+                          (best_ms * 1e-3);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(out);
+    (void)hipGetLastError();
+    return rc;
+}
+
 int ext_sync(ext_ctx* c) {
     int rc = enter(c);
     if (rc) return rc;

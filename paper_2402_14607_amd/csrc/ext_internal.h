@@ -141,6 +141,11 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
                           const uint32_t* part, uint32_t grid, uint32_t lds_bytes,
                           hipStream_t stream);
 
+// Queue the VALU issue-rate probe: blocks x kThreads lanes, each running
+// iters * 16 * 9 VALU operations; out holds blocks * kThreads words.
+hipError_t launch_valu_probe(uint32_t* out, uint32_t blocks, uint32_t iters, hipStream_t stream);
+constexpr uint32_t kProbeOpsPerIter = 16 * 9;  // 8 AND-XORs and 1 funnel shift, 16 times
+
 // Resident work-groups per CU of the batched kernel at this LDS size.
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,
                            int* blocks_per_cu);

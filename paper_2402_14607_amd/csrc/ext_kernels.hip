@@ -646,6 +646,30 @@ stage_kernel(const uint8_t* __restrict__ src, const ScatterDesc* __restrict__ de
     }
 }
 
+// Issue-rate probe: every lane runs eight independent v_bitop3_b32 chains
+// (the extraction kernel's AND-XOR) plus one funnel shift per round of eight,
+// and writes one word, out[global id], so the work cannot be dropped.
+__global__ void __launch_bounds__(kThreads)
+valu_probe_kernel(uint32_t* __restrict__ out, uint32_t seed, uint32_t iters) {
+    const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+    uint32_t a[8], m = seed * gid + 0x9e3779b9u;
+    const uint32_t y = gid ^ 0x5bd1e995u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = gid + (uint32_t)j;
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = and_xor(m, y + (uint32_t)j, a[j]);
+            m = funnel(m, y, 1u);
+        }
+    }
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v ^= a[j];
+    out[gid] = v;
+}
+
 // Clears the queue head (a kernel, not a memset node, so that the pair can be
 // captured in a graph and replayed).
 __global__ void reset_head_kernel(uint32_t* head) {
@@ -758,6 +782,12 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
     if (grid == 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(combine_kernel, dim3(grid), dim3(kThreads), lds_bytes, stream, streams, jobs,
                        n_jobs, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_valu_probe(uint32_t* out, uint32_t blocks, uint32_t iters, hipStream_t stream) {
+    if (!out || blocks == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(valu_probe_kernel, dim3(blocks), dim3(kThreads), 0, stream, out, 7u, iters);
     return hipGetLastError();
 }
 
