@@ -88,8 +88,15 @@ typedef struct {
                                    time and keep the fastest (cached per shape) */
     uint32_t threads;           /* work-group size, 0 = 256; 1024 shortens the critical
                                    path of shapes with more than 256 items per pair */
-    uint32_t reserved[3];
+    uint32_t kernel;            /* plain and streaming forms: EXT_KERNEL_AUTO (default),
+                                   EXT_KERNEL_WORD (word-level Karatsuba kernel) or
+                                   EXT_KERNEL_BITSLICE (32 pairs per work-group bit-sliced
+                                   across pairs; fields of at most 128 bits, else
+                                   EXT_ENOTSUP).  Both give the same bytes; AUTO takes
+                                   the one that measures faster for the shape */
+    uint32_t reserved[2];
 } ext_params;
+enum { EXT_KERNEL_AUTO = 0, EXT_KERNEL_WORD = 1, EXT_KERNEL_BITSLICE = 2 };
 
 /* Fill *p with defaults (b = 8, conventional modulus, host memory, a stream
  * of the library's own, 256 MiB cap, current device). */

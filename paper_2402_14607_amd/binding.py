@@ -40,6 +40,7 @@ EXPORTED = (
 )
 
 EXT_SIM_SERVED = 0
+KERNEL_AUTO, KERNEL_WORD, KERNEL_BITSLICE = 0, 1, 2
 EXT_SIM_PLAIN = 1
 
 
@@ -64,7 +65,8 @@ class ExtParams(ctypes.Structure):
         ("pairs_per_group", ctypes.c_uint32),
         ("autotune", ctypes.c_uint32),
         ("threads", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("kernel", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 
@@ -258,7 +260,7 @@ def _ptr(buf) -> int:
 
 def make_params(lib, *, device_memory=True, stream=None, taps=None, sample_bits=8,
                 device_bytes_cap=0, device=-1, autotune=False, base_bits=0, groups=0,
-                pairs_per_group=0, threads=0) -> ExtParams:
+                pairs_per_group=0, threads=0, kernel=0) -> ExtParams:
     p = ExtParams()
     lib.ext_params_init(ctypes.byref(p))
     p.sample_bits = sample_bits
@@ -277,6 +279,7 @@ def make_params(lib, *, device_memory=True, stream=None, taps=None, sample_bits=
     p.base_bits = base_bits
     p.groups = groups
     p.pairs_per_group = pairs_per_group
+    p.kernel = kernel
     p.threads = threads
     return p
 
@@ -287,12 +290,12 @@ class Extractor:
     def __init__(self, n_bits: int, m_bits: int, *, device_memory: bool = True, stream=None,
                  taps=None, sample_bits: int = 8, device_bytes_cap: int = 0, device: int = -1,
                  autotune: bool = False, base_bits: int = 0, groups: int = 0,
-                 pairs_per_group: int = 0, threads: int = 0):
+                 pairs_per_group: int = 0, threads: int = 0, kernel: int = 0):
         self.lib = load()
         p = make_params(self.lib, device_memory=device_memory, stream=stream, taps=taps,
                         sample_bits=sample_bits, device_bytes_cap=device_bytes_cap,
                         device=device, autotune=autotune, base_bits=base_bits, groups=groups,
-                        pairs_per_group=pairs_per_group, threads=threads)
+                        pairs_per_group=pairs_per_group, threads=threads, kernel=kernel)
         self.n_bits = n_bits
         self.m_bits = m_bits
         self.device_memory = device_memory

@@ -137,6 +137,7 @@ struct ext_ctx {
     uint32_t b = 8;
     std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
     ExtShape shape{};
+    bool bitslice = false;  // plain/streaming launches take the bit-sliced kernel
     uint32_t mem_kind = EXT_MEM_HOST;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -215,10 +216,24 @@ int enter(ext_ctx* c) {
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
 int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
-    HIP_TRY(c, qext::launch_extract(c->shape, (const uint8_t*)x, (const uint8_t*)y, (uint8_t*)out,
-                                    n_pairs, c->stream));
+    if (c->bitslice)
+        HIP_TRY(c, qext::launch_bitslice(c->shape, (const uint8_t*)x, (const uint8_t*)y,
+                                         (uint8_t*)out, n_pairs, c->stream));
+    else
+        HIP_TRY(c, qext::launch_extract(c->shape, (const uint8_t*)x, (const uint8_t*)y,
+                                        (uint8_t*)out, n_pairs, c->stream));
     return EXT_OK;
 }
+
+// The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits (its
+// chunked planes stay below 64 KiB of LDS).
+bool bitslice_applies(const ExtShape& s) {
+    return s.q <= qext::kBitsliceMaxQ && s.q % 8 == 0 &&
+           (uint64_t)qext::bitslice_lds_words(s) * 4 <= 65536;
+}
+
+// EXT_KERNEL_AUTO's choice among the shapes the bit-sliced kernel applies to.
+bool bitslice_preferred(const ExtShape&) { return false; }
 
 }  // namespace
 
@@ -283,6 +298,7 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
     if (n_bits == 0 || m_bits == 0 || n_bits % m_bits || m_bits % b) return EXT_EINVAL;
     if (p->mem_kind != EXT_MEM_HOST && p->mem_kind != EXT_MEM_DEVICE) return EXT_EINVAL;
     if (n_bits / m_bits > 0xffffffffull) return EXT_EINVAL;
+    if (p->kernel > EXT_KERNEL_BITSLICE) return EXT_EINVAL;
     std::vector<uint32_t> taps;
     if (p->n_taps == 0) {
         try {
@@ -305,12 +321,36 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
     ExtShape shape;
     qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group, p->threads};
     if (p->base_bits % 32) return EXT_EINVAL;
-    if (!qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
-                          (uint32_t)taps.size(), knobs, &shape))
-        return EXT_ENOTSUP;
-
+    const uint32_t n_e = (uint32_t)(n_bits / m_bits);
+    const bool planned = qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(),
+                                          knobs, &shape);
+    bool bs = false;
+    if (p->kernel != EXT_KERNEL_WORD) {
+        // the bit-sliced kernel needs only the field, the element count and P
+        ExtShape bsh{};
+        bsh.q = m_bits;
+        bsh.n_e = n_e;
+        bsh.n_taps = (uint32_t)taps.size();
+        for (size_t k = 0; k < taps.size(); ++k) bsh.taps[k] = taps[k];
+        bsh.qbytes = m_bits / 8;
+        bsh.nbytes = (uint32_t)(n_bits / 8);
+        bsh.align = 1;  // byte gathers
+        bsh.threads = qext::kThreads;
+        bs = m_bits % 8 == 0 && n_bits / 8 <= 0xffffffffull && bitslice_applies(bsh) &&
+             (p->kernel == EXT_KERNEL_BITSLICE || bitslice_preferred(bsh));
+        if (bs) {
+            if (planned) {
+                shape.align = 1;
+            } else {
+                shape = bsh;
+            }
+        }
+    }
+    if (p->kernel == EXT_KERNEL_BITSLICE && !bs) return EXT_ENOTSUP;
+    if (!bs && !planned) return EXT_ENOTSUP;
     ext_ctx* c = new (std::nothrow) ext_ctx;
     if (!c) return EXT_ENOMEM;
+    c->bitslice = bs;
     c->n_bits = n_bits;
     c->m_bits = m_bits;
     c->b = b;
@@ -342,7 +382,7 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         delete c;
         return EXT_EDEVICE;
     }
-    if (p->autotune) {
+    if (p->autotune && !c->bitslice) {
         qext::PlanKnobs tuned;
         ExtShape ts;
         if (qext::autotune_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
@@ -378,9 +418,11 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
              "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"base_bits\": %u, \"karatsuba_levels\": %u, "
              "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
              "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d, \"padded\": %u, "
-             "\"slot_words\": %u}",
+             "\"slot_words\": %u, \"kernel\": \"%s\"}",
              (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
-             s.groups, s.stage, s.lds_words * 4, s.threads, s.padded, s.qw);
+             s.groups, s.stage,
+             c->bitslice ? qext::bitslice_lds_words(s) * 4 : s.lds_words * 4, s.threads,
+             s.padded, s.qw, c->bitslice ? "bitslice" : "word");
     return EXT_OK;
 }
 

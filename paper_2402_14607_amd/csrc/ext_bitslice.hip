@@ -1,0 +1,382 @@
+// ext_bitslice.hip -- bit-sliced kernel for small fields (q <= 128) with many
+// elements per block, such as the paper's own point (71 elements of F_2^80).
+//
+// A word-level product of q <= 128 bits spends most of its issue slots on
+// shifts and masks (a 96-bit schoolbook product: 7 of 19).  Here a work-group
+// takes 32 block pairs and transposes them so that bit p of a 32-bit "plane"
+// word belongs to pair p: plane (e, j) holds bit j of element e of all 32
+// pairs.  The carry-less product of every element pair is then
+//     c[t] ^= x[j] & y[t - j]      (one v_bitop3_b32 per (j, t), 32 pairs at once)
+// with no shift and no mask, summed over the elements as the paper's inner
+// product (Def. 3.2) asks, reduced modulo P plane by plane, and transposed
+// back into q-bit outputs.
+//
+// The 32 pairs' blocks are one contiguous region per side.  The elements are
+// taken in chunks of ec; for each chunk a work-group (256 lanes)
+//   1. stages the chunk's bytes of both sides in LDS as they are, with
+//      16-byte loads issued one chunk ahead (in flight during the products of
+//      the chunk before);
+//   2. transposes them: item (side, element, word w) gathers word w of the
+//      element of the 32 pairs, transposes the 32x32 bit matrix in registers
+//      and writes 32 planes (zero at or above q); Y planes have zero margins
+//      before (kYLo) and after (kYHi);
+//   3. multiplies: lane (16x16 tile position (j-block, t-block), element
+//      subset) accumulates the tile's 16 output planes in registers (x[j] for
+//      16 j, y[t - j] from a 31-plane window) over its elements of the chunk.
+// After the last chunk the lanes XOR their tiles into the shared sum C (LDS
+// atomics); then C is reduced modulo P, one output plane per lane (two
+// folding passes, taps below q/2); lane w transposes planes 32w .. 32w+31 back
+// into word w of the 32 outputs, and the work-group stores its npw*q/8 bytes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ext_internal.h"
+
+namespace qext {
+namespace {
+
+constexpr uint32_t kBsPairs = 32;   // pairs per work-group (bits of a plane)
+constexpr uint32_t kTile = 16;      // planes per tile side
+constexpr uint32_t kYLo = 16;       // zero Y planes before each element
+constexpr uint32_t kYHi = 32;       // zero Y planes after each element's jp planes
+
+__device__ __forceinline__ uint32_t bs_and_xor(uint32_t a, uint32_t b, uint32_t acc) {
+    return __builtin_amdgcn_bitop3_b32(a, b, acc, 0x6A);  // (a & b) ^ acc
+}
+
+// One block-swap step of the 32x32 transpose: for rows r with bit J clear,
+// the columns of row r with bit J set are exchanged with the columns of row
+// r + J with bit J clear (M selects the columns with bit J clear).  Steps of
+// 16 and 8 move whole bytes (one v_perm_b32 per row); the others take a
+// shift and a bit select (v_bitop3_b32 0xD8: (a & ~m) | (b & m)) per row.
+__device__ __forceinline__ uint32_t bs_select(uint32_t a, uint32_t b, uint32_t m) {
+    return __builtin_amdgcn_bitop3_b32(a, b, m, 0xD8);
+}
+
+template <int J, uint32_t M>
+__device__ __forceinline__ void transpose_step(uint32_t (&a)[32]) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+        if (r & J) continue;
+        const uint32_t lo = a[r], hi = a[r + J];
+        if constexpr (J == 16) {
+            a[r] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);      // lo.b0 lo.b1 hi.b0 hi.b1
+            a[r + J] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);  // lo.b2 lo.b3 hi.b2 hi.b3
+        } else if constexpr (J == 8) {
+            a[r] = __builtin_amdgcn_perm(hi, lo, 0x06020400u);      // lo.b0 hi.b0 lo.b2 hi.b2
+            a[r + J] = __builtin_amdgcn_perm(hi, lo, 0x07030501u);  // lo.b1 hi.b1 lo.b3 hi.b3
+        } else {
+            a[r] = bs_select(lo, hi << J, M << J);
+            a[r + J] = bs_select(hi, lo >> J, M);
+        }
+    }
+}
+
+// In place: on entry bit c of a[r] is element (r, c); on exit bit r of a[c]
+// is element (r, c).
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+    transpose_step<16, 0x0000FFFFu>(a);
+    transpose_step<8, 0x00FF00FFu>(a);
+    transpose_step<4, 0x0F0F0F0Fu>(a);
+    transpose_step<2, 0x33333333u>(a);
+    transpose_step<1, 0x55555555u>(a);
+}
+
+// (hi:lo) >> (s mod 32); s = 0 gives lo
+__device__ __forceinline__ uint32_t bs_funnel(uint32_t hi, uint32_t lo, uint32_t s) {
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+}
+
+// Bytes [16k - lead, 16k - lead + 16) of the region [src, src + len)
+// (lead = src & 15) one by one, zero outside it: for the units that straddle
+// an end of the region, so that no access leaves it.
+__device__ __forceinline__ uint4 bs_edge_unit(const uint8_t* __restrict__ src, uint32_t len,
+                                           uint32_t lead, uint32_t k) {
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t b = 0; b < 16u; ++b) {
+        const uint32_t rb = 16u * k + b;
+        if (rb >= lead && rb < lead + len) v[b >> 2] |= (uint32_t)src[rb - lead] << (8u * (b & 3u));
+    }
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+constexpr uint32_t kElemsPerLane = 2;  // elements per product lane per chunk
+constexpr uint32_t kStageRegs = 4;     // 16-byte staging loads per lane per chunk
+constexpr uint32_t kChunkBytes = 224;  // most bytes of one pair's chunk (units <= 16)
+constexpr uint32_t kChunkElems = 128;  // most elements per chunk (LDS stays below 56 KiB)
+constexpr uint32_t kPadBlock = kTile + 1;  // LDS words per 16 planes (one pad word)
+
+// LDS word of plane m of an element laid out in blocks of 16 planes and one
+// pad word: tiles of different j-blocks, t-blocks and elements fall in
+// different banks.
+__host__ __device__ constexpr uint32_t bs_pad(uint32_t m) { return kPadBlock * (m >> 4) + (m & 15u); }
+
+// Geometry of the kernel for (q, n_e) and a work-group of nt lanes; the host
+// sizes LDS with the same function.  Elements are processed in chunks of ec:
+// each chunk's bytes are staged raw, transposed into planes, multiplied.
+struct BsGeom {
+    uint32_t qb, qw, jp, xs, ys;
+    uint32_t jb_n, tb_n, reach, n_pos;  // product tiles: positions (j-block, t-block)
+    uint32_t subsets, ec, units;        // element subsets, chunk elements, 16-byte units
+    uint32_t raw, xp, yp, cp, zp, ot, total;  // LDS word offsets and size
+};
+
+__host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt) {
+    BsGeom g;
+    g.qb = q / 8;
+    g.qw = (q + 31) / 32;
+    g.jp = (q + kTile - 1) / kTile * kTile;
+    g.xs = g.jp / kTile * kPadBlock;                    // X: planes 0 .. jp - 1
+    g.ys = (kYLo + g.jp + kYHi) / kTile * kPadBlock;    // Y: planes -kYLo .. jp + kYHi - 1
+    g.jb_n = g.jp / kTile;
+    g.tb_n = (2 * q - 1 + kTile - 1) / kTile;
+    g.reach = (q + 14) / kTile + 1;       // t-blocks per j-block: t - j up to q + 14
+    g.n_pos = g.jb_n * g.reach;           // at most 72 (q = 128)
+    uint32_t s = nt / g.n_pos;
+    if (s == 0) s = 1;
+    if (s > n_e) s = n_e;
+    uint32_t ec = s * kElemsPerLane;
+    if (ec > n_e) ec = n_e;
+    if (ec > kChunkBytes / g.qb) ec = kChunkBytes / g.qb;
+    if (ec > kChunkElems) ec = kChunkElems;
+    if (s > ec) s = ec;
+    g.subsets = s;
+    g.ec = ec;
+    g.units = (ec * g.qb + 14) / 16 + 1;  // covers ec*qb bytes at any offset mod 16
+    g.raw = 0;                            // [2 sides][32 pairs][4*units] + 4 slack words
+    g.xp = 2 * kBsPairs * 4 * g.units + 4;
+    g.yp = g.xp + ec * g.xs;              // X planes [ec][xs]
+    g.cp = g.yp + ec * g.ys;              // Y planes [ec][ys], plane k at bs_pad(kYLo + k)
+    g.zp = g.cp + 2 * g.jp + kTile;       // C [2 jp + kTile]
+    g.ot = g.zp + g.jp;                   // Z [jp]
+    g.total = g.ot + kBsPairs * g.qw;     // outputs [32][qw]
+    return g;
+}
+
+// Work-group of nt = 256 lanes over npw <= 32 pairs from pair0; the pairs'
+// blocks form one contiguous region of npw*nbytes bytes per side.
+__global__ void __launch_bounds__(kThreads, 3)
+bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
+                uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t q = sh.q, n_e = sh.n_e, nbytes = sh.nbytes;
+    const BsGeom g = bs_geom(q, n_e, nt);
+    const uint32_t qb = g.qb, qw = g.qw, jp = g.jp, xs = g.xs, ys = g.ys, ec = g.ec;
+    const uint32_t units = g.units;
+    uint32_t* raw = lds + g.raw;
+    uint32_t* xp = lds + g.xp;
+    uint32_t* yp = lds + g.yp;
+    uint32_t* cp = lds + g.cp;
+    uint32_t* zp = lds + g.zp;
+    uint32_t* ot = lds + g.ot;
+
+    const uint64_t pair0 = (uint64_t)blockIdx.x * kBsPairs;
+    if (pair0 >= n_pairs) return;
+    const uint32_t npw = n_pairs - pair0 < kBsPairs ? (uint32_t)(n_pairs - pair0) : kBsPairs;
+    const uint8_t* xb = x + pair0 * nbytes;
+    const uint8_t* yb = y + pair0 * nbytes;
+    const uint32_t len = npw * nbytes;
+    const uint32_t lead_x = (uint32_t)((uintptr_t)xb & 15u);
+    const uint32_t lead_y = (uint32_t)((uintptr_t)yb & 15u);
+
+    for (uint32_t i = tid; i < 2 * jp + kTile; i += nt) cp[i] = 0u;
+    for (uint32_t i = tid; i < ec * (kYLo + kYHi); i += nt) {  // Y's zero margins
+        const uint32_t e = i / (kYLo + kYHi), r = i - e * (kYLo + kYHi);
+        yp[e * ys + bs_pad(r < kYLo ? r : jp + r)] = 0u;  // r >= kYLo: plane jp + (r - kYLo)
+    }
+
+    // ---- staging: unit k = (side, pair p, u) of chunk c is the 16-byte unit
+    // (lead + p*nbytes + c*ec*qb) / 16 + u of the side's raw region.  Units
+    // inside the region are loaded (in flight while the chunk before is
+    // multiplied); units that straddle an end are read bytewise when stored;
+    // units outside it, and of pairs past npw, are zero.
+    const uint32_t n_units = 2 * kBsPairs * units;  // <= kStageRegs * nt
+    uint4 st[kStageRegs];
+    uint32_t edge = 0;  // bit r: unit r straddles an end of the region
+    auto unit_of = [&](uint32_t k, uint32_t c, uint32_t& side, uint32_t& uk) -> bool {
+        side = k / (kBsPairs * units);
+        const uint32_t rem = k - side * (kBsPairs * units);
+        const uint32_t p = rem / units, u = rem - p * units;
+        const uint32_t lead = side ? lead_y : lead_x;
+        uk = ((lead + p * nbytes + c * ec * qb) >> 4) + u;
+        return p < npw;
+    };
+    auto load_chunk = [&](uint32_t c) {
+        edge = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kStageRegs; ++r) {
+            const uint32_t k = tid + r * nt;
+            st[r] = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t side, uk;
+            if (k < n_units && unit_of(k, c, side, uk)) {
+                const uint32_t lead = side ? lead_y : lead_x;
+                const uint32_t first = 16u * uk;
+                if (first >= lead && first + 16u <= lead + len)
+                    st[r] = reinterpret_cast<const uint4*>((side ? yb : xb) - lead)[uk];
+                else if (first < lead + len && first + 16u > lead)
+                    edge |= 1u << r;
+            }
+        }
+    };
+    auto store_chunk = [&](uint32_t c) {
+#pragma unroll
+        for (uint32_t r = 0; r < kStageRegs; ++r) {
+            const uint32_t k = tid + r * nt;
+            if (k < n_units) {
+                uint4 v = st[r];
+                if (edge & (1u << r)) {
+                    uint32_t side, uk;
+                    unit_of(k, c, side, uk);
+                    v = bs_edge_unit(side ? yb : xb, len, side ? lead_y : lead_x, uk);
+                }
+                reinterpret_cast<uint4*>(raw)[k] = v;
+            }
+        }
+    };
+
+    // ---- product item of this lane: tile position and element subset
+    const uint32_t pos = tid % g.n_pos, sub = tid / g.n_pos;
+    const uint32_t jb = pos / g.reach, dt = pos - jb * g.reach, tb = jb + dt;
+    const bool active = sub < g.subsets && tb < g.tb_n;
+    const uint32_t t0 = tb * kTile;
+    // y window: k = t - j from 16 dt - 15 to 16 dt + 15, planes m = kYLo + k =
+    // 16 dt + 1 + d (d = 0 .. 30) at bs_pad(m) = 17 dt + (1 + d) + ((1 + d) >> 4),
+    // within [-kYLo, jp + kYHi) since 16 dt <= q + 14 and jp >= q
+    const uint32_t xoff = jb * kPadBlock, yoff = dt * kPadBlock;
+    uint32_t acc[kTile];
+#pragma unroll
+    for (uint32_t i = 0; i < kTile; ++i) acc[i] = 0u;
+
+    const uint32_t n_chunks = (n_e + ec - 1) / ec;
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (uint32_t c = 0; c < n_chunks; ++c) {
+        const uint32_t e_cnt = (c + 1) * ec <= n_e ? ec : n_e - c * ec;
+        const uint32_t eoff = c * ec * qb;
+        // ---- transposes: item (side, element le, word w) gathers word w of
+        // element le of the 32 pairs (two LDS words and a funnel shift each;
+        // pairs past npw were staged as zero), transposes, and writes planes
+        // 32w .. 32w + 31
+        const uint32_t items = 2 * e_cnt * qw;
+        for (uint32_t it = tid; it < items; it += nt) {
+            const uint32_t side = it / (e_cnt * qw);
+            const uint32_t rem = it - side * (e_cnt * qw);
+            const uint32_t le = rem / qw, w = rem - le * qw;
+            const uint32_t* rs = raw + side * (kBsPairs * 4 * units);
+            const uint32_t lead = side ? lead_y : lead_x;
+            const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
+            const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
+            const uint32_t lt = le * qb + 4u * w;  // byte of the word in the pair's chunk
+            uint32_t a[32];
+            // both words are always read (the second may be the next pair's
+            // or a slack word) so that the 64 reads issue back to back
+#pragma unroll
+            for (uint32_t p = 0; p < 32; ++p) {
+                const uint32_t o = ((lead + p * nbytes + eoff) & 15u) + lt;
+                const uint32_t* r2 = rs + p * 4 * units + (o >> 2);
+                a[p] = bs_funnel(r2[1], r2[0], o * 8u) & keep;
+            }
+            transpose32(a);
+            // plane j = 32w + i at bs_pad(j) (X) or bs_pad(kYLo + j) (Y)
+            uint32_t* dst = side ? yp + le * ys + kPadBlock + 2 * kPadBlock * w
+                                 : xp + le * xs + 2 * kPadBlock * w;
+#pragma unroll
+            for (uint32_t i = 0; i < 32; ++i)
+                if (32u * w + i < jp) dst[bs_pad(i)] = a[i];  // zero for j >= q (bytes masked)
+        }
+        __syncthreads();
+        if (c + 1 < n_chunks) load_chunk(c + 1);  // in flight during the products
+        // ---- products: c[t] ^= x[j] & y[t - j] over the 16x16 tile
+        if (active) {
+            for (uint32_t le = sub; le < e_cnt; le += g.subsets) {
+                const uint32_t* xe = xp + le * xs + xoff;
+                const uint32_t* yw = yp + le * ys + yoff;
+                uint32_t xv[kTile], yv[2 * kTile - 1];
+#pragma unroll
+                for (uint32_t i = 0; i < kTile; ++i) xv[i] = xe[i];
+#pragma unroll
+                for (uint32_t d = 0; d < 2 * kTile - 1; ++d) yv[d] = yw[(1 + d) + ((1 + d) >> 4)];
+#pragma unroll
+                for (uint32_t i = 0; i < kTile; ++i)        // t = t0 + i
+#pragma unroll
+                    for (uint32_t jj = 0; jj < kTile; ++jj)  // j = j0 + jj: y index t - j
+                        acc[i] = bs_and_xor(xv[jj], yv[i - jj + kTile - 1], acc[i]);
+            }
+        }
+        if (c + 1 < n_chunks) store_chunk(c + 1);
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (uint32_t i = 0; i < kTile; ++i)
+            if (acc[i]) atomicXor(cp + t0 + i, acc[i]);  // t0 + i < tb_n * kTile <= 2 jp + kTile
+    }
+    __syncthreads();
+
+    // ---- reduction modulo P ------------------------------------------
+    // C = C_lo + t^q H with H[i] = c[q + i] (i <= q - 2) and t^q = 1 + sum_f t^f
+    // (every tap f < q/2).  t^f H = (t^f H mod t^q) + t^q U_f with U_f[i] =
+    // H[i + q - f] = c[2q + i - f] for i <= f - 2; D = sum_f U_f; t^q D = D +
+    // sum_g t^g D needs no further reduction.  Output plane t < q:
+    //   z[t] = c[t] + H[t] + sum_f H[t - f] + D[t] + sum_g D[t - g].
+    for (uint32_t t = tid; t < q; t += nt) {
+        uint32_t z = cp[t] ^ (t + 1 < q ? cp[q + t] : 0u);
+        for (uint32_t k = 0; k < sh.n_taps; ++k) {
+            const uint32_t f = sh.taps[k];
+            if (t >= f) z ^= cp[q + t - f];                  // (t^f H)[t], t - f <= q - 2
+            if (t + 1 < f) z ^= cp[2 * q + t - f];           // U_f[t] in D[t]
+            for (uint32_t k2 = 0; k2 < sh.n_taps; ++k2) {    // U_f[t - g] in (t^g D)[t]
+                const uint32_t gg = sh.taps[k2];
+                if (t >= gg && t - gg + 1 < f) z ^= cp[2 * q + (t - gg) - f];
+            }
+        }
+        zp[t] = z;
+    }
+    __syncthreads();
+
+    // ---- output: lane w transposes planes 32w .. 32w + 31 into word w of
+    // the 32 outputs; then the work-group stores its npw*qb bytes
+    for (uint32_t w = tid; w < qw; w += nt) {
+        uint32_t a[32];
+#pragma unroll
+        for (uint32_t i = 0; i < 32; ++i) a[i] = 32u * w + i < q ? zp[32u * w + i] : 0u;
+        transpose32(a);  // a[p] = word w of pair p's output
+#pragma unroll
+        for (uint32_t p = 0; p < 32; ++p) ot[p * qw + w] = a[p];
+    }
+    __syncthreads();
+    uint8_t* ob = out + pair0 * qb;
+    for (uint32_t i = tid; i < npw * qb; i += nt) {
+        const uint32_t p = i / qb, k = i - p * qb;
+        ob[i] = (uint8_t)(ot[p * qw + (k >> 2)] >> (8u * (k & 3u)));
+    }
+}
+
+}  // namespace
+
+uint32_t bitslice_lds_words(const ExtShape& s) {
+    if (s.q == 0 || s.q % 8 || s.q > kBitsliceMaxQ || s.n_e == 0) return 0xffffffffu;
+    return bs_geom(s.q, s.n_e, kThreads).total;
+}
+
+hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
+                           uint64_t n_pairs, hipStream_t stream) {
+    if (n_pairs == 0) return hipSuccess;
+    if (s.q == 0 || s.q > kBitsliceMaxQ || s.q % 8 || s.n_e == 0) return hipErrorInvalidValue;
+    if ((uint64_t)s.nbytes * 8 != (uint64_t)s.q * s.n_e || (uint64_t)s.nbytes * kBsPairs > 0xffffffffull)
+        return hipErrorInvalidValue;
+    const BsGeom g = bs_geom(s.q, s.n_e, kThreads);
+    if (g.n_pos > (uint32_t)kThreads || 2 * kBsPairs * g.units > kStageRegs * (uint32_t)kThreads)
+        return hipErrorInvalidValue;
+    const uint64_t groups = (n_pairs + kBsPairs - 1) / kBsPairs;
+    if (groups > 0x7fffffffull) return hipErrorInvalidValue;
+    const uint32_t lds = g.total * 4u;
+    if (lds > 65536u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bitslice_kernel, dim3((uint32_t)groups), dim3(kThreads), lds, stream, x, y,
+                       out, n_pairs, s);
+    return hipGetLastError();
+}
+
+}  // namespace qext

@@ -146,6 +146,15 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
 hipError_t launch_valu_probe(uint32_t* out, uint32_t blocks, uint32_t iters, hipStream_t stream);
 constexpr uint32_t kProbeOpsPerIter = 16 * 9;  // 8 AND-XORs and 1 funnel shift, 16 times
 
+// Bit-sliced kernel for small fields (ext_bitslice.hip): 32 block pairs per
+// 256-lane work-group, any q <= kBitsliceMaxQ divisible by 8, blocks and
+// outputs at any byte offset.  bitslice_lds_words: its LDS need (the launch
+// is refused above 64 KiB).
+constexpr uint32_t kBitsliceMaxQ = 128;
+uint32_t bitslice_lds_words(const ExtShape& s);
+hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
+                           uint64_t n_pairs, hipStream_t stream);
+
 // Resident work-groups per CU of the batched kernel at this LDS size.
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,
                            int* blocks_per_cu);

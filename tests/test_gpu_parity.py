@@ -321,7 +321,7 @@ def test_zero_pairs_and_errors(dev):
 # streaming form
 # ---------------------------------------------------------------------------
 def run_stream(dev, w, chunks_x, chunks_y, device_memory=False, cap=0, poll_every=1,
-               combined=True):
+               combined=True, kernel=0):
     """Feed X and Y in the given chunk sizes (in one ext_submit per step when
     combined, else one side per call), poll as it goes, then drain.
     Returns (output bytes, dropped bits, EAGAIN count)."""
@@ -329,7 +329,7 @@ def run_stream(dev, w, chunks_x, chunks_y, device_memory=False, cap=0, poll_ever
 
     ex = binding.Extractor(w.n_bits, w.m_bits, device_memory=device_memory,
                            stream=torch.cuda.current_stream(dev).cuda_stream if device_memory else None,
-                           device_bytes_cap=cap)
+                           device_bytes_cap=cap, kernel=kernel)
     s = ex.open_stream()
     qb = w.m_bits // 8
     collected = []
