@@ -225,10 +225,10 @@ int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs
     return EXT_OK;
 }
 
-// The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits (its
-// chunked planes stay below 64 KiB of LDS).
+// The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits and
+// blocks below 8 MiB (its chunked planes stay below 64 KiB of LDS).
 bool bitslice_applies(const ExtShape& s) {
-    return s.q <= qext::kBitsliceMaxQ && s.q % 8 == 0 &&
+    return s.q <= qext::kBitsliceMaxQ && s.q % 8 == 0 && s.nbytes < (1u << 23) &&
            (uint64_t)qext::bitslice_lds_words(s) * 4 <= 65536;
 }
 
@@ -336,7 +336,7 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         bsh.nbytes = (uint32_t)(n_bits / 8);
         bsh.align = 1;  // byte gathers
         bsh.threads = qext::kThreads;
-        bs = m_bits % 8 == 0 && n_bits / 8 <= 0xffffffffull && bitslice_applies(bsh) &&
+        bs = m_bits % 8 == 0 && n_bits / 8 < (1ull << 23) && bitslice_applies(bsh) &&
              (p->kernel == EXT_KERNEL_BITSLICE || bitslice_preferred(bsh));
         if (bs) {
             if (planned) {

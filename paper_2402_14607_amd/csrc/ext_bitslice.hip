@@ -100,11 +100,20 @@ __device__ __forceinline__ uint4 bs_edge_unit(const uint8_t* __restrict__ src, u
     return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
+// n / d for n, d < 2^16 with m = bs_recip(d): for d >= 2, m = 2^32/d + e
+// (0 <= e <= 1) and (n m) >> 32 is exact, since e adds at most n/2^32 < 1/d
+// to n/d; d = 1 (m would be 2^32) is marked by m = 0.
+__host__ __device__ inline uint32_t bs_recip(uint32_t d) {
+    return d <= 1 ? 0u : (uint32_t)(0xffffffffull / d) + 1u;
+}
+__device__ __forceinline__ uint32_t bs_div(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
+
 constexpr uint32_t kElemsPerLane = 2;  // elements per product lane per chunk
 constexpr uint32_t kStageRegs = 4;     // 16-byte staging loads per lane per chunk
 constexpr uint32_t kChunkBytes = 224;  // most bytes of one pair's chunk (units <= 16)
 constexpr uint32_t kChunkElems = 128;  // most elements per chunk (LDS stays below 56 KiB)
 constexpr uint32_t kPadBlock = kTile + 1;  // LDS words per 16 planes (one pad word)
+constexpr uint32_t kRawSkew = 16;          // extra words before side Y's raw bytes (banks)
 
 // LDS word of plane m of an element laid out in blocks of 16 planes and one
 // pad word: tiles of different j-blocks, t-blocks and elements fall in
@@ -116,7 +125,8 @@ __host__ __device__ constexpr uint32_t bs_pad(uint32_t m) { return kPadBlock * (
 // each chunk's bytes are staged raw, transposed into planes, multiplied.
 struct BsGeom {
     uint32_t qb, qw, jp, xs, ys;
-    uint32_t jb_n, tb_n, reach, n_pos;  // product tiles: positions (j-block, t-block)
+    uint32_t jb_n, tb_n, reach, n_pos;  // product tiles: positions (j-block, offset)
+    uint32_t fold;                      // 1: q % 16 == 0, diagonal tiles carry the last offset
     uint32_t subsets, ec, units;        // element subsets, chunk elements, 16-byte units
     uint32_t raw, xp, yp, cp, zp, ot, total;  // LDS word offsets and size
 };
@@ -127,11 +137,18 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
     g.qw = (q + 31) / 32;
     g.jp = (q + kTile - 1) / kTile * kTile;
     g.xs = g.jp / kTile * kPadBlock;                    // X: planes 0 .. jp - 1
-    g.ys = (kYLo + g.jp + kYHi) / kTile * kPadBlock;    // Y: planes -kYLo .. jp + kYHi - 1
+    // Y: planes -kYLo .. jp + kYHi - 1, element stride odd so that the plane
+    // writes of up to 32 elements fall in different banks
+    g.ys = (kYLo + g.jp + kYHi) / kTile * kPadBlock + 1;
     g.jb_n = g.jp / kTile;
     g.tb_n = (2 * q - 1 + kTile - 1) / kTile;
-    g.reach = (q + 14) / kTile + 1;       // t-blocks per j-block: t - j up to q + 14
-    g.n_pos = g.jb_n * g.reach;           // at most 72 (q = 128)
+    // t-block tb = jb + dt covers t - j from 16 dt - 15 to 16 dt + 15, so dt
+    // runs to (q + 14) / 16.  When 16 divides q, the tile at dt = 0 needs only
+    // j <= t and the one at dt = q/16 only j > t: one lane takes both halves
+    // (256 operations, like a full tile), and dt runs to q/16 - 1.
+    g.fold = q % kTile == 0 ? 1u : 0u;
+    g.reach = g.fold ? q / kTile : (q + 14) / kTile + 1;
+    g.n_pos = g.jb_n * g.reach;           // at most 72 (q = 120)
     uint32_t s = nt / g.n_pos;
     if (s == 0) s = 1;
     if (s > n_e) s = n_e;
@@ -143,8 +160,8 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
     g.subsets = s;
     g.ec = ec;
     g.units = (ec * g.qb + 14) / 16 + 1;  // covers ec*qb bytes at any offset mod 16
-    g.raw = 0;                            // [2 sides][32 pairs][4*units] + 4 slack words
-    g.xp = 2 * kBsPairs * 4 * g.units + 4;
+    g.raw = 0;                            // [2 sides][32 pairs][4*units], sides kRawSkew
+    g.xp = 2 * kBsPairs * 4 * g.units + kRawSkew + 4;  // words apart, + 4 slack words
     g.yp = g.xp + ec * g.xs;              // X planes [ec][xs]
     g.cp = g.yp + ec * g.ys;              // Y planes [ec][ys], plane k at bs_pad(kYLo + k)
     g.zp = g.cp + 2 * g.jp + kTile;       // C [2 jp + kTile]
@@ -192,26 +209,32 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     // multiplied); units that straddle an end are read bytewise when stored;
     // units outside it, and of pairs past npw, are zero.
     const uint32_t n_units = 2 * kBsPairs * units;  // <= kStageRegs * nt
-    uint4 st[kStageRegs];
-    uint32_t edge = 0;  // bit r: unit r straddles an end of the region
-    auto unit_of = [&](uint32_t k, uint32_t c, uint32_t& side, uint32_t& uk) -> bool {
-        side = k / (kBsPairs * units);
+    // slot r of this lane: unit k = tid + r*nt, packed as (lead + p*nbytes) << 4 | u
+    // (below 2^32: nbytes < 2^23), or ~0 for no unit (k >= n_units or p >= npw)
+    const uint32_t rcp_units = bs_recip(units);  // k < 2^11, units <= 16
+    uint32_t slot[kStageRegs];
+#pragma unroll
+    for (uint32_t r = 0; r < kStageRegs; ++r) {
+        const uint32_t k = tid + r * nt;
+        const uint32_t side = k >= kBsPairs * units ? 1u : 0u;
         const uint32_t rem = k - side * (kBsPairs * units);
-        const uint32_t p = rem / units, u = rem - p * units;
-        const uint32_t lead = side ? lead_y : lead_x;
-        uk = ((lead + p * nbytes + c * ec * qb) >> 4) + u;
-        return p < npw;
+        const uint32_t p = bs_div(rem, rcp_units), u = rem - p * units;
+        slot[r] = (k < n_units && p < npw) ? ((side ? lead_y : lead_x) + p * nbytes) << 4 | u : ~0u;
+    }
+    uint4 st[kStageRegs];
+    uint32_t edge = 0;  // bit r: slot r's unit straddles an end of the region
+    auto unit_index = [&](uint32_t r, uint32_t c) -> uint32_t {
+        return (((slot[r] >> 4) + c * ec * qb) >> 4) + (slot[r] & 15u);
     };
     auto load_chunk = [&](uint32_t c) {
         edge = 0;
 #pragma unroll
         for (uint32_t r = 0; r < kStageRegs; ++r) {
-            const uint32_t k = tid + r * nt;
             st[r] = make_uint4(0u, 0u, 0u, 0u);
-            uint32_t side, uk;
-            if (k < n_units && unit_of(k, c, side, uk)) {
+            if (slot[r] != ~0u) {
+                const uint32_t side = tid + r * nt >= kBsPairs * units ? 1u : 0u;
                 const uint32_t lead = side ? lead_y : lead_x;
-                const uint32_t first = 16u * uk;
+                const uint32_t uk = unit_index(r, c), first = 16u * uk;
                 if (first >= lead && first + 16u <= lead + len)
                     st[r] = reinterpret_cast<const uint4*>((side ? yb : xb) - lead)[uk];
                 else if (first < lead + len && first + 16u > lead)
@@ -226,27 +249,31 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
             if (k < n_units) {
                 uint4 v = st[r];
                 if (edge & (1u << r)) {
-                    uint32_t side, uk;
-                    unit_of(k, c, side, uk);
-                    v = bs_edge_unit(side ? yb : xb, len, side ? lead_y : lead_x, uk);
+                    const uint32_t side = k >= kBsPairs * units ? 1u : 0u;
+                    v = bs_edge_unit(side ? yb : xb, len, side ? lead_y : lead_x, unit_index(r, c));
                 }
-                reinterpret_cast<uint4*>(raw)[k] = v;
+                reinterpret_cast<uint4*>(raw + (k >= kBsPairs * units ? kRawSkew : 0u))[k] = v;
             }
         }
     };
 
-    // ---- product item of this lane: tile position and element subset
+    // Lane (position (jb, dt), element subset): x planes j = 16 jb + jj, output
+    // planes t = 16 (jb + dt) + i.  Terms with j <= t (jj <= i) take y plane
+    // 16 da + (i - jj) and go to acc_lo (t-block jb + da); terms with j > t take
+    // y plane 16 db + (i - jj) and go to acc_hi (t-block jb + db).  A plain tile
+    // has da = db = dt; a folded diagonal tile has da = 0, db = q/16.
     const uint32_t pos = tid % g.n_pos, sub = tid / g.n_pos;
-    const uint32_t jb = pos / g.reach, dt = pos - jb * g.reach, tb = jb + dt;
-    const bool active = sub < g.subsets && tb < g.tb_n;
-    const uint32_t t0 = tb * kTile;
-    // y window: k = t - j from 16 dt - 15 to 16 dt + 15, planes m = kYLo + k =
-    // 16 dt + 1 + d (d = 0 .. 30) at bs_pad(m) = 17 dt + (1 + d) + ((1 + d) >> 4),
-    // within [-kYLo, jp + kYHi) since 16 dt <= q + 14 and jp >= q
-    const uint32_t xoff = jb * kPadBlock, yoff = dt * kPadBlock;
-    uint32_t acc[kTile];
+    const uint32_t jb = pos / g.reach, dt = pos - jb * g.reach;
+    const uint32_t da = dt, db = (g.fold && dt == 0) ? q / kTile : dt;
+    const bool active = sub < g.subsets && jb + dt < g.tb_n;
+    // y planes 16 da + m (m = 0 .. 15) at bs_pad(kYLo + 16 da + m) = 17 (da + 1) + m,
+    // and 16 db - 15 + m (m = 0 .. 14) at 17 db + 1 + m; all within
+    // [-kYLo, jp + kYHi) since 16 db <= q + 14 and jp >= q
+    const uint32_t xoff = jb * kPadBlock;
+    const uint32_t yoff_a = (da + 1) * kPadBlock, yoff_b = db * kPadBlock + 1;
+    uint32_t acc_lo[kTile], acc_hi[kTile];
 #pragma unroll
-    for (uint32_t i = 0; i < kTile; ++i) acc[i] = 0u;
+    for (uint32_t i = 0; i < kTile; ++i) acc_lo[i] = acc_hi[i] = 0u;
 
     const uint32_t n_chunks = (n_e + ec - 1) / ec;
     load_chunk(0);
@@ -255,19 +282,20 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     for (uint32_t c = 0; c < n_chunks; ++c) {
         const uint32_t e_cnt = (c + 1) * ec <= n_e ? ec : n_e - c * ec;
         const uint32_t eoff = c * ec * qb;
-        // ---- transposes: item (side, element le, word w) gathers word w of
+        // ---- transposes: item (word w, side, element le) gathers word w of
         // element le of the 32 pairs (two LDS words and a funnel shift each;
         // pairs past npw were staged as zero), transposes, and writes planes
-        // 32w .. 32w + 31
+        // 32w .. 32w + 31.  Items run word-major, so a wave holds one or two
+        // words and the last word's byte mask and plane bound rarely diverge.
         const uint32_t items = 2 * e_cnt * qw;
+        const uint32_t rcp_2e = bs_recip(2 * e_cnt);  // items < 2^16
         for (uint32_t it = tid; it < items; it += nt) {
-            const uint32_t side = it / (e_cnt * qw);
-            const uint32_t rem = it - side * (e_cnt * qw);
-            const uint32_t le = rem / qw, w = rem - le * qw;
-            const uint32_t* rs = raw + side * (kBsPairs * 4 * units);
+            const uint32_t w = bs_div(it, rcp_2e);
+            const uint32_t rem = it - w * (2 * e_cnt);
+            const uint32_t side = rem >= e_cnt ? 1u : 0u;
+            const uint32_t le = rem - side * e_cnt;
+            const uint32_t* rs = raw + side * (kBsPairs * 4 * units + kRawSkew);
             const uint32_t lead = side ? lead_y : lead_x;
-            const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
-            const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
             const uint32_t lt = le * qb + 4u * w;  // byte of the word in the pair's chunk
             uint32_t a[32];
             // both words are always read (the second may be the next pair's
@@ -276,15 +304,24 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
             for (uint32_t p = 0; p < 32; ++p) {
                 const uint32_t o = ((lead + p * nbytes + eoff) & 15u) + lt;
                 const uint32_t* r2 = rs + p * 4 * units + (o >> 2);
-                a[p] = bs_funnel(r2[1], r2[0], o * 8u) & keep;
+                a[p] = bs_funnel(r2[1], r2[0], o * 8u);
+            }
+            if (qb - 4u * w < 4u) {  // the element's last word: bytes past q/8 are the next one's
+                const uint32_t keep = (1u << (8u * (qb - 4u * w))) - 1u;
+#pragma unroll
+                for (uint32_t p = 0; p < 32; ++p) a[p] &= keep;
             }
             transpose32(a);
-            // plane j = 32w + i at bs_pad(j) (X) or bs_pad(kYLo + j) (Y)
+            // plane j = 32w + i at bs_pad(j) (X) or bs_pad(kYLo + j) (Y); planes
+            // q .. jp - 1 are zero (masked bytes); 32w + 16 <= jp always
             uint32_t* dst = side ? yp + le * ys + kPadBlock + 2 * kPadBlock * w
                                  : xp + le * xs + 2 * kPadBlock * w;
 #pragma unroll
-            for (uint32_t i = 0; i < 32; ++i)
-                if (32u * w + i < jp) dst[bs_pad(i)] = a[i];  // zero for j >= q (bytes masked)
+            for (uint32_t i = 0; i < 16; ++i) dst[bs_pad(i)] = a[i];
+            if (32u * w + 32u <= jp) {
+#pragma unroll
+                for (uint32_t i = 16; i < 32; ++i) dst[bs_pad(i)] = a[i];
+            }
         }
         __syncthreads();
         if (c + 1 < n_chunks) load_chunk(c + 1);  // in flight during the products
@@ -292,26 +329,44 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
         if (active) {
             for (uint32_t le = sub; le < e_cnt; le += g.subsets) {
                 const uint32_t* xe = xp + le * xs + xoff;
-                const uint32_t* yw = yp + le * ys + yoff;
-                uint32_t xv[kTile], yv[2 * kTile - 1];
+                const uint32_t* ya = yp + le * ys + yoff_a;
+                const uint32_t* yb2 = yp + le * ys + yoff_b;
+                // the two halves one after the other: 16 y planes live at a time
+                uint32_t xv[kTile], yv[kTile];
 #pragma unroll
                 for (uint32_t i = 0; i < kTile; ++i) xv[i] = xe[i];
 #pragma unroll
-                for (uint32_t d = 0; d < 2 * kTile - 1; ++d) yv[d] = yw[(1 + d) + ((1 + d) >> 4)];
+                for (uint32_t m = 0; m < kTile; ++m) yv[m] = ya[m];
 #pragma unroll
-                for (uint32_t i = 0; i < kTile; ++i)        // t = t0 + i
+                for (uint32_t i = 0; i < kTile; ++i)
 #pragma unroll
-                    for (uint32_t jj = 0; jj < kTile; ++jj)  // j = j0 + jj: y index t - j
-                        acc[i] = bs_and_xor(xv[jj], yv[i - jj + kTile - 1], acc[i]);
+                    for (uint32_t jj = 0; jj <= i; ++jj)
+                        acc_lo[i] = bs_and_xor(xv[jj], yv[i - jj], acc_lo[i]);
+#pragma unroll
+                for (uint32_t m = 0; m < kTile - 1; ++m) yv[m] = yb2[m];
+#pragma unroll
+                for (uint32_t i = 0; i < kTile; ++i)
+#pragma unroll
+                    for (uint32_t jj = i + 1; jj < kTile; ++jj)
+                        acc_hi[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_hi[i]);
             }
         }
         if (c + 1 < n_chunks) store_chunk(c + 1);
         __syncthreads();
     }
-    if (active) {
+    if (active) {  // t-blocks below tb_n + 1 (folded: jb + q/16 <= 2q/16 - 1)
+        uint32_t* ca = cp + (jb + da) * kTile;
+        uint32_t* cb = cp + (jb + db) * kTile;
 #pragma unroll
-        for (uint32_t i = 0; i < kTile; ++i)
-            if (acc[i]) atomicXor(cp + t0 + i, acc[i]);  // t0 + i < tb_n * kTile <= 2 jp + kTile
+        for (uint32_t i = 0; i < kTile; ++i) {
+            if (da == db) {
+                const uint32_t v = acc_lo[i] ^ acc_hi[i];
+                if (v) atomicXor(ca + i, v);
+            } else {
+                if (acc_lo[i]) atomicXor(ca + i, acc_lo[i]);
+                if (acc_hi[i]) atomicXor(cb + i, acc_hi[i]);
+            }
+        }
     }
     __syncthreads();
 
@@ -365,7 +420,7 @@ hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y
                            uint64_t n_pairs, hipStream_t stream) {
     if (n_pairs == 0) return hipSuccess;
     if (s.q == 0 || s.q > kBitsliceMaxQ || s.q % 8 || s.n_e == 0) return hipErrorInvalidValue;
-    if ((uint64_t)s.nbytes * 8 != (uint64_t)s.q * s.n_e || (uint64_t)s.nbytes * kBsPairs > 0xffffffffull)
+    if ((uint64_t)s.nbytes * 8 != (uint64_t)s.q * s.n_e || s.nbytes >= (1u << 23))
         return hipErrorInvalidValue;
     const BsGeom g = bs_geom(s.q, s.n_e, kThreads);
     if (g.n_pos > (uint32_t)kThreads || 2 * kBsPairs * g.units > kStageRegs * (uint32_t)kThreads)
