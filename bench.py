@@ -202,6 +202,24 @@ def paper_point_leg(dev, stream, steps: int, warmup: int):
     out_gbps = pairs * m / (ms * 1e-3) / 1e9
     log("paper-point leg: %.4f ms per launch, %.2f Gbps output, %s" % (ms, out_gbps, parity))
     ex.close()
+    # the other kernel on the same launch, for comparison
+    other = binding.KERNEL_WORD if plan.get("kernel") == "bitslice" else binding.KERNEL_BITSLICE
+    ex2 = binding.Extractor(n, m, device_memory=True, sample_bits=16, stream=stream.cuda_stream,
+                            autotune=True, kernel=other)
+    out2 = torch.empty_like(out)
+    ex2.extract(x, y, out2, pairs)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        ex2.extract(x, y, out2, pairs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms2 = a.elapsed_time(b) / steps
+    same = bool(torch.equal(out, out2))
+    other_plan = json.loads(ex2.describe())
+    ex2.close()
+    log("paper-point leg: %s kernel %.4f ms per launch, same bytes: %s"
+        % (other_plan["kernel"], ms2, same))
     return {
         "workload": "paper parameter point: n_e=71 elements of F_2^80 per block (n=5680 bits, "
                     "355 16-bit samples), 262144 block pairs, iid round(N(32768, 682^2)) "
@@ -212,6 +230,9 @@ def paper_point_leg(dev, stream, steps: int, warmup: int):
         "roofline_frac": round(pairs * n * m / (ms * 1e-3) / 1e12 / PEAK_BITMAC_T, 4),
         "parity": parity,
         "kernel_plan": plan,
+        "other_kernel": {"kernel": other_plan["kernel"], "ms_per_launch": round(ms2, 5),
+                         "output_gbps": round(pairs * m / (ms2 * 1e-3) / 1e9, 3),
+                         "same_bytes": same},
         "context_fpga_output_gbps": 64.0,
     }
 

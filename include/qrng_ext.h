@@ -92,8 +92,11 @@ typedef struct {
                                    EXT_KERNEL_WORD (word-level Karatsuba kernel) or
                                    EXT_KERNEL_BITSLICE (32 pairs per work-group bit-sliced
                                    across pairs; fields of at most 128 bits, else
-                                   EXT_ENOTSUP).  Both give the same bytes; AUTO takes
-                                   the one that measures faster for the shape */
+                                   EXT_ENOTSUP).  Both give the same bytes.  AUTO takes
+                                   the bit-sliced kernel for fields of 32 to 112 bits
+                                   that 16 divides with at least 30 elements per block
+                                   (where it measured faster), or, with autotune set,
+                                   whichever of the two times faster for the shape */
     uint32_t reserved[2];
 } ext_params;
 enum { EXT_KERNEL_AUTO = 0, EXT_KERNEL_WORD = 1, EXT_KERNEL_BITSLICE = 2 };

@@ -140,6 +140,77 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
     return hipSuccess;
 }
 
+namespace {
+std::map<TuneKey, bool> g_kernel_cache;
+}  // namespace
+
+// Word-level plan (tuned by autotune_shape) against the bit-sliced kernel:
+// time per pair of each over synthetic blocks, the faster one wins.
+hipError_t choose_kernel(const ExtShape& bs, hipStream_t stream, bool* use_bitslice) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const TuneKey key{dev, bs.q, bs.n_e, bs.n_taps, bs.n_taps > 0 ? bs.taps[0] : 0,
+                      bs.n_taps > 1 ? bs.taps[1] : 0, bs.n_taps > 2 ? bs.taps[2] : 0};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_kernel_cache.find(key);
+        if (it != g_kernel_cache.end()) {
+            *use_bitslice = it->second;
+            return hipSuccess;
+        }
+    }
+    PlanKnobs knobs;
+    float word_per_pair = 0;
+    e = autotune_shape(bs.q, bs.n_e, bs.taps, bs.n_taps, stream, &knobs, &word_per_pair);
+    if (e != hipSuccess) return e;
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const uint64_t nb = bs.nbytes;
+    uint64_t pairs = (uint64_t)cus * 8 * 32;  // ~8 work-groups of 32 pairs per CU
+    pairs = std::max<uint64_t>(32, std::min<uint64_t>(pairs, (64ull << 20) / nb));
+    uint8_t *dx = nullptr, *dy = nullptr, *dout = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<uint8_t> host(pairs * nb);
+    std::mt19937_64 rng(0x5eed ^ bs.q ^ (uint64_t)bs.n_e << 32);
+    for (auto& b : host) b = (uint8_t)rng();
+    float bs_per_pair = 1e30f;
+    do {
+        if ((e = hipMalloc((void**)&dx, pairs * nb)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&dy, pairs * nb)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&dout, pairs * bs.qbytes)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(dx, host.data(), pairs * nb, hipMemcpyHostToDevice, stream)) !=
+            hipSuccess)
+            break;
+        if ((e = hipMemcpyAsync(dy, host.data(), pairs * nb, hipMemcpyHostToDevice, stream)) !=
+            hipSuccess)
+            break;
+        if ((e = hipEventCreate(&e0)) != hipSuccess) break;
+        if ((e = hipEventCreate(&e1)) != hipSuccess) break;
+        auto run = [&] { return launch_bitslice(bs, dx, dy, dout, pairs, stream); };
+        if ((e = run()) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+        if (e != hipSuccess) break;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        bs_per_pair = ms / 3.0f / (float)pairs;
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(dx);
+    (void)hipFree(dy);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return e;
+    *use_bitslice = bs_per_pair < word_per_pair;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_kernel_cache[key] = *use_bitslice;
+    return hipSuccess;
+}
+
 }  // namespace qext
 
 // ---------------------------------------------------------------------------

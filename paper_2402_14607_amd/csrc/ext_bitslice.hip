@@ -411,6 +411,15 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
 
 }  // namespace
 
+void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* tile_positions,
+                       uint32_t* element_subsets, uint32_t* folded) {
+    const BsGeom g = bs_geom(s.q, s.n_e, kThreads);
+    *chunk_elements = g.ec;
+    *tile_positions = g.n_pos;
+    *element_subsets = g.subsets;
+    *folded = g.fold;
+}
+
 uint32_t bitslice_lds_words(const ExtShape& s) {
     if (s.q == 0 || s.q % 8 || s.q > kBitsliceMaxQ || s.n_e == 0) return 0xffffffffu;
     return bs_geom(s.q, s.n_e, kThreads).total;

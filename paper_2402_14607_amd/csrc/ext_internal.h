@@ -110,6 +110,10 @@ hipError_t launch_batch(uint32_t bw, uint32_t threads, bool padded, const BatchS
 hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                           hipStream_t stream, PlanKnobs* best, float* best_ms);
 
+// Autotuned choice between the word-level kernel (its best plan) and the
+// bit-sliced kernel for a shape the latter applies to; cached per device.
+hipError_t choose_kernel(const ExtShape& bitslice_shape, hipStream_t stream, bool* use_bitslice);
+
 // One byte range to move from a staging buffer into a device ring.
 struct ScatterDesc {
     uint64_t src_off;  // byte offset in the staging buffer
@@ -152,6 +156,10 @@ constexpr uint32_t kProbeOpsPerIter = 16 * 9;  // 8 AND-XORs and 1 funnel shift,
 // is refused above 64 KiB).
 constexpr uint32_t kBitsliceMaxQ = 128;
 uint32_t bitslice_lds_words(const ExtShape& s);
+// Geometry of the bit-sliced kernel for s: elements per chunk, 16x16 tile
+// positions, element subsets, and whether diagonal tiles are folded.
+void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* tile_positions,
+                       uint32_t* element_subsets, uint32_t* folded);
 hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
                            uint64_t n_pairs, hipStream_t stream);
 

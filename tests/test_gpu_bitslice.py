@@ -176,3 +176,22 @@ def test_selection_errors(dev):
     assert e.value.code == binding.EXT_EINVAL
     with binding.Extractor(2048, 256, kernel=binding.KERNEL_AUTO) as ex:
         assert json.loads(ex.describe())["kernel"] == "word"   # q above 128
+
+
+def test_auto_choice(dev):
+    """AUTO takes the bit-sliced kernel at the paper's point and the word
+    kernel for few elements; with autotune it times both, and every choice
+    gives the oracle's bytes."""
+    import torch
+
+    for n_e, want in ((71, "bitslice"), (4, "word"), (40, "bitslice")):
+        with binding.Extractor(80 * n_e, 80) as ex:
+            assert json.loads(ex.describe())["kernel"] == want, n_e
+    w = inputs.plain_workload(5680, 80, 45, 63, 64)
+    with binding.Extractor(5680, 80, device_memory=True, autotune=True,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        say("autotuned choice at the paper's point: " + ex.describe())
+        out = torch.zeros(45 * 10, dtype=torch.uint8, device=dev)
+        ex.extract(to_dev(dev, w.x), to_dev(dev, w.y), out, 45)
+        ex.sync()
+    assert np.array_equal(out.cpu().numpy(), oracle.ext_blocks(w.x, w.y, 5680, 80))
