@@ -79,6 +79,31 @@ def test_ragged_pair_counts(dev, pairs):
     assert np.array_equal(got, oracle.ext_blocks(w.x, w.y, 5680, 80))
 
 
+@pytest.mark.parametrize("off_x,off_y", [(4, 12), (12, 8), (8, 0)])
+def test_unaligned_device_pointers(dev, off_x, off_y):
+    """x and y 4-byte aligned (the interface's requirement) but off a 16-byte
+    boundary: the staging reads the units at the region's ends byte by byte
+    and must neither miss nor cross them."""
+    import torch
+
+    pairs = 70
+    w = inputs.plain_workload(5680, 80, pairs, 65 + off_x, 66 + off_y)
+    nb = w.x.size
+    bx = torch.full((nb + 32,), 0x5A, dtype=torch.uint8, device=dev)
+    by = torch.full((nb + 32,), 0xC3, dtype=torch.uint8, device=dev)
+    bx[off_x:off_x + nb] = to_dev(dev, w.x)
+    by[off_y:off_y + nb] = to_dev(dev, w.y)
+    out = torch.full((pairs * 10 + 16,), 0xA5, dtype=torch.uint8, device=dev)
+    say("bitslice unaligned x+%d y+%d" % (off_x, off_y))
+    with binding.Extractor(5680, 80, device_memory=True, kernel=BS,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        ex.extract(bx[off_x:off_x + nb], by[off_y:off_y + nb], out, pairs)
+        ex.sync()
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:pairs * 10], oracle.ext_blocks(w.x, w.y, 5680, 80))
+    assert np.all(got[pairs * 10:] == 0xA5)
+
+
 def test_extremes(dev):
     """All-zero and all-one blocks and the edge elements 1 and t^(q-1), which
     reach the lowest and the highest product planes."""
