@@ -519,6 +519,8 @@ def main():
             "traffic": traffic,
             "valu_issue_frac": valu_frac,
             "valu_probe_lane_ops_per_s": round(valu_rate, -9),
+            # 256 CUs x 4 SIMDs x 16 lanes issue one v_bitop3_b32 lane-op per clock
+            "probe_clock_ghz": round(valu_rate / (256 * 64) / 1e9, 3) if valu_rate > 0 else None,
             "note": "achieved counts the schoolbook n*m bit-MACs per pair; peak is one "
                     "32-bit AND-XOR (v_bitop3_b32) per lane per clock on every lane; the "
                     "kernel uses Karatsuba, so frac above 1 is possible; valu_issue_frac is "
