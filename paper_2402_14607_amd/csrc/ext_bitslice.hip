@@ -16,14 +16,15 @@
 //   1. stages the chunk's bytes of both sides in LDS as they are, with
 //      16-byte loads issued one chunk ahead (in flight during the products of
 //      the chunk before);
-//   2. transposes them: item (side, element, word w) gathers word w of the
+//   2. transposes them: item (word w, side, element) gathers word w of the
 //      element of the 32 pairs, transposes the 32x32 bit matrix in registers
 //      and writes 32 planes (zero at or above q); Y planes have zero margins
 //      before (kYLo) and after (kYHi);
-//   3. multiplies: lane (16x16 tile position (j-block, t-block), element
-//      subset) accumulates the tile's 16 output planes in registers (x[j] for
-//      16 j, y[t - j] from a 31-plane window) over its elements of the chunk.
-// After the last chunk the lanes XOR their tiles into the shared sum C (LDS
+//   3. multiplies: lane (16x16 tile position (j-block, t-block offset),
+//      element subset) accumulates the tile's output planes in registers
+//      (x[j] for 16 j, y[t - j] from two windows of 16 and 15 planes) over
+//      its elements of the chunk, keeping the sums across chunks.
+// After the last chunk the lanes XOR their sums into the shared sum C (LDS
 // atomics); then C is reduced modulo P, one output plane per lane (two
 // folding passes, taps below q/2); lane w transposes planes 32w .. 32w+31 back
 // into word w of the 32 outputs, and the work-group stores its npw*q/8 bytes.
