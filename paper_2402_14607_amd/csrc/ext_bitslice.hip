@@ -121,6 +121,11 @@ constexpr uint32_t kRawSkew = 16;          // extra words before side Y's raw by
 // different banks.
 __host__ __device__ constexpr uint32_t bs_pad(uint32_t m) { return kPadBlock * (m >> 4) + (m & 15u); }
 
+// Whether the diagonal tiles are folded (one lane takes both triangles).  It
+// saves a sixth of the products at q = 80 but holds 16 more registers per
+// lane; measured on MI355X over q = 32 .. 112, it pays from q = 96 on.
+__host__ __device__ constexpr bool bs_fold(uint32_t q) { return q % kTile == 0 && q >= 96; }
+
 // Geometry of the kernel for (q, n_e) and a work-group of nt lanes; the host
 // sizes LDS with the same function.  Elements are processed in chunks of ec:
 // each chunk's bytes are staged raw, transposed into planes, multiplied.
@@ -147,7 +152,7 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
     // runs to (q + 14) / 16.  When 16 divides q, the tile at dt = 0 needs only
     // j <= t and the one at dt = q/16 only j > t: one lane takes both halves
     // (256 operations, like a full tile), and dt runs to q/16 - 1.
-    g.fold = q % kTile == 0 ? 1u : 0u;
+    g.fold = bs_fold(q) ? 1u : 0u;
     g.reach = g.fold ? q / kTile : (q + 14) / kTile + 1;
     g.n_pos = g.jb_n * g.reach;           // at most 72 (q = 120)
     uint32_t s = nt / g.n_pos;
@@ -173,7 +178,11 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
 
 // Work-group of nt = 256 lanes over npw <= 32 pairs from pair0; the pairs'
 // blocks form one contiguous region of npw*nbytes bytes per side.
-__global__ void __launch_bounds__(kThreads, 3)
+// FOLD: the kernel for shapes with bs_fold(q) (two 16-plane sums per lane).
+// Four work-groups per CU (4 waves per SIMD): FOLD = false needs no more than
+// 128 VGPRs; FOLD = true spills a few registers outside the inner loops.
+template <bool FOLD>
+__global__ void __launch_bounds__(kThreads, 4)
 bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
                 uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -272,9 +281,12 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     // [-kYLo, jp + kYHi) since 16 db <= q + 14 and jp >= q
     const uint32_t xoff = jb * kPadBlock;
     const uint32_t yoff_a = (da + 1) * kPadBlock, yoff_b = db * kPadBlock + 1;
-    uint32_t acc_lo[kTile], acc_hi[kTile];
+    // (not folded: da == db, both halves go to acc_lo and acc_hi stays unused)
+    uint32_t acc_lo[kTile], acc_hi[FOLD ? kTile : 1];
 #pragma unroll
-    for (uint32_t i = 0; i < kTile; ++i) acc_lo[i] = acc_hi[i] = 0u;
+    for (uint32_t i = 0; i < kTile; ++i) acc_lo[i] = 0u;
+#pragma unroll
+    for (uint32_t i = 0; i < (FOLD ? kTile : 1); ++i) acc_hi[i] = 0u;
 
     const uint32_t n_chunks = (n_e + ec - 1) / ec;
     load_chunk(0);
@@ -288,13 +300,17 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
         // pairs past npw were staged as zero), transposes, and writes planes
         // 32w .. 32w + 31.  Items run word-major, so a wave holds one or two
         // words and the last word's byte mask and plane bound rarely diverge.
-        const uint32_t items = 2 * e_cnt * qw;
-        const uint32_t rcp_2e = bs_recip(2 * e_cnt);  // items < 2^16
-        for (uint32_t it = tid; it < items; it += nt) {
-            const uint32_t w = bs_div(it, rcp_2e);
-            const uint32_t rem = it - w * (2 * e_cnt);
-            const uint32_t side = rem >= e_cnt ? 1u : 0u;
-            const uint32_t le = rem - side * e_cnt;
+        // each side's items fill whole waves (padded to 64 slots), so the side,
+        // and with it the pairs' byte offsets, are uniform across a wave
+        const uint32_t side_items = e_cnt * qw;
+        const uint32_t side_slots = (side_items + 63u) & ~63u;
+        const uint32_t rcp_e = bs_recip(e_cnt);  // side_items < 2^16
+        for (uint32_t it = tid; it < 2 * side_slots; it += nt) {
+            const uint32_t side = __builtin_amdgcn_readfirstlane(it >= side_slots ? 1u : 0u);
+            const uint32_t r = it - side * side_slots;
+            if (r >= side_items) continue;
+            const uint32_t w = bs_div(r, rcp_e);  // word-major within the side
+            const uint32_t le = r - w * e_cnt;
             const uint32_t* rs = raw + side * (kBsPairs * 4 * units + kRawSkew);
             const uint32_t lead = side ? lead_y : lead_x;
             const uint32_t lt = le * qb + 4u * w;  // byte of the word in the pair's chunk
@@ -302,10 +318,14 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
             // both words are always read (the second may be the next pair's
             // or a slack word) so that the 64 reads issue back to back
 #pragma unroll
-            for (uint32_t p = 0; p < 32; ++p) {
-                const uint32_t o = ((lead + p * nbytes + eoff) & 15u) + lt;
-                const uint32_t* r2 = rs + p * 4 * units + (o >> 2);
-                a[p] = bs_funnel(r2[1], r2[0], o * 8u);
+            for (uint32_t h = 0; h < 32; h += 8) {
+#pragma unroll
+                for (uint32_t p = h; p < h + 8; ++p) {
+                    const uint32_t o = ((lead + p * nbytes + eoff) & 15u) + lt;
+                    const uint32_t* r2 = rs + p * 4 * units + (o >> 2);
+                    a[p] = bs_funnel(r2[1], r2[0], o * 8u);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (qb - 4u * w < 4u) {  // the element's last word: bytes past q/8 are the next one's
                 const uint32_t keep = (1u << (8u * (qb - 4u * w))) - 1u;
@@ -325,7 +345,6 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
             }
         }
         __syncthreads();
-        if (c + 1 < n_chunks) load_chunk(c + 1);  // in flight during the products
         // ---- products: c[t] ^= x[j] & y[t - j] over the 16x16 tile
         if (active) {
             for (uint32_t le = sub; le < e_cnt; le += g.subsets) {
@@ -348,11 +367,18 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
 #pragma unroll
                 for (uint32_t i = 0; i < kTile; ++i)
 #pragma unroll
-                    for (uint32_t jj = i + 1; jj < kTile; ++jj)
-                        acc_hi[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_hi[i]);
+                    for (uint32_t jj = i + 1; jj < kTile; ++jj) {
+                        if constexpr (FOLD)
+                            acc_hi[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_hi[i]);
+                        else
+                            acc_lo[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_lo[i]);
+                    }
             }
         }
-        if (c + 1 < n_chunks) store_chunk(c + 1);
+        if (c + 1 < n_chunks) {  // the next chunk's bytes (raw is free after the transposes)
+            load_chunk(c + 1);
+            store_chunk(c + 1);
+        }
         __syncthreads();
     }
     if (active) {  // t-blocks below tb_n + 1 (folded: jb + q/16 <= 2q/16 - 1)
@@ -360,12 +386,16 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
         uint32_t* cb = cp + (jb + db) * kTile;
 #pragma unroll
         for (uint32_t i = 0; i < kTile; ++i) {
-            if (da == db) {
-                const uint32_t v = acc_lo[i] ^ acc_hi[i];
-                if (v) atomicXor(ca + i, v);
+            if constexpr (FOLD) {
+                if (da == db) {
+                    const uint32_t v = acc_lo[i] ^ acc_hi[i];
+                    if (v) atomicXor(ca + i, v);
+                } else {
+                    if (acc_lo[i]) atomicXor(ca + i, acc_lo[i]);
+                    if (acc_hi[i]) atomicXor(cb + i, acc_hi[i]);
+                }
             } else {
                 if (acc_lo[i]) atomicXor(ca + i, acc_lo[i]);
-                if (acc_hi[i]) atomicXor(cb + i, acc_hi[i]);
             }
         }
     }
@@ -439,8 +469,12 @@ hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
     const uint32_t lds = g.total * 4u;
     if (lds > 65536u) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(bitslice_kernel, dim3((uint32_t)groups), dim3(kThreads), lds, stream, x, y,
-                       out, n_pairs, s);
+    if (bs_fold(s.q))
+        hipLaunchKernelGGL(bitslice_kernel<true>, dim3((uint32_t)groups), dim3(kThreads), lds,
+                           stream, x, y, out, n_pairs, s);
+    else
+        hipLaunchKernelGGL(bitslice_kernel<false>, dim3((uint32_t)groups), dim3(kThreads), lds,
+                           stream, x, y, out, n_pairs, s);
     return hipGetLastError();
 }
 
