@@ -14,9 +14,9 @@
 // The 32 pairs' blocks are one contiguous region per side.  The elements are
 // taken in chunks of ec; for each chunk a work-group (256 lanes)
 //   1. stages the chunk's bytes of both sides in LDS as they are, with
-//      16-byte loads issued one chunk ahead (in flight during the products of
-//      the chunk before);
-//   2. transposes them: item (word w, side, element) gathers word w of the
+//      16-byte loads (issued after the products of the chunk before, when
+//      the raw area is free);
+//   2. transposes them: item (side, word w, element) gathers word w of the
 //      element of the 32 pairs, transposes the 32x32 bit matrix in registers
 //      and writes 32 planes (zero at or above q); Y planes have zero margins
 //      before (kYLo) and after (kYHi);
@@ -215,9 +215,9 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
 
     // ---- staging: unit k = (side, pair p, u) of chunk c is the 16-byte unit
     // (lead + p*nbytes + c*ec*qb) / 16 + u of the side's raw region.  Units
-    // inside the region are loaded (in flight while the chunk before is
-    // multiplied); units that straddle an end are read bytewise when stored;
-    // units outside it, and of pairs past npw, are zero.
+    // inside the region are loaded with 16-byte loads; units that straddle an
+    // end are read bytewise when stored; units outside it, and of pairs past
+    // npw, are zero.
     const uint32_t n_units = 2 * kBsPairs * units;  // <= kStageRegs * nt
     // slot r of this lane: unit k = tid + r*nt, packed as (lead + p*nbytes) << 4 | u
     // (below 2^32: nbytes < 2^23), or ~0 for no unit (k >= n_units or p >= npw)
@@ -295,13 +295,12 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     for (uint32_t c = 0; c < n_chunks; ++c) {
         const uint32_t e_cnt = (c + 1) * ec <= n_e ? ec : n_e - c * ec;
         const uint32_t eoff = c * ec * qb;
-        // ---- transposes: item (word w, side, element le) gathers word w of
+        // ---- transposes: item (side, word w, element le) gathers word w of
         // element le of the 32 pairs (two LDS words and a funnel shift each;
         // pairs past npw were staged as zero), transposes, and writes planes
-        // 32w .. 32w + 31.  Items run word-major, so a wave holds one or two
-        // words and the last word's byte mask and plane bound rarely diverge.
-        // each side's items fill whole waves (padded to 64 slots), so the side,
-        // and with it the pairs' byte offsets, are uniform across a wave
+        // 32w .. 32w + 31.  Each side's items fill whole waves (padded to 64
+        // slots), so the side, and with it the pairs' byte offsets, are uniform
+        // across a wave; within a side the items run word-major
         const uint32_t side_items = e_cnt * qw;
         const uint32_t side_slots = (side_items + 63u) & ~63u;
         const uint32_t rcp_e = bs_recip(e_cnt);  // side_items < 2^16
