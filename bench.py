@@ -386,8 +386,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every block pair is independent, so N GPUs "
-              "would each run this same kernel on their own share (see DESIGN.md); "
-              "--gpus %d is not supported." % args.gpus, file=sys.stderr)
+              "would each run this same kernel on their own range of block pairs and write "
+              "their outputs in place, with no exchange; --gpus %d is not supported."
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
