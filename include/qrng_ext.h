@@ -28,10 +28,12 @@
  *   - output coefficient j of Z^(l) is output bit l*m + j, bytes LSB first
  *     (m/8 bytes per block pair, little-endian 32-bit words).
  *
- * Supported shapes on the GPU path: m a multiple of 32 whose odd part
- * (m/32 with all factors 2 removed) is at most 15, n a multiple of m,
- * and every non-leading exponent of P below m/2.  Everything else returns
- * EXT_ENOTSUP.
+ * Supported shapes on the GPU path: m a multiple of 8 (and of b), n a
+ * multiple of m, and every non-leading exponent of P at most m/2 (the
+ * conventional modulus qualifies for every such m up to 4096).  Fields whose
+ * degree is not a multiple of 32, or whose word count has an odd part above
+ * 15, are computed in zero-padded slots; blocks and outputs may then sit at
+ * any byte.  Everything else returns EXT_ENOTSUP.
  *
  * Errors: every call returns EXT_OK (0) or a negative ext_status; no call
  * aborts or throws.  A HIP failure is reported as EXT_EDEVICE and is sticky:
@@ -96,7 +98,10 @@ typedef struct {
                                    the bit-sliced kernel for fields of 32 to 112 bits
                                    that 16 divides with at least 30 elements per block
                                    (where it measured faster), or, with autotune set,
-                                   whichever of the two times faster for the shape */
+                                   whichever of the two times faster for the shape.
+                                   The batched, served and growing forms run the
+                                   word-level kernel: they answer EXT_KERNEL_BITSLICE
+                                   with EXT_ENOTSUP */
     uint32_t reserved[2];
 } ext_params;
 enum { EXT_KERNEL_AUTO = 0, EXT_KERNEL_WORD = 1, EXT_KERNEL_BITSLICE = 2 };

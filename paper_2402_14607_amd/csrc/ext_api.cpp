@@ -60,7 +60,7 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
         if (taps[t] == 0 || taps[t] >= q) return false;
         max_tap = std::max(max_tap, taps[t]);
     }
-    if (2 * max_tap > q) return false;  // two folding passes suffice only below q/2
+    if (2 * max_tap > q) return false;  // two folding passes suffice up to q/2
     // element groups: g groups of ceil(n_e / g) elements (the last may hold
     // fewer), for every g that this partition realises exactly
     auto realised = [&](uint32_t g) { return (n_e + (n_e + g - 1) / g - 1) / ((n_e + g - 1) / g) == g; };
@@ -228,8 +228,10 @@ int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs
 // The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits and
 // blocks below 8 MiB (its chunked planes stay below 64 KiB of LDS).
 bool bitslice_applies(const ExtShape& s) {
+    uint32_t max_tap = 0;  // its reduction folds twice, which suffices up to q/2
+    for (uint32_t k = 0; k < s.n_taps; ++k) max_tap = std::max(max_tap, s.taps[k]);
     return s.q <= qext::kBitsliceMaxQ && s.q % 8 == 0 && s.nbytes < (1u << 23) &&
-           (uint64_t)qext::bitslice_lds_words(s) * 4 <= 65536;
+           2 * max_tap <= s.q && (uint64_t)qext::bitslice_lds_words(s) * 4 <= 65536;
 }
 
 // EXT_KERNEL_AUTO's choice without autotuning, among the shapes the

@@ -277,6 +277,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
     ext_params_init(&def);
     if (!p) p = &def;
     if (p->n_taps) return EXT_EINVAL;  // batches use the conventional modulus of each m
+    if (p->kernel > EXT_KERNEL_BITSLICE) return EXT_EINVAL;
+    if (p->kernel == EXT_KERNEL_BITSLICE) return EXT_ENOTSUP;  // word-level kernels only
     ext_batch* b = new (std::nothrow) ext_batch;
     if (!b) return EXT_ENOMEM;
     int dev = p->device;

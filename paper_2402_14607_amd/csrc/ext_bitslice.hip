@@ -26,7 +26,7 @@
 //      its elements of the chunk, keeping the sums across chunks.
 // After the last chunk the lanes XOR their sums into the shared sum C (LDS
 // atomics); then C is reduced modulo P, one output plane per lane (two
-// folding passes, taps below q/2); lane w transposes planes 32w .. 32w+31 back
+// folding passes, taps at most q/2); lane w transposes planes 32w .. 32w+31 back
 // into word w of the 32 outputs, and the work-group stores its npw*q/8 bytes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -402,7 +402,7 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
 
     // ---- reduction modulo P ------------------------------------------
     // C = C_lo + t^q H with H[i] = c[q + i] (i <= q - 2) and t^q = 1 + sum_f t^f
-    // (every tap f < q/2).  t^f H = (t^f H mod t^q) + t^q U_f with U_f[i] =
+    // (every tap f <= q/2).  t^f H = (t^f H mod t^q) + t^q U_f with U_f[i] =
     // H[i + q - f] = c[2q + i - f] for i <= f - 2; D = sum_f U_f; t^q D = D +
     // sum_g t^g D needs no further reduction.  Output plane t < q:
     //   z[t] = c[t] + H[t] + sum_f H[t - f] + D[t] + sum_g D[t - g].

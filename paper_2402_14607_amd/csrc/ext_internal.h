@@ -28,7 +28,7 @@ struct ExtShape {
     uint32_t epg;      // elements per group (n_e / groups)
     uint32_t stage;    // 1: the work-group's input blocks are staged in LDS
     uint32_t n_taps;   // 1 (trinomial) or 3 (pentanomial)
-    uint32_t taps[3];  // non-leading nonzero exponents of P, each < q/2
+    uint32_t taps[3];  // non-leading nonzero exponents of P, each at most q/2
     uint32_t dn;       // words of the second reduction pass, ceil((max tap - 1)/32)
     uint32_t lds_words;
     uint32_t align;    // required byte alignment of x and y (16 when operands are

@@ -196,6 +196,13 @@ def test_selection_errors(dev):
     with pytest.raises(binding.ExtError) as e:
         binding.Extractor(136 * 4, 136, kernel=BS)      # q above 128
     assert e.value.code == binding.EXT_ENOTSUP
+    # a modulus with a tap above q/2 (the reciprocal of the conventional one
+    # of degree 64) needs more than two folding passes: neither kernel takes it
+    assert oracle.is_irreducible(64, (64, 63, 61, 60, 0))
+    for kernel in (BS, binding.KERNEL_AUTO):
+        with pytest.raises(binding.ExtError) as e:
+            binding.Extractor(64 * 40, 64, taps=(63, 61, 60), kernel=kernel)
+        assert e.value.code == binding.EXT_ENOTSUP, kernel
     with pytest.raises(binding.ExtError) as e:
         binding.Extractor(1024, 256, kernel=3)
     assert e.value.code == binding.EXT_EINVAL

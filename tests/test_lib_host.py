@@ -81,3 +81,23 @@ def test_strerror_and_bad_arguments():
     assert lib.ext_create(1000 * 24, 24, ctypes.byref(p), ctypes.byref(h)) == binding.EXT_EINVAL
     assert lib.ext_destroy(None) == 0
     assert lib.ext_submit(None, None, 0, None, 0, None) == binding.EXT_EINVAL
+
+
+def test_word_only_forms_refuse_the_bitsliced_kernel():
+    """The batched, served and growing forms run the word-level kernel: a
+    request for the bit-sliced one is EXT_ENOTSUP, an unknown kernel value
+    EXT_EINVAL, both answered before any device call."""
+    import ctypes
+
+    lib = binding.load()
+    for kernel, want in ((binding.KERNEL_BITSLICE, binding.EXT_ENOTSUP), (3, binding.EXT_EINVAL)):
+        p = binding.make_params(lib, kernel=kernel)
+        h = ctypes.c_void_p()
+        item = binding.BatchItem()
+        item.n_bits, item.m_bits, item.n_pairs = 5680, 80, 1
+        assert lib.ext_batch_create(ctypes.byref(item), 1, ctypes.byref(p), ctypes.byref(h)) == want
+        cfg = binding.ServerConfig()
+        lib.ext_server_config_init(ctypes.byref(cfg))
+        assert lib.ext_server_create(ctypes.byref(cfg), ctypes.byref(p), ctypes.byref(h)) == want
+        assert lib.ext_growing_create(71, 80, 1, ctypes.byref(p), ctypes.byref(h)) == want
+        assert not h.value
