@@ -227,3 +227,35 @@ def test_auto_choice(dev):
         ex.extract(to_dev(dev, w.x), to_dev(dev, w.y), out, 45)
         ex.sync()
     assert np.array_equal(out.cpu().numpy(), oracle.ext_blocks(w.x, w.y, 5680, 80))
+
+
+def test_random_shapes_against_oracle(dev):
+    """40 seeded random cases: q any multiple of 8 up to 128, 1 to 160
+    elements, 1 to 100 pairs, inputs at 4-byte offsets from a 16-byte
+    boundary, canary bytes after the output; full compare with the oracle."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(2024))
+    for case in range(40):
+        m = 8 * int(rng.integers(1, 17))
+        n_e = int(rng.integers(1, 161))
+        pairs = int(rng.integers(1, 101))
+        off_x, off_y = 4 * int(rng.integers(0, 4)), 4 * int(rng.integers(0, 4))
+        n = m * n_e
+        nb = pairs * n // 8
+        x = rng.integers(0, 256, nb, dtype=np.uint8)
+        y = rng.integers(0, 256, nb, dtype=np.uint8)
+        say("random case %d: m=%d n_e=%d pairs=%d offsets %d/%d" % (case, m, n_e, pairs, off_x, off_y))
+        bx = torch.zeros(nb + 32, dtype=torch.uint8, device=dev)
+        by = torch.zeros(nb + 32, dtype=torch.uint8, device=dev)
+        bx[off_x:off_x + nb] = to_dev(dev, x)
+        by[off_y:off_y + nb] = to_dev(dev, y)
+        qb = m // 8
+        out = torch.full((pairs * qb + 16,), 0xA5, dtype=torch.uint8, device=dev)
+        with binding.Extractor(n, m, device_memory=True, kernel=BS,
+                               stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+            ex.extract(bx[off_x:off_x + nb], by[off_y:off_y + nb], out, pairs)
+            ex.sync()
+        got = out.cpu().numpy()
+        assert np.array_equal(got[:pairs * qb], oracle.ext_blocks(x, y, n, m)), case
+        assert np.all(got[pairs * qb:] == 0xA5), case
