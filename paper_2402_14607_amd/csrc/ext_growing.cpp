@@ -40,12 +40,32 @@ struct ext_growing {
     uint64_t cap_blocks = 0;
     uint8_t *dx = nullptr, *dy = nullptr, *dout = nullptr;  // host-memory mode
     uint64_t cap_in = 0, cap_out = 0;
+    // the launches of one call (one per base size) are independent: they run
+    // on lane streams forked from and joined back into `stream` with events
+    static constexpr int kLanes = 4;
+    hipStream_t lanes[kLanes] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t joins[kLanes] = {};
     int sticky = EXT_OK;
 };
 
 namespace {
 
 constexpr uint32_t kMaxGroups = 64;  // distinct (base size, work-group size) launches per call
+
+void release_lanes(ext_growing* g) {
+    for (int i = 0; i < ext_growing::kLanes; ++i) {
+        if (g->lanes[i]) {
+            (void)hipStreamSynchronize(g->lanes[i]);
+            (void)hipStreamDestroy(g->lanes[i]);
+        }
+        if (g->joins[i]) (void)hipEventDestroy(g->joins[i]);
+        g->lanes[i] = nullptr;
+        g->joins[i] = nullptr;
+    }
+    if (g->fork) (void)hipEventDestroy(g->fork);
+    g->fork = nullptr;
+}
 
 void free_scratch(ext_growing* g) {
     (void)hipFree(g->d_streams);
@@ -172,6 +192,17 @@ int ext_growing_create(uint32_t n_e, uint32_t q1, uint32_t delta_steps, const ex
         delete g;
         return EXT_EDEVICE;
     }
+    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < ext_growing::kLanes; ++i)
+        ok = hipStreamCreateWithFlags(&g->lanes[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&g->joins[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        release_lanes(g);
+        if (g->own_stream) (void)hipStreamDestroy(g->stream);
+        delete g;
+        return EXT_EDEVICE;
+    }
     *out = g;
     return EXT_OK;
 }
@@ -224,6 +255,7 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
         // from here on work is queued: every exit waits for the stream first,
         // so no copy still reads the caller's or these host buffers
         auto device_error = [&]() {
+            for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
             (void)hipStreamSynchronize(g->stream);
             (void)hipGetLastError();
             return g->sticky = EXT_EDEVICE;
@@ -237,6 +269,7 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
         struct L {
             uint32_t bw, threads, off, n, lds, grid;
+            uint64_t cost;  // sum of its tiles' costs
         };
         std::vector<L> launches;
         for (auto& kv : groups) {
@@ -244,8 +277,9 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
             // longest tiles first, so the queue ends with short ones
             std::stable_sort(v.begin(), v.end(),
                              [](const auto& a, const auto& c) { return a.first > c.first; });
-            L ln{kv.first.first, kv.first.second, (uint32_t)tiles.size(), (uint32_t)v.size(), 0, 0};
+            L ln{kv.first.first, kv.first.second, (uint32_t)tiles.size(), (uint32_t)v.size(), 0, 0, 0};
             for (auto& t : v) {
+                ln.cost += t.first;
                 tiles.push_back(BatchTile{t.second, 1, 0, 0, 0, 0});
                 ln.lds = std::max(ln.lds, streams[t.second].shape.lds_words * 4);
             }
@@ -260,10 +294,33 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
             hipMemcpyAsync(g->d_tiles, tiles.data(), r.k * sizeof(BatchTile),
                            hipMemcpyHostToDevice, g->stream))
             return device_error();
-        for (size_t i = 0; i < launches.size(); ++i) {
+        // fork: the lanes start after the table copies (and the caller's work
+        // queued before this call); costliest launches first, each on the
+        // least loaded lane; join: the stream waits for every lane used
+        if (hipEventRecord(g->fork, g->stream) != hipSuccess) return device_error();
+        std::vector<size_t> order(launches.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t c) { return launches[a].cost > launches[c].cost; });
+        uint64_t load[ext_growing::kLanes] = {};
+        bool used[ext_growing::kLanes] = {};
+        for (size_t i : order) {
             const L& ln = launches[i];
+            int lane = 0;
+            for (int l = 1; l < ext_growing::kLanes; ++l)
+                if (load[l] < load[lane]) lane = l;
+            if (!used[lane] && hipStreamWaitEvent(g->lanes[lane], g->fork, 0) != hipSuccess)
+                return device_error();
+            used[lane] = true;
+            load[lane] += ln.cost + 1;
             if (qext::launch_batch(ln.bw, ln.threads, true, g->d_streams, g->d_tiles + ln.off, ln.n,
-                                   g->d_heads + i, ln.grid, ln.lds, g->stream) != hipSuccess)
+                                   g->d_heads + i, ln.grid, ln.lds, g->lanes[lane]) != hipSuccess)
+                return device_error();
+        }
+        for (int l = 0; l < ext_growing::kLanes; ++l) {
+            if (!used[l]) continue;
+            if (hipEventRecord(g->joins[l], g->lanes[l]) != hipSuccess ||
+                hipStreamWaitEvent(g->stream, g->joins[l], 0) != hipSuccess)
                 return device_error();
         }
         if (host && hipMemcpyAsync(out, g->dout, r.out_bytes, hipMemcpyDeviceToHost, g->stream))
@@ -281,6 +338,7 @@ int ext_growing_destroy(ext_growing* g) {
     if (!g) return EXT_EINVAL;
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
+    release_lanes(g);
     free_scratch(g);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
