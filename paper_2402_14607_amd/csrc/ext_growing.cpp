@@ -289,9 +289,14 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
             ln.grid = (uint32_t)std::min<uint64_t>(ln.n, (uint64_t)cus * occ);
             launches.push_back(ln);
         }
+        // the tables and the launches' zeroed queue heads, in stream order
+        // before the lanes fork (a copy, so that no launch needs a reset kernel)
+        static const uint32_t kZeroHeads[kMaxGroups] = {};
         if (hipMemcpyAsync(g->d_streams, streams.data(), r.k * sizeof(BatchStream),
                            hipMemcpyHostToDevice, g->stream) ||
             hipMemcpyAsync(g->d_tiles, tiles.data(), r.k * sizeof(BatchTile),
+                           hipMemcpyHostToDevice, g->stream) ||
+            hipMemcpyAsync(g->d_heads, kZeroHeads, launches.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, g->stream))
             return device_error();
         // fork: the lanes start after the table copies (and the caller's work
@@ -313,8 +318,9 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
                 return device_error();
             used[lane] = true;
             load[lane] += ln.cost + 1;
-            if (qext::launch_batch(ln.bw, ln.threads, true, g->d_streams, g->d_tiles + ln.off, ln.n,
-                                   g->d_heads + i, ln.grid, ln.lds, g->lanes[lane]) != hipSuccess)
+            if (qext::launch_batch_noreset(ln.bw, ln.threads, true, g->d_streams,
+                                           g->d_tiles + ln.off, ln.n, g->d_heads + i, nullptr,
+                                           ln.grid, ln.lds, g->lanes[lane]) != hipSuccess)
                 return device_error();
         }
         for (int l = 0; l < ext_growing::kLanes; ++l) {
