@@ -109,9 +109,9 @@ __host__ __device__ inline uint32_t bs_recip(uint32_t d) {
 }
 __device__ __forceinline__ uint32_t bs_div(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
 
-constexpr uint32_t kElemsPerLane = 2;  // elements per product lane per chunk
+constexpr uint32_t kElemsPerLane = 3;  // elements per product lane per chunk
 constexpr uint32_t kStageRegs = 4;     // 16-byte staging loads per lane per chunk
-constexpr uint32_t kChunkBytes = 224;  // most bytes of one pair's chunk (units <= 16)
+constexpr uint32_t kChunkBytes = 240;  // most bytes of one pair's chunk (units <= 16)
 constexpr uint32_t kChunkElems = 128;  // most elements per chunk (LDS stays below 56 KiB)
 constexpr uint32_t kPadBlock = kTile + 1;  // LDS words per 16 planes (one pad word)
 constexpr uint32_t kRawSkew = 16;          // extra words before side Y's raw bytes (banks)
@@ -126,9 +126,10 @@ __host__ __device__ constexpr uint32_t bs_pad(uint32_t m) { return kPadBlock * (
 // lane; measured on MI355X over q = 32 .. 112, it pays from q = 96 on.
 __host__ __device__ constexpr bool bs_fold(uint32_t q) { return q % kTile == 0 && q >= 96; }
 
-// Geometry of the kernel for (q, n_e) and a work-group of nt lanes; the host
-// sizes LDS with the same function.  Elements are processed in chunks of ec:
-// each chunk's bytes are staged raw, transposed into planes, multiplied.
+// Geometry of the kernel for (q, n_e) and a work-group of nt lanes, computed
+// once per launch on the host and passed to the kernel.  Elements are
+// processed in chunks of ec: each chunk's bytes are staged raw, transposed
+// into planes, multiplied.
 struct BsGeom {
     uint32_t qb, qw, jp, xs, ys;
     uint32_t jb_n, tb_n, reach, n_pos;  // product tiles: positions (j-block, offset)
@@ -137,7 +138,7 @@ struct BsGeom {
     uint32_t raw, xp, yp, cp, zp, ot, total;  // LDS word offsets and size
 };
 
-__host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt) {
+inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt) {
     BsGeom g;
     g.qb = q / 8;
     g.qw = (q + 31) / 32;
@@ -162,17 +163,24 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
     if (ec > n_e) ec = n_e;
     if (ec > kChunkBytes / g.qb) ec = kChunkBytes / g.qb;
     if (ec > kChunkElems) ec = kChunkElems;
+    // the largest chunk whose layout fits 40 KiB (four work-groups on a CU's
+    // 160 KiB) while it still holds an element for every subset, and 64 KiB
+    for (;;) {
+        g.ec = ec;
+        g.units = (ec * g.qb + 14) / 16 + 1;  // covers ec*qb bytes at any offset mod 16
+        g.raw = 0;                            // [2 sides][32 pairs][4*units], sides kRawSkew
+        g.xp = 2 * kBsPairs * 4 * g.units + kRawSkew + 4;  // words apart, + 4 slack words
+        g.yp = g.xp + ec * g.xs;              // X planes [ec][xs]
+        g.cp = g.yp + ec * g.ys;              // Y planes [ec][ys], plane k at bs_pad(kYLo + k)
+        g.zp = g.cp + 2 * g.jp + kTile;       // C [2 jp + kTile]
+        g.ot = g.zp + g.jp;                   // Z [jp]
+        g.total = g.ot + kBsPairs * g.qw;     // outputs [32][qw]
+        if ((g.total * 4u <= 40960u || ec <= s) && g.total * 4u <= 65536u) break;
+        if (ec == 1) break;
+        --ec;
+    }
     if (s > ec) s = ec;
     g.subsets = s;
-    g.ec = ec;
-    g.units = (ec * g.qb + 14) / 16 + 1;  // covers ec*qb bytes at any offset mod 16
-    g.raw = 0;                            // [2 sides][32 pairs][4*units], sides kRawSkew
-    g.xp = 2 * kBsPairs * 4 * g.units + kRawSkew + 4;  // words apart, + 4 slack words
-    g.yp = g.xp + ec * g.xs;              // X planes [ec][xs]
-    g.cp = g.yp + ec * g.ys;              // Y planes [ec][ys], plane k at bs_pad(kYLo + k)
-    g.zp = g.cp + 2 * g.jp + kTile;       // C [2 jp + kTile]
-    g.ot = g.zp + g.jp;                   // Z [jp]
-    g.total = g.ot + kBsPairs * g.qw;     // outputs [32][qw]
     return g;
 }
 
@@ -184,11 +192,10 @@ __host__ __device__ inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt)
 template <bool FOLD>
 __global__ void __launch_bounds__(kThreads, 4)
 bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
-                uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh) {
+                uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh, BsGeom g) {
     extern __shared__ __align__(16) uint32_t lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t q = sh.q, n_e = sh.n_e, nbytes = sh.nbytes;
-    const BsGeom g = bs_geom(q, n_e, nt);
     const uint32_t qb = g.qb, qw = g.qw, jp = g.jp, xs = g.xs, ys = g.ys, ec = g.ec;
     const uint32_t units = g.units;
     uint32_t* raw = lds + g.raw;
@@ -470,10 +477,10 @@ hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y
     if (lds > 65536u) return hipErrorInvalidValue;
     if (bs_fold(s.q))
         hipLaunchKernelGGL(bitslice_kernel<true>, dim3((uint32_t)groups), dim3(kThreads), lds,
-                           stream, x, y, out, n_pairs, s);
+                           stream, x, y, out, n_pairs, s, g);
     else
         hipLaunchKernelGGL(bitslice_kernel<false>, dim3((uint32_t)groups), dim3(kThreads), lds,
-                           stream, x, y, out, n_pairs, s);
+                           stream, x, y, out, n_pairs, s, g);
     return hipGetLastError();
 }
 
