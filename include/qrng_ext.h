@@ -95,7 +95,7 @@ typedef struct {
                                    EXT_KERNEL_BITSLICE (32 pairs per work-group bit-sliced
                                    across pairs; fields of at most 128 bits, else
                                    EXT_ENOTSUP).  Both give the same bytes.  AUTO takes
-                                   the bit-sliced kernel for fields of 32 to 112 bits
+                                   the bit-sliced kernel for fields of 16 to 128 bits
                                    that 16 divides with at least 30 elements per block
                                    (where it measured faster), or, with autotune set,
                                    whichever of the two times faster for the shape.

@@ -235,13 +235,13 @@ bool bitslice_applies(const ExtShape& s) {
 }
 
 // EXT_KERNEL_AUTO's choice without autotuning, among the shapes the
-// bit-sliced kernel applies to: fields of 32 to 112 bits that 16 divides
-// (its product tiles fold, every lane's operations are useful) with at least
-// 30 elements per block.  Measured on MI355X over 18 shapes from (80, 4) to
-// (128, 100): in this region it is 1.1x to 2.6x faster than the word-level
-// kernel; outside it the word-level kernel was faster or within 7%.
+// bit-sliced kernel applies to: fields of 16 to 128 bits that 16 divides
+// (whole 16x16 product tiles) with at least 30 elements per block.  Measured
+// on MI355X over 19 shapes from (80, 4) to (128, 100): in this region it is
+// 1.0x (q = 128 at 40 elements) to 3.2x faster than the word-level kernel;
+// outside it the word-level kernel was faster or within 2%.
 bool bitslice_preferred(const ExtShape& s) {
-    return s.q % 16 == 0 && s.q >= 32 && s.q <= 112 && s.n_e >= 30;
+    return s.q % 16 == 0 && s.q >= 16 && s.q <= 128 && s.n_e >= 30;
 }
 
 }  // namespace
