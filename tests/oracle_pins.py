@@ -26,6 +26,11 @@ What each pin rests on:
   pin_moduli         the stored moduli are irreducible (Rabin), Rabin agrees with
                      brute-force trial division on small degrees, and the stored
                      modulus is the convention's choice (exhaustive for small q)
+  pin_sampled        the sampled path (block pairs listed by index, outputs packed
+                     densely in list order) returns, for every listed index, the
+                     bits the whole-stream path (pinned above) computes for that
+                     block pair: unsorted lists, repeats, the first and last pair,
+                     fields whose degree is not a multiple of 8
 """
 from __future__ import annotations
 
@@ -350,5 +355,32 @@ def pin_moduli(lib=None):
             q, table[q], best)
 
 
+def pin_sampled(lib=None):
+    rng = _rng(107)
+    for q, n_e in ((64, 4), (80, 3), (24, 5), (256, 2), (12, 2)):
+        nbits = q * n_e
+        blocks = 9
+        exps = oracle.modulus(q)
+        nbytes = (blocks * nbits + 7) // 8
+        x = rng.integers(0, 256, nbytes + 3, dtype=np.uint8)
+        y = rng.integers(0, 256, nbytes, dtype=np.uint8)
+        whole = np.unpackbits(oracle.ext_blocks(x, y, nbits, q, exps, lib=lib),
+                              bitorder="little")
+        assert whole.size >= blocks * q
+        # as many listed pairs as blocks: unsorted, with repeats, first and
+        # last included; then a random order of every block
+        lists = [np.asarray([8, 0, 3, 3, 7, 1, 8, 2, 5], dtype=np.uint64),
+                 rng.permutation(blocks).astype(np.uint64)]
+        for idx in lists:
+            got = np.unpackbits(oracle.ext_sampled(x, y, idx, nbits, q, exps, lib=lib),
+                                bitorder="little")
+            assert got.size == (idx.size * q + 7) // 8 * 8
+            for k, l in enumerate(idx.tolist()):
+                assert np.array_equal(got[k * q:(k + 1) * q], whole[l * q:(l + 1) * q]), \
+                    "sampled pair %d (block %d) differs from the whole-stream output, q=%d" % (
+                        k, l, q)
+            assert not got[idx.size * q:].any(), "bits after the last listed pair are set"
+
+
 ALL_PINS = [pin_fips197, pin_identity, pin_matrix, pin_no_reduction, pin_bilinear, pin_field,
-            pin_hadamard, pin_balanced, pin_partition, pin_moduli]
+            pin_hadamard, pin_balanced, pin_partition, pin_moduli, pin_sampled]

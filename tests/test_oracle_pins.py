@@ -41,6 +41,11 @@ MUTATIONS = [
      "xb[r] = (uint8_t)get_bit(x, l * q + r);"),
     ("drop_top_coefficient", "for (int64_t d = 2 * (int64_t)q - 2; d >= (int64_t)q; d--) {",
      "for (int64_t d = 2 * (int64_t)q - 3; d >= (int64_t)q; d--) {"),
+    # the sampled path's own index arithmetic (its anchors occur only there)
+    ("sampled_reads_kth_block", "uint64_t l = idx[k];", "uint64_t l = k;"),
+    ("sampled_output_at_block_index", "put_bit(out, k * (uint64_t)q + j, z[j]);",
+     "put_bit(out, l * (uint64_t)q + j, z[j]);"),
+    ("sampled_list_reversed", "uint64_t l = idx[k];", "uint64_t l = idx[n_idx - 1 - k];"),
 ]
 
 
