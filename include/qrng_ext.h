@@ -212,18 +212,36 @@ int ext_extract(ext_ctx *c, const void *x, const void *y, uint64_t n_pairs, void
 int ext_sync(ext_ctx *c);
 
 /*
- * Streaming form.  A stream is one (X, Y) channel pair fed in arbitrary
- * chunks; the partial block still waiting for data is kept on the device.
- * Block l is computed as soon as both sides hold (l+1)*n/8 bytes; outputs
- * come back from ext_poll strictly in block order, each exactly once.
+ * Streaming form: Algorithm 1 run online.  The paper's sources are unbounded
+ * sample streams X and Y (Sec. 3); block l is the restriction X_{I_l} of a
+ * source to the l-th run of n/b consecutive samples (Algorithm 1's loop over
+ * the index sets I_l), and the output is the concatenation Z^(0) Z^(1) ... of
+ * the per-block results (Thm. 3.6, Thm. 3.7).  A stream is one (X, Y) channel
+ * pair fed in chunks of any length, the two sides independently; the partial
+ * block still waiting for data stays on the device.  Block l is computed as
+ * soon as both sides hold (l+1)*n/8 bytes; outputs come back from ext_poll
+ * strictly in block order, each exactly once.
  */
-int ext_stream_open(ext_ctx *c, ext_stream **out);
 
 /*
- * Append x_len bytes to X and y_len bytes to Y (either may be 0).  The data
- * are copied before the call returns (host memory) or read in stream order on
- * the context's stream (device memory, borrowed until that work is done).
- * Launches the extraction of every block pair completed by this chunk.
+ * Open a stream on context c.  n_bits and m_bits give the stream's own block
+ * length and output size; 0 takes the context's.  A stream whose shape
+ * differs from the context's uses the context's modulus when m_bits equals
+ * the context's m, else the conventional modulus of degree m_bits (see
+ * Conventions), and the planner's default launch plan for its shape; its
+ * kernel follows the context's ext_params.kernel.  The shape rules are those
+ * of ext_create (EXT_EINVAL, EXT_ENOTSUP).  Memory kind, stream, device and
+ * the per-stream device_bytes_cap come from the context.  *out is released
+ * by ext_stream_close (or ext_destroy of c).
+ */
+int ext_stream_open(ext_ctx *c, uint64_t n_bits, uint32_t m_bits, ext_stream **out);
+
+/*
+ * Append x_len bytes to X and y_len bytes to Y (either may be 0): the next
+ * samples of each source, in order.  The data are copied before the call
+ * returns (host memory) or read in stream order on the context's stream
+ * (device memory, borrowed until that work is done).  Launches the
+ * extraction of every block pair I_l completed by this chunk.
  * EXT_EAGAIN: the bytes held on the device would exceed device_bytes_cap;
  * nothing was consumed -- poll, then submit again.
  * *seq_out (may be NULL) receives the number of block pairs launched so far.
@@ -232,10 +250,11 @@ int ext_submit(ext_stream *s, const void *x, size_t x_len, const void *y, size_t
                uint64_t *seq_out);
 
 /*
- * Non-blocking: copy finished outputs, in block order, into out (host or
- * device memory per mem_kind), at most out_cap bytes and only whole blocks
- * (m/8 bytes each).  *out_len receives the bytes written; *blocks_done (may
- * be NULL) the number of blocks returned so far over the stream's life.
+ * Non-blocking: copy finished outputs Z^(l), in block order (the
+ * concatenation of Thm. 3.6/3.7), into out (host or device memory per
+ * mem_kind), at most out_cap bytes and only whole blocks (m/8 bytes each).
+ * *out_len receives the bytes written; *blocks_done (may be NULL) the number
+ * of blocks returned so far over the stream's life.
  */
 int ext_poll(ext_stream *s, void *out, size_t out_cap, size_t *out_len, uint64_t *blocks_done);
 
@@ -245,9 +264,10 @@ int ext_drain(ext_stream *s, void *out, size_t out_cap, size_t *out_len, uint64_
 
 /*
  * Close the stream: the trailing partial block (fewer than n bits on either
- * side) is dropped and its size, max over the two sides, is reported in
- * *dropped_bits (may be NULL).  Outputs not yet polled are discarded.  The
- * handle is freed; using it afterwards is undefined.
+ * side; Algorithm 1 consumes whole blocks only) is dropped and its size, max
+ * over the two sides, is reported in *dropped_bits (may be NULL).  Outputs
+ * not yet polled are discarded.  The handle is freed; using it afterwards is
+ * undefined.
  */
 int ext_stream_close(ext_stream *s, uint64_t *dropped_bits);
 

@@ -175,7 +175,8 @@ def load() -> ctypes.CDLL:
         "ext_is_irreducible": (ctypes.c_int, [u32, u32p, u32]),
         "ext_extract": (ctypes.c_int, [vp, vp, vp, u64, vp]),
         "ext_sync": (ctypes.c_int, [vp]),
-        "ext_stream_open": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
+        "ext_stream_open": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.POINTER(vp)]),
         "ext_submit": (ctypes.c_int, [vp, vp, sz, vp, sz, u64p]),
         "ext_poll": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
         "ext_drain": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
@@ -339,18 +340,23 @@ class Extractor:
     def sync(self) -> None:
         _check(self.lib.ext_sync(self.handle), "ext_sync")
 
-    def open_stream(self) -> "Stream":
-        return Stream(self)
+    def open_stream(self, n_bits: int = 0, m_bits: int = 0) -> "Stream":
+        """A stream of the context's shape, or of its own (n_bits, m_bits)."""
+        return Stream(self, n_bits, m_bits)
 
 
 class Stream:
-    """One ext_stream (an (X, Y) channel pair) of an Extractor."""
+    """One ext_stream (an (X, Y) channel pair) of an Extractor; n_bits and
+    m_bits of 0 take the Extractor's shape."""
 
-    def __init__(self, ex: Extractor):
+    def __init__(self, ex: Extractor, n_bits: int = 0, m_bits: int = 0):
         self.ex = ex
         self.lib = ex.lib
         self.handle = ctypes.c_void_p()
-        _check(self.lib.ext_stream_open(ex.handle, ctypes.byref(self.handle)), "ext_stream_open")
+        self.n_bits = n_bits or ex.n_bits
+        self.m_bits = m_bits or ex.m_bits
+        _check(self.lib.ext_stream_open(ex.handle, n_bits, m_bits, ctypes.byref(self.handle)),
+               "ext_stream_open")
 
     def submit(self, x, x_len: int, y, y_len: int) -> int:
         """Returns EXT_OK or EXT_EAGAIN; raises on other errors."""
@@ -514,7 +520,10 @@ def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max
              producer_threads=4,
              config: ServerConfig | None = None, autotune=False):
     """Run the load generator.  channels: list of (n_bits, m_bits, pool_x, pool_y)
-    with uint8 numpy pools.  Returns (result dict, list of captured outputs or None)."""
+    with uint8 numpy pools, each read cyclically from its start.  capture: False,
+    True (every channel) or the indices of the channels whose whole output is
+    kept.  Returns (result dict, per-channel captured outputs (None for a
+    channel not captured) or None)."""
     lib = load()
     n = len(channels)
     nbits = (ctypes.c_uint64 * n)(*[c[0] for c in channels])
@@ -542,15 +551,22 @@ def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max
     cfg.seed = seed
     cfg.producer_threads = producer_threads
     caps = None
-    if capture:
+    if capture is not False and capture is not None:
+        # capture=True: every channel; else an iterable of channel indices
+        which = set(range(n)) if capture is True else {int(c) for c in capture}
         bufs = []
-        for (nb_, mb_, _, _) in channels:
+        for i, (nb_, mb_, _, _) in enumerate(channels):
+            if i not in which:
+                bufs.append(None)
+                continue
             # generous: every chunk of the horizon at the channel's share of the rate
-            share = raw_bytes_per_s / n * (warmup_s + duration_s) * 3.0 + 64 * nb_ // 8 * 4
+            share = (raw_bytes_per_s / n * (warmup_s + duration_s + grace_s) * 3.0
+                     + 64 * nb_ // 8 * 4)
             bufs.append(np.zeros(int(share * mb_ / (2 * nb_)) + 1024, dtype=np.uint8))
         caps = bufs
-        cfg.capture = (ctypes.c_void_p * n)(*[b.ctypes.data for b in bufs])
-        cfg.capture_cap = (ctypes.c_uint64 * n)(*[b.size for b in bufs])
+        cfg.capture = (ctypes.c_void_p * n)(*[b.ctypes.data if b is not None else None
+                                              for b in bufs])
+        cfg.capture_cap = (ctypes.c_uint64 * n)(*[b.size if b is not None else 0 for b in bufs])
     sc = config or server_config()
     cfg.server_cfg = ctypes.pointer(sc)
     p = make_params(lib, device_memory=False, autotune=autotune)
@@ -562,7 +578,8 @@ def simulate(channels, *, mode=EXT_SIM_SERVED, raw_bytes_per_s, min_chunk=1, max
         raise ExtError(rc, "ext_serve_simulate")
     out = {n_: getattr(res, n_) for n_, _ in SimResult._fields_ if n_ != "reserved"}
     out["admission_gave_up"] = rc == EXT_EAGAIN
-    captured = [b[: clen[i]] for i, b in enumerate(caps)] if caps is not None else None
+    captured = ([b[: clen[i]] if b is not None else None for i, b in enumerate(caps)]
+                if caps is not None else None)
     return out, captured
 
 

@@ -30,18 +30,34 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libqrngext.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
-    t0 = time.time()
+def _run(cmd):
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
     # hipcc's host pass warns about the device-only target feature; drop that line
     noise = "is not a recognized feature for this target"
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln]
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed (%d):\n%s" % (res.returncode, "\n".join(msgs)))
+        raise RuntimeError("hipcc failed (%d): %s\n%s" % (res.returncode, " ".join(cmd),
+                                                          "\n".join(msgs)))
+    return msgs
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, one object each) and link
+    libqrngext.so (always recompiles)."""
+    import concurrent.futures as cf
+    import tempfile
+
+    t0 = time.time()
+    jobs = jobs or max(1, min(len(SOURCES), len(os.sched_getaffinity(0)), 16))
+    with tempfile.TemporaryDirectory(prefix="qrngext_build_") as tmpd:
+        objs = [os.path.join(tmpd, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, s),
+                                                                 "-o", o]
+                for s, o in zip(SOURCES, objs)]
+        with cf.ThreadPoolExecutor(jobs) as pool:
+            msgs = [m for ms in pool.map(_run, cmds) for m in ms]
+        tmp = LIB + ".tmp%d" % os.getpid()
+        msgs += _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     if verbose and msgs:
         print("\n".join(msgs), file=sys.stderr)
     os.replace(tmp, LIB)

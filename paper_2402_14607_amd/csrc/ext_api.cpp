@@ -138,6 +138,7 @@ struct ext_ctx {
     std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
     ExtShape shape{};
     bool bitslice = false;  // plain/streaming launches take the bit-sliced kernel
+    uint32_t kernel = EXT_KERNEL_AUTO;  // ext_params.kernel, for streams of other shapes
     uint32_t mem_kind = EXT_MEM_HOST;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -169,6 +170,8 @@ struct ext_stream {
     bool closed = false;
     uint64_t nb = 0;  // bytes per block
     uint64_t qb = 0;  // output bytes per block
+    ExtShape shape{};       // launch plan of the stream's (n, m)
+    bool bitslice = false;  // the stream's launches take the bit-sliced kernel
     // pending input on the device: double buffers, live bytes [head, tail)
     uint8_t* xbuf[2] = {nullptr, nullptr};
     uint8_t* ybuf[2] = {nullptr, nullptr};
@@ -215,14 +218,19 @@ int enter(ext_ctx* c) {
 
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
-int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
-    if (c->bitslice)
-        HIP_TRY(c, qext::launch_bitslice(c->shape, (const uint8_t*)x, (const uint8_t*)y,
+int launch(ext_ctx* c, const ExtShape& shape, bool bitslice, const void* x, const void* y,
+           void* out, uint64_t n_pairs) {
+    if (bitslice)
+        HIP_TRY(c, qext::launch_bitslice(shape, (const uint8_t*)x, (const uint8_t*)y,
                                          (uint8_t*)out, n_pairs, c->stream));
     else
-        HIP_TRY(c, qext::launch_extract(c->shape, (const uint8_t*)x, (const uint8_t*)y,
+        HIP_TRY(c, qext::launch_extract(shape, (const uint8_t*)x, (const uint8_t*)y,
                                         (uint8_t*)out, n_pairs, c->stream));
     return EXT_OK;
+}
+
+int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
+    return launch(c, c->shape, c->bitslice, x, y, out, n_pairs);
 }
 
 // The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits and
@@ -242,6 +250,42 @@ bool bitslice_applies(const ExtShape& s) {
 // outside it the word-level kernel was faster or within 2%.
 bool bitslice_preferred(const ExtShape& s) {
     return s.q % 16 == 0 && s.q >= 16 && s.q <= 128 && s.n_e >= 30;
+}
+
+// The launch plan of (n_bits, m_bits, taps) for ext_params.kernel `kernel`
+// without autotuning: the word-level plan from the knobs, and whether the
+// bit-sliced kernel takes the shape (the AUTO rule, or asked for).  *bsh
+// receives the bit-sliced kernel's shape, *bs_ok whether it applies.
+// EXT_ENOTSUP when no kernel takes the shape.
+int plan_kernel(uint64_t n_bits, uint32_t m_bits, const std::vector<uint32_t>& taps,
+                const qext::PlanKnobs& knobs, uint32_t kernel, ExtShape* shape, bool* bitslice,
+                ExtShape* bsh, bool* bs_ok) {
+    const uint32_t n_e = (uint32_t)(n_bits / m_bits);
+    const bool planned = qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), knobs,
+                                          shape);
+    bool bs = false, ok = false;
+    *bsh = ExtShape{};
+    if (kernel != EXT_KERNEL_WORD) {
+        bsh->q = m_bits;
+        bsh->n_e = n_e;
+        bsh->n_taps = (uint32_t)taps.size();
+        for (size_t k = 0; k < taps.size(); ++k) bsh->taps[k] = taps[k];
+        bsh->qbytes = m_bits / 8;
+        bsh->nbytes = (uint32_t)(n_bits / 8);
+        bsh->align = 1;  // byte gathers
+        bsh->threads = qext::kThreads;
+        ok = m_bits % 8 == 0 && n_bits / 8 < (1ull << 23) && bitslice_applies(*bsh);
+        bs = ok && (kernel == EXT_KERNEL_BITSLICE || !planned || bitslice_preferred(*bsh));
+    }
+    if (kernel == EXT_KERNEL_BITSLICE && !bs) return EXT_ENOTSUP;
+    if (!bs && !planned) return EXT_ENOTSUP;
+    if (bs) {
+        if (planned) shape->align = 1;  // byte gathers
+        else *shape = *bsh;
+    }
+    *bitslice = bs;
+    *bs_ok = ok && planned;
+    return EXT_OK;
 }
 
 }  // namespace
@@ -327,38 +371,19 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
     } else {
         return EXT_EINVAL;
     }
-    ExtShape shape;
+    ExtShape shape, bsh;
     qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group, p->threads};
     if (p->base_bits % 32) return EXT_EINVAL;
-    const uint32_t n_e = (uint32_t)(n_bits / m_bits);
-    const bool planned = qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(),
-                                          knobs, &shape);
-    bool bs = false, bs_ok = false, tune_kernel = false;
-    ExtShape bsh{};  // the bit-sliced kernel needs only the field, the element count and P
-    if (p->kernel != EXT_KERNEL_WORD) {
-        bsh.q = m_bits;
-        bsh.n_e = n_e;
-        bsh.n_taps = (uint32_t)taps.size();
-        for (size_t k = 0; k < taps.size(); ++k) bsh.taps[k] = taps[k];
-        bsh.qbytes = m_bits / 8;
-        bsh.nbytes = (uint32_t)(n_bits / 8);
-        bsh.align = 1;  // byte gathers
-        bsh.threads = qext::kThreads;
-        bs_ok = m_bits % 8 == 0 && n_bits / 8 < (1ull << 23) && bitslice_applies(bsh);
-        // AUTO: the rule, or (autotune) a timing once the stream exists
-        bs = bs_ok && (p->kernel == EXT_KERNEL_BITSLICE || !planned || bitslice_preferred(bsh));
-        tune_kernel = bs_ok && planned && p->kernel == EXT_KERNEL_AUTO && p->autotune;
-    }
-    if (p->kernel == EXT_KERNEL_BITSLICE && !bs) return EXT_ENOTSUP;
-    if (!bs && !planned) return EXT_ENOTSUP;
+    bool bs = false, bs_ok = false;
+    const int prc = plan_kernel(n_bits, m_bits, taps, knobs, p->kernel, &shape, &bs, &bsh, &bs_ok);
+    if (prc) return prc;
+    // AUTO with autotune: a timing once the stream exists decides
+    const bool tune_kernel = bs_ok && p->kernel == EXT_KERNEL_AUTO && p->autotune;
     ext_ctx* c = new (std::nothrow) ext_ctx;
     if (!c) return EXT_ENOMEM;
     c->bitslice = bs;
+    c->kernel = p->kernel;
     c->n_bits = n_bits;
-    if (bs) {
-        if (planned) shape.align = 1;  // byte gathers
-        else shape = bsh;
-    }
     c->m_bits = m_bits;
     c->b = b;
     c->taps = taps;
@@ -573,16 +598,43 @@ int ext_destroy(ext_ctx* c) {
 // ---------------------------------------------------------------------------
 // streaming form
 // ---------------------------------------------------------------------------
-int ext_stream_open(ext_ctx* c, ext_stream** out) {
+int ext_stream_open(ext_ctx* c, uint64_t n_bits, uint32_t m_bits, ext_stream** out) {
     if (!out) return EXT_EINVAL;
     *out = nullptr;
     int rc = enter(c);
     if (rc) return rc;
+    if (!n_bits) n_bits = c->n_bits;
+    if (!m_bits) m_bits = c->m_bits;
+    ExtShape shape = c->shape;
+    bool bitslice = c->bitslice;
+    if (n_bits != c->n_bits || m_bits != c->m_bits) {
+        // a shape of its own: the context's modulus when the field is the
+        // context's, else the conventional one of degree m; the default plan
+        if (n_bits % m_bits || m_bits % c->b || n_bits / m_bits > 0xffffffffull)
+            return EXT_EINVAL;
+        std::vector<uint32_t> taps;
+        if (m_bits == c->m_bits) {
+            taps = c->taps;
+        } else {
+            try {
+                if (!qext::default_modulus(m_bits, &taps)) return EXT_ENOTSUP;
+            } catch (const std::bad_alloc&) {
+                return EXT_ENOMEM;
+            }
+        }
+        ExtShape bsh;
+        bool bs_ok = false;
+        rc = plan_kernel(n_bits, m_bits, taps, qext::PlanKnobs{}, c->kernel, &shape, &bitslice,
+                         &bsh, &bs_ok);
+        if (rc) return rc;
+    }
     ext_stream* s = new (std::nothrow) ext_stream;
     if (!s) return EXT_ENOMEM;
     s->ctx = c;
-    s->nb = c->n_bits / 8;
-    s->qb = c->m_bits / 8;
+    s->nb = n_bits / 8;
+    s->qb = m_bits / 8;
+    s->shape = shape;
+    s->bitslice = bitslice;
     // every side holds at most cap bytes of pending input plus one block
     s->buf_bytes = ((c->cap + s->nb - 1) / s->nb + 1) * s->nb;
     // room for as many outputs as the pending input could produce, times two
@@ -678,8 +730,8 @@ int launch_ready(ext_stream* s) {
         k = std::min(k, s->out_slots - pos);  // no wrap inside one launch
         const uint8_t* xp = s->xbuf[s->xcur] + s->xhead;
         const uint8_t* yp = s->ybuf[s->ycur] + s->yhead;
-        if (((uintptr_t)xp | (uintptr_t)yp) & (c->shape.align - 1)) return EXT_EINVAL;
-        int rc = launch(c, xp, yp, s->oring + pos * s->qb, k);
+        if (((uintptr_t)xp | (uintptr_t)yp) & (s->shape.align - 1)) return EXT_EINVAL;
+        int rc = launch(c, s->shape, s->bitslice, xp, yp, s->oring + pos * s->qb, k);
         if (rc) return rc;
         Launch L{pos, k, 0, nullptr};
         HIP_TRY(c, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));

@@ -144,6 +144,7 @@ struct ext_server {
     static constexpr uint32_t kMaxInflight = kSlots - 1;
     Slot slots[kSlots];
     int filling = 0;
+    bool launching = false;  // a slot has been taken and its kernels are not all queued yet
     std::deque<int> inflight;
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int> occ_cache;  // (bw, threads, lds)
     std::mutex mu;
@@ -235,6 +236,17 @@ int occupancy(ext_server* s, uint32_t bw, uint32_t threads, uint32_t padded, uin
 // (lock held on entry and exit; released around the HIP calls).
 int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
     const uint64_t t_enter = now_ns();
+    // While set, ext_server_close waits: the taken slot may hold scatter
+    // descriptors into a closing channel's rings, and its staging kernel is
+    // queued without the lock.  Cleared (lock held) on every return.
+    struct Launching {
+        ext_server* s;
+        ~Launching() {
+            s->launching = false;
+            s->cv.notify_all();
+        }
+    } launching_guard{s};
+    s->launching = true;
     const int idx = s->filling;
     Slot& sl = s->slots[idx];
     // the next filling slot: one that is neither in flight nor this one
@@ -822,6 +834,10 @@ int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
                                      [&](const Resv& r) { return r.ch == channel; }),
                       sl.resv.end());
     }
+    // a cycle being built may hold this channel's bytes in the slot it took
+    // before the close: once its kernels are queued, the stream syncs below
+    // cover its staging
+    while (s->launching) s->cv.wait(lk);
     // pairs received but not yet launched are dropped with the channel; wait
     // for the stream before freeing the rings
     lk.unlock();

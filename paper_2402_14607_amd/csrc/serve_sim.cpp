@@ -125,7 +125,7 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
                     128, (cfg->server_cfg ? cfg->server_cfg->ring_bytes : (4ull << 20)) / ch[c]->nb);
             p.device_bytes_cap = ring * ch[c]->nb;
             rc = ext_create(cfg->n_bits[c], cfg->m_bits[c], &p, &ch[c]->ctx);
-            if (rc == EXT_OK) rc = ext_stream_open(ch[c]->ctx, &ch[c]->st);
+            if (rc == EXT_OK) rc = ext_stream_open(ch[c]->ctx, 0, 0, &ch[c]->st);
         }
     }
     auto teardown = [&] {
@@ -174,28 +174,36 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             }
             Chan& c = *ch[e.ch];
             const uint64_t len = (uint64_t)e.k * c.nb;
-            if (c.pool_pos + len > cfg->pool_bytes[e.ch]) c.pool_pos = 0;
-            const uint8_t* xs = cfg->pool_x[e.ch] + c.pool_pos;
-            const uint8_t* ys = cfg->pool_y[e.ch] + c.pool_pos;
-            for (;;) {
-                int r;
-                if (srv) {
-                    r = ext_server_submit(srv, c.sid, xs, len, ys, len);
-                } else {
-                    std::lock_guard<std::mutex> g(c.mu);
-                    r = ext_submit(c.st, xs, len, ys, len, nullptr);
-                }
-                if (r == EXT_EAGAIN) {
-                    eagain++;
-                    if (now_ns() > win_hi + (uint64_t)(cfg->grace_s * 1e9)) {
-                        fail.store(EXT_EAGAIN);
-                        break;
+            // the pool is read cyclically: a chunk that runs past its end goes
+            // in two submissions (both whole blocks), the second from the start
+            const uint64_t pool = cfg->pool_bytes[e.ch];
+            const uint64_t first = std::min(len, pool - c.pool_pos);
+            for (int piece = 0; piece < 2 && !fail.load(); ++piece) {
+                const uint64_t off = piece ? 0 : c.pool_pos;
+                const uint64_t plen = piece ? len - first : first;
+                if (!plen) continue;
+                const uint8_t* xs = cfg->pool_x[e.ch] + off;
+                const uint8_t* ys = cfg->pool_y[e.ch] + off;
+                for (;;) {
+                    int r;
+                    if (srv) {
+                        r = ext_server_submit(srv, c.sid, xs, plen, ys, plen);
+                    } else {
+                        std::lock_guard<std::mutex> g(c.mu);
+                        r = ext_submit(c.st, xs, plen, ys, plen, nullptr);
                     }
-                    std::this_thread::yield();
-                    continue;
+                    if (r == EXT_EAGAIN) {
+                        eagain++;
+                        if (now_ns() > win_hi + (uint64_t)(cfg->grace_s * 1e9)) {
+                            fail.store(EXT_EAGAIN);
+                            break;
+                        }
+                        std::this_thread::yield();
+                        continue;
+                    }
+                    if (r != EXT_OK) fail.store(r);
+                    break;
                 }
-                if (r != EXT_OK) fail.store(r);
-                break;
             }
             if (fail.load()) break;
             const uint64_t t_sub = now_ns();
@@ -207,7 +215,7 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             uint64_t prev = max_lag.load();
             while (lag > prev && !max_lag.compare_exchange_weak(prev, lag)) {
             }
-            c.pool_pos += len;
+            c.pool_pos = (c.pool_pos + len) % pool;
             {
                 std::lock_guard<std::mutex> g(c.mu);
                 c.submitted += e.k;

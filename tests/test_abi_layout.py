@@ -54,3 +54,21 @@ def test_struct_layout(c_layout, cname):
     assert ctypes.sizeof(cls) == c_layout[(cname, "size")], cname
     for fname, *_ in cls._fields_:
         assert getattr(cls, fname).offset == c_layout[(cname, fname)], (cname, fname)
+
+
+def test_stream_open_prototype(tmp_path):
+    """ext_stream_open takes the stream's own (n_bits, m_bits): the header's
+    prototype has that signature (a C function-pointer assignment that fails
+    to compile otherwise) and the binding declares the same argument types."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "proto.c"
+    src.write_text('#include "qrng_ext.h"\n'
+                   "int (*f)(ext_ctx *, uint64_t, uint32_t, ext_stream **) = ext_stream_open;\n")
+    subprocess.run([cc, "-std=c99", "-Werror", "-Wincompatible-pointer-types", "-c", "-I",
+                    os.path.join(ROOT, "include"), str(src), "-o", str(tmp_path / "proto.o")],
+                   check=True)
+    args = list(binding.load().ext_stream_open.argtypes)
+    assert args == [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                    ctypes.POINTER(ctypes.c_void_p)]

@@ -321,16 +321,19 @@ def test_zero_pairs_and_errors(dev):
 # streaming form
 # ---------------------------------------------------------------------------
 def run_stream(dev, w, chunks_x, chunks_y, device_memory=False, cap=0, poll_every=1,
-               combined=True, kernel=0):
+               combined=True, kernel=0, ctx_shape=None, ctx_taps=None, sample_bits=8):
     """Feed X and Y in the given chunk sizes (in one ext_submit per step when
-    combined, else one side per call), poll as it goes, then drain.
-    Returns (output bytes, dropped bits, EAGAIN count)."""
+    combined, else one side per call), poll as it goes, then drain.  With
+    ctx_shape = (n, m) the context has that shape and the stream is opened
+    with w's own.  Returns (output bytes, dropped bits, EAGAIN count)."""
     import torch
 
-    ex = binding.Extractor(w.n_bits, w.m_bits, device_memory=device_memory,
+    cn, cm = ctx_shape if ctx_shape else (w.n_bits, w.m_bits)
+    ex = binding.Extractor(cn, cm, device_memory=device_memory,
                            stream=torch.cuda.current_stream(dev).cuda_stream if device_memory else None,
-                           device_bytes_cap=cap, kernel=kernel)
-    s = ex.open_stream()
+                           device_bytes_cap=cap, kernel=kernel, taps=ctx_taps,
+                           sample_bits=sample_bits)
+    s = ex.open_stream(w.n_bits, w.m_bits) if ctx_shape else ex.open_stream()
     qb = w.m_bits // 8
     collected = []
     xs = torch.from_numpy(w.x).to(dev) if device_memory else w.x
@@ -416,3 +419,53 @@ def test_stream_admission_backpressure(dev):
     assert eagain > 0
     assert dropped == 0
     assert np.array_equal(got, want)
+
+
+# (context n, m, taps), (stream n, m): streams whose shape is not their
+# context's -- another field (the conventional modulus of its degree),
+# the same field with more elements (the context's own modulus, here a
+# non-conventional one), and the paper's point on a bit-sliced-capable shape
+STREAM_SHAPES = [((8192, 2048, None), (1024, 256)),
+                 ((1024, 256, (16, 3, 1)), (4096, 256)),
+                 ((8192, 2048, None), (5680, 80)),
+                 ((512, 128, None), (65536, 16384))]
+
+
+@pytest.mark.parametrize("ctx,shape", STREAM_SHAPES, ids=lambda v: str(v))
+def test_stream_shape_of_its_own(dev, ctx, shape):
+    n, m = shape
+    cn, cm, taps = ctx
+    if taps is not None:
+        assert binding.is_irreducible(cm, taps)
+    pairs = 3 if n >= 65536 else 40
+    w = inputs.plain_workload(n, m, pairs, 61, 62)
+    tail = 5
+    w.x = np.concatenate([w.x, np.arange(tail, dtype=np.uint8)])
+    exps = (cm,) + tuple(sorted(taps, reverse=True)) + (0,) if (taps and cm == m) else None
+    want = oracle.ext_blocks(w.x, w.y, n, m, exps)
+    rng = np.random.Generator(np.random.PCG64(n + m))
+    cx, cy = [], []
+    for total, out in ((w.x.size, cx), (w.y.size, cy)):
+        while total:
+            c = int(min(total, rng.integers(1, 3 * n // 8)))
+            out.append(c)
+            total -= c
+    for device_memory in (False, True):
+        say("stream n=%d m=%d on a context n=%d m=%d taps=%s, device_memory=%s"
+            % (n, m, cn, cm, taps, device_memory))
+        got, dropped, _ = run_stream(dev, w, cx, cy, device_memory=device_memory,
+                                     ctx_shape=(cn, cm), ctx_taps=taps)
+        assert np.array_equal(got, want)
+        assert dropped == 8 * tail
+
+
+def test_stream_shape_refusals(dev):
+    with binding.Extractor(8192, 2048, device_memory=False) as ex:
+        for n, m, code in ((1000, 256, binding.EXT_EINVAL), (48, 12, binding.EXT_EINVAL),
+                           (1024, 8, binding.EXT_OK)):
+            if code == binding.EXT_OK:
+                ex.open_stream(n, m).close()
+                continue
+            with pytest.raises(binding.ExtError) as e:
+                ex.open_stream(n, m)
+            assert e.value.code == code, (n, m)

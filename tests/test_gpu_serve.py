@@ -218,3 +218,61 @@ def test_load_generator_plain_mode_runs(dev):
         blocks = c.size // (m // 8)
         nb = n // 8
         assert np.array_equal(c, plain(n, m, x[:blocks * nb], y[:blocks * nb]))
+
+
+def test_close_with_pending_partial_block_while_others_stream(dev):
+    """Channels that hold a pending partial block (bytes in the current
+    cycle's staging, no complete pair) are opened and closed over and over
+    while other channels keep streaming from another thread: the closes
+    report the dropped bits, the slots are reused, and the streaming
+    channels' outputs still equal the plain form's."""
+    import threading
+
+    live = [inputs.plain_workload(2048, 512, 600, 950 + i, 960 + i) for i in range(3)]
+    with binding.Server(config=binding.server_config(ring_blocks=32)) as srv:
+        chans = [srv.open(w.n_bits, w.m_bits) for w in live]
+        stop = threading.Event()
+        errors = []
+
+        def feed():
+            try:
+                nb = 256
+                pos = [0] * len(live)
+                while not stop.is_set() and any(p < 600 for p in pos):
+                    for i, (c, w) in enumerate(zip(chans, live)):
+                        if pos[i] >= 600:
+                            continue
+                        k = min(3, 600 - pos[i])
+                        sl = slice(pos[i] * nb, (pos[i] + k) * nb)
+                        if srv.submit(c, w.x[sl], w.y[sl]) == binding.EXT_OK:
+                            pos[i] += k
+            except Exception as e:  # surfaced below
+                errors.append(e)
+
+        got = {c: [] for c in chans}
+        t = threading.Thread(target=feed)
+        t.start()
+        closes = 0
+        part = inputs.plain_workload(8192, 2048, 1, 970, 971)
+        try:
+            while t.is_alive() or closes < 40:
+                c = srv.open(8192, 2048)
+                # 700 of 1024 bytes of X, all of Y: a partial block, no pair
+                assert srv.submit(c, part.x[:700], part.y) == binding.EXT_OK
+                assert srv.close_channel(c) == 8 * 1024
+                closes += 1
+                for cc in chans:
+                    buf = np.empty(1 << 16, dtype=np.uint8)
+                    n, _ = srv.poll(cc, buf)
+                    if n:
+                        got[cc].append(buf[:n].copy())
+        finally:
+            stop.set()
+            t.join()
+        assert not errors, errors
+        have = {c: sum(g.size for g in got[c]) for c in chans}
+        rest = drain(srv, chans, {c: 600 * 64 - have[c] for c in chans})
+    say("closed %d channels holding partial blocks while 3 channels streamed" % closes)
+    for c, w in zip(chans, live):
+        out = np.concatenate(got[c] + [rest[c]])
+        assert np.array_equal(out, plain(w.n_bits, w.m_bits, w.x, w.y))
