@@ -632,6 +632,44 @@ def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
     return out
 
 
+def run_only(args):
+    """One leg alone, its record printed as one JSON line."""
+    import torch
+
+    from paper_2402_14607_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+    k = args.leg_steps
+    if args.only == "tiny":
+        rec = tiny_leg(dev, stream, steps=k or 200, warmup=20)
+    elif args.only == "stress":
+        rec = stress_leg(dev, stream, steps=k or 10, warmup=2)
+    elif args.only == "batched":
+        rec = batched_leg(dev, stream, steps=k or 10, warmup=2)
+    elif args.only == "paper_point":
+        rec = paper_point_leg(dev, stream, steps=k or 20, warmup=3)
+    elif args.only == "growing":
+        rec = growing_leg(dev, stream, steps=k or 10, warmup=2)
+    else:
+        w = inputs.paper_block(N_PAIRS)
+        sweep = tuple(int(v) for v in args.serve_sweep.split(",") if v.strip())
+        rec = served_leg(w, dev, stream, duration_s=args.serve_seconds, warmup_s=1.0,
+                         modes=args.serve_modes.split(","), wg_per_cu=args.serve_wg_per_cu,
+                         max_inflight=args.serve_inflight, split_pairs=args.serve_split,
+                         producers=args.serve_producers, timing=args.serve_timing, sweep=sweep)
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+        probe = torch.empty_like(src)
+        for _ in range(4):
+            probe.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 4 x %d bytes device-to-device" % src.numel())
+    print(json.dumps({"leg": args.only, "record": rec}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -662,6 +700,12 @@ def main():
                     help="1: time every server cycle's phases with GPU events (diagnostic)")
     ap.add_argument("--serve-wg-per-cu", type=int, default=0,
                     help="persistent work-groups per CU in a served cycle (0 = as many as fit)")
+    ap.add_argument("--only", default="",
+                    choices=["", "tiny", "stress", "batched", "paper_point", "growing", "served"],
+                    help="run only this leg (no paper-block leg, no CPU baseline) and print "
+                         "its record: for profiling one workload's kernels")
+    ap.add_argument("--leg-steps", type=int, default=0,
+                    help="timed launches of the leg chosen with --only (0: its default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, also run a plain 64 MiB device copy 4 times (the "
                          "reference kernel that scales HBM traffic counters)")
@@ -676,6 +720,10 @@ def main():
     import numpy as np
 
     from paper_2402_14607_amd import inputs
+
+    if args.only:
+        run_only(args)
+        return
 
     log("generating the paper-block workload (n=%d, m=%d, %d pairs)" % (N_BITS, M_BITS, N_PAIRS))
     w = inputs.paper_block(N_PAIRS)
