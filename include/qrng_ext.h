@@ -160,6 +160,31 @@ int ext_growing_blocks(const ext_growing *g, uint64_t n_bytes, uint64_t *k_block
  * outside the built-in table) or no launch plan. */
 int ext_growing_extract(ext_growing *g, const void *x, const void *y, uint64_t n_bytes,
                         uint64_t max_blocks, void *out, uint64_t out_cap, uint64_t *n_blocks);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ext_growing_extract on device memory, with the same arguments, results
+ * and errors, that allocates nothing.  Its launch tables and queue heads
+ * live in a static device array of the library (about 0.7 MiB, one copy per
+ * GPU, held until the process ends; its address on each GPU is looked up
+ * when an ext_growing is first created there) instead of buffers the handle
+ * allocates.  The queue heads are cleared by every call.
+ *   - the handle must have been created with mem_kind = EXT_MEM_DEVICE, else
+ *     EXT_EINVAL;
+ *   - at most EXT_NOALLOC_MAX_BLOCKS blocks per call: a call whose k (the
+ *     whole blocks in n_bytes, capped by max_blocks) is larger returns
+ *     EXT_ENOMEM and does nothing;
+ *   - EXT_EDEVICE if the array's address could not be looked up.
+ * Every call on a GPU, from any handle, uses that GPU's one array: calls
+ * that overlap on one GPU race and must be serialised by the caller (this
+ * call returns after its outputs are written, so one thread at a time per
+ * GPU suffices).
+ */
+enum { EXT_NOALLOC_MAX_BLOCKS = 4096 };
+int ext_growing_extract_noalloc(ext_growing *g, const void *x, const void *y, uint64_t n_bytes,
+                                uint64_t max_blocks, void *out, uint64_t out_cap,
+                                uint64_t *n_blocks);
 int ext_growing_destroy(ext_growing *g);
 
 /*

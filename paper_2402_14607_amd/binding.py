@@ -35,7 +35,8 @@ EXPORTED = (
     "ext_server_submit", "ext_server_poll", "ext_server_close", "ext_server_stats_get",
     "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
     "ext_choose_params", "ext_block_error_log2", "ext_stream_error_log2", "ext_output_bits",
-    "ext_growing_create", "ext_growing_blocks", "ext_growing_extract", "ext_growing_destroy",
+    "ext_growing_create", "ext_growing_blocks", "ext_growing_extract",
+    "ext_growing_extract_noalloc", "ext_growing_destroy",
     "ext_probe_valu_rate",
 )
 
@@ -208,6 +209,7 @@ def load() -> ctypes.CDLL:
                                               ctypes.POINTER(vp)]),
         "ext_growing_blocks": (ctypes.c_int, [vp, u64, u64p, u64p, u64p]),
         "ext_growing_extract": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
+        "ext_growing_extract_noalloc": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
         "ext_growing_destroy": (ctypes.c_int, [vp]),
         "ext_probe_valu_rate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
@@ -644,6 +646,17 @@ class Growing:
         _check(self.lib.ext_growing_extract(self.handle, _ptr(x), _ptr(y), n_bytes, max_blocks,
                                             _ptr(out), out_cap, ctypes.byref(k)),
                "ext_growing_extract")
+        return k.value
+
+    def extract_noalloc(self, x, y, n_bytes: int, out, out_cap: int,
+                        max_blocks: int = 2 ** 64 - 1) -> int:
+        """ext_growing_extract_noalloc: as extract (device memory only), with
+        the launch tables in the library's static device scratch."""
+        k = ctypes.c_uint64()
+        _check(self.lib.ext_growing_extract_noalloc(self.handle, _ptr(x), _ptr(y), n_bytes,
+                                                    max_blocks, _ptr(out), out_cap,
+                                                    ctypes.byref(k)),
+               "ext_growing_extract_noalloc")
         return k.value
 
     def close(self):

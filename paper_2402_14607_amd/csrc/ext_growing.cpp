@@ -51,7 +51,8 @@ struct ext_growing {
 
 namespace {
 
-constexpr uint32_t kMaxGroups = 64;  // distinct (base size, work-group size) launches per call
+constexpr uint32_t kMaxGroups = qext::kNoAllocMaxLaunches;  // distinct (base size, work-group
+                                                            // size) launches per call
 
 void release_lanes(ext_growing* g) {
     for (int i = 0; i < ext_growing::kLanes; ++i) {
@@ -184,6 +185,9 @@ int ext_growing_create(uint32_t n_e, uint32_t q1, uint32_t delta_steps, const ex
         return EXT_EDEVICE;
     }
     g->device = dev;
+    // set-up of the allocation-free call: this device's copy of the static
+    // scratch (a failure leaves only that call unusable)
+    (void)qext::noalloc_scratch_init(dev);
     if (p->use_hip_stream) {
         g->stream = (hipStream_t)p->hip_stream;
     } else if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) == hipSuccess) {
@@ -217,14 +221,30 @@ int ext_growing_blocks(const ext_growing* g, uint64_t n_bytes, uint64_t* k_block
     return EXT_OK;
 }
 
-int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n_bytes,
-                        uint64_t max_blocks, void* out, uint64_t out_cap, uint64_t* n_blocks) {
+}  // extern "C"
+
+namespace {
+
+// Where a call's launch tables and queue heads live on the device.
+struct Tables {
+    BatchStream* streams;
+    BatchTile* tiles;
+    uint32_t* heads;
+};
+
+// Blocks 0 .. k-1 of x and y into out (ext_growing_extract); the launch
+// tables go to *fixed when given (nothing is allocated then), else to the
+// handle's scratch, grown on demand.
+int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_bytes,
+                   uint64_t max_blocks, void* out, uint64_t out_cap, uint64_t* n_blocks,
+                   const Tables* fixed) {
     if (!g) return EXT_EINVAL;
     if (g->sticky) return g->sticky;
     if (n_blocks) *n_blocks = 0;
     const Geo r = geometry(g, n_bytes, max_blocks);
     if (r.k == 0) return EXT_OK;
     if (!x || !y || !out || out_cap < r.out_bytes) return EXT_EINVAL;
+    if (fixed && r.k > qext::kNoAllocMaxBlocks) return EXT_ENOMEM;
     if (hipSetDevice(g->device) != hipSuccess) return EXT_EDEVICE;
     int rc = EXT_OK;
     std::vector<BatchStream> streams;
@@ -233,8 +253,14 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
     std::map<std::pair<uint32_t, uint32_t>, std::vector<std::pair<uint64_t, uint32_t>>> groups;
     try {
         streams.reserve(r.k);
-        rc = grow(g, r.k, r.in_bytes, r.out_bytes);
-        if (rc) return rc;
+        Tables tab;
+        if (fixed) {
+            tab = *fixed;
+        } else {
+            rc = grow(g, r.k, r.in_bytes, r.out_bytes);
+            if (rc) return rc;
+            tab = Tables{g->d_streams, g->d_tiles, g->d_heads};
+        }
         const bool host = g->params.mem_kind == EXT_MEM_HOST;
         const uint8_t* xs = host ? g->dx : (const uint8_t*)x;
         const uint8_t* ys = host ? g->dy : (const uint8_t*)y;
@@ -292,11 +318,11 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
         // the tables and the launches' zeroed queue heads, in stream order
         // before the lanes fork (a copy, so that no launch needs a reset kernel)
         static const uint32_t kZeroHeads[kMaxGroups] = {};
-        if (hipMemcpyAsync(g->d_streams, streams.data(), r.k * sizeof(BatchStream),
+        if (hipMemcpyAsync(tab.streams, streams.data(), r.k * sizeof(BatchStream),
                            hipMemcpyHostToDevice, g->stream) ||
-            hipMemcpyAsync(g->d_tiles, tiles.data(), r.k * sizeof(BatchTile),
+            hipMemcpyAsync(tab.tiles, tiles.data(), r.k * sizeof(BatchTile),
                            hipMemcpyHostToDevice, g->stream) ||
-            hipMemcpyAsync(g->d_heads, kZeroHeads, launches.size() * sizeof(uint32_t),
+            hipMemcpyAsync(tab.heads, kZeroHeads, launches.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, g->stream))
             return device_error();
         // fork: the lanes start after the table copies (and the caller's work
@@ -318,8 +344,8 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
                 return device_error();
             used[lane] = true;
             load[lane] += ln.cost + 1;
-            if (qext::launch_batch_noreset(ln.bw, ln.threads, true, g->d_streams,
-                                           g->d_tiles + ln.off, ln.n, g->d_heads + i, nullptr,
+            if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams,
+                                           tab.tiles + ln.off, ln.n, tab.heads + i, nullptr,
                                            ln.grid, ln.lds, g->lanes[lane]) != hipSuccess)
                 return device_error();
         }
@@ -338,6 +364,29 @@ int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n
     }
     if (n_blocks) *n_blocks = r.k;
     return EXT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ext_growing_extract(ext_growing* g, const void* x, const void* y, uint64_t n_bytes,
+                        uint64_t max_blocks, void* out, uint64_t out_cap, uint64_t* n_blocks) {
+    return extract_blocks(g, x, y, n_bytes, max_blocks, out, out_cap, n_blocks, nullptr);
+}
+
+int ext_growing_extract_noalloc(ext_growing* g, const void* x, const void* y, uint64_t n_bytes,
+                                uint64_t max_blocks, void* out, uint64_t out_cap,
+                                uint64_t* n_blocks) {
+    if (!g) return EXT_EINVAL;
+    // host memory would need device staging buffers
+    if (g->params.mem_kind != EXT_MEM_DEVICE) return EXT_EINVAL;
+    uint8_t* base = (uint8_t*)qext::noalloc_scratch(g->device);
+    if (!base) return EXT_EDEVICE;  // the per-device lookup at create time failed
+    const Tables tab{(BatchStream*)(base + qext::kNoAllocStreamsOff),
+                     (BatchTile*)(base + qext::kNoAllocTilesOff),
+                     (uint32_t*)(base + qext::kNoAllocHeadsOff)};
+    return extract_blocks(g, x, y, n_bytes, max_blocks, out, out_cap, n_blocks, &tab);
 }
 
 int ext_growing_destroy(ext_growing* g) {

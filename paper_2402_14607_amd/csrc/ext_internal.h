@@ -167,4 +167,22 @@ hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,
                            int* blocks_per_cu);
 
+// Static device scratch of the allocation-free growing-block call
+// (ext_noalloc.hip): the launch tables of at most kNoAllocMaxBlocks blocks
+// (one stream and one tile each) and kNoAllocMaxLaunches queue heads.
+constexpr uint32_t kNoAllocMaxBlocks = 4096;
+constexpr uint32_t kNoAllocMaxLaunches = 64;
+constexpr size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kNoAllocStreamsOff = 0;
+constexpr size_t kNoAllocTilesOff = round256(kNoAllocMaxBlocks * sizeof(BatchStream));
+constexpr size_t kNoAllocHeadsOff =
+    kNoAllocTilesOff + round256(kNoAllocMaxBlocks * sizeof(BatchTile));
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocHeadsOff + round256(kNoAllocMaxLaunches * sizeof(uint32_t));
+// Look up this device's copy of the static scratch (once per device; the
+// library calls it when a growing-block handle is created on the device).
+hipError_t noalloc_scratch_init(int device);
+// Device address of that copy, or null if it has not been looked up.
+void* noalloc_scratch(int device);
+
 }  // namespace qext
