@@ -586,6 +586,9 @@ def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
             "mean_cycle_ms": round(res["mean_cycle_us"] / 1e3, 4),
             "eagain_ring": int(res["eagain_ring"]),
             "eagain_stage": int(res["eagain_stage"]),
+            "admission": {"rings_bytes": int(res["rings_bytes"]),
+                          "device_free_bytes_at_open": int(res["free_bytes"]),
+                          "opens_refused_for_memory": int(res["eagain_mem"])},
         }
 
     runs = (("served", binding.EXT_SIM_SERVED, rate, 0.0),

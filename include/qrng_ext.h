@@ -30,7 +30,7 @@
  *
  * Supported shapes on the GPU path: m a multiple of 8 (and of b), n a
  * multiple of m, and every non-leading exponent of P at most m/2 (the
- * conventional modulus qualifies for every such m up to 4096).  Fields whose
+ * conventional modulus qualifies for every such m from 8 to 8192).  Fields whose
  * degree is not a multiple of 32, or whose word count has an odd part above
  * 15, are computed in zero-padded slots; blocks and outputs may then sit at
  * any byte.  Everything else returns EXT_ENOTSUP.
@@ -128,8 +128,10 @@ int ext_destroy(ext_ctx *c);
 int ext_get_modulus(const ext_ctx *c, uint32_t *exps, uint32_t cap, uint32_t *n);
 
 /* The conventional modulus of degree m (see Conventions) without creating a
- * context: same output format as ext_get_modulus.  EXT_ENOTSUP if m is
- * outside the library's table and too large to search quickly (> 4096). */
+ * context: same output format as ext_get_modulus.  The library's table holds
+ * every multiple of 8 up to 8192 (and 16384); other degrees up to 32768 are
+ * searched at first use (on up to 16 host threads; about a second at 10000
+ * bits, minutes at 32768) and cached; EXT_ENOTSUP above 32768. */
 int ext_default_modulus(uint32_t m_bits, uint32_t *exps, uint32_t cap, uint32_t *n);
 
 /* 1 if t^m + sum t^taps + 1 is irreducible over GF(2), 0 if not, <0 on a
@@ -156,8 +158,8 @@ int ext_growing_blocks(const ext_growing *g, uint64_t n_bytes, uint64_t *k_block
  * the whole blocks they hold, at most max_blocks) into out (out_cap bytes, at
  * least the k blocks' output bytes, else EXT_EINVAL); *n_blocks = k.  Memory
  * kind and stream as for ext_extract; returns after the outputs are written.
- * EXT_ENOTSUP if some q_l has no conventional modulus in reach (q_l > 4096
- * outside the built-in table) or no launch plan. */
+ * EXT_ENOTSUP if some q_l has no conventional modulus in reach (above 32768
+ * bits; see ext_default_modulus) or no launch plan. */
 int ext_growing_extract(ext_growing *g, const void *x, const void *y, uint64_t n_bytes,
                         uint64_t max_blocks, void *out, uint64_t out_cap, uint64_t *n_blocks);
 
@@ -181,6 +183,59 @@ int ext_growing_extract(ext_growing *g, const void *x, const void *y, uint64_t n
  * call returns after its outputs are written, so one thread at a time per
  * GPU suffices).
  */
+/*
+ * Online form of Algorithm 2 (Sec. 3.3, Ext_bs^neq on sources of unbounded
+ * length): X and Y arrive in chunks of any length, the two sides
+ * independently.  The stream carries Algorithm 2's state from call to call --
+ * the next block l (from 0), its degree q_l = q1 + l * delta_steps * b, and i,
+ * the bytes per source that blocks 0 .. l-1 took -- and keeps the bytes of
+ * the block still incomplete in device memory.  Block l is launched as soon
+ * as both sources hold its q_l * n_e / 8 bytes; its q_l / 8 output bytes come
+ * back from ext_growing_poll in block order, each exactly once, so that after
+ * k blocks the caller holds Z^(0) Z^(1) ... Z^(k-1), m_k bits (Thm. 3.6).
+ * Memory kind, HIP stream and device come from g; one thread at a time per
+ * handle (streams of one handle share its GPU streams).
+ */
+typedef struct ext_growing_stream ext_growing_stream;
+/* Open a stream on g in state (l, q_l, i) = (0, q1, 0).  Released by
+ * ext_growing_close (or ext_growing_destroy of g). */
+int ext_growing_open(ext_growing *g, ext_growing_stream **out);
+/* Append x_len bytes to X and y_len bytes to Y (either may be 0): the next
+ * samples of each source.  Host data are copied before the call returns;
+ * device data are read in stream order and borrowed until that work is done.
+ * Launches every block the chunk completes.  Nothing is consumed when the
+ * call returns
+ *   EXT_EAGAIN  if either side would hold more pending bytes than its limit
+ *               -- device_bytes_cap, lowered so that their outputs fit in
+ *               half of the stream's output ring (1 to 64 MiB), and never
+ *               below two blocks of the next degree -- or the outputs of the
+ *               completed blocks would not fit beside the unpolled ones:
+ *               poll (or feed the other side), then submit again;
+ *   EXT_ENOTSUP if a completed block's degree has no conventional modulus in
+ *               reach (above 32768 bits, or beyond the built-in table of the
+ *               multiples of 8 up to 8192 and a search, run at first use,
+ *               that fails) or no launch plan.
+ * *blocks_launched (may be NULL): blocks launched so far. */
+int ext_growing_submit(ext_growing_stream *s, const void *x, size_t x_len, const void *y,
+                       size_t y_len, uint64_t *blocks_launched);
+/* Non-blocking: copy finished outputs into out (host or device memory per
+ * mem_kind), whole blocks only, in block order, at most out_cap bytes;
+ * *out_len: bytes written; *blocks_done (may be NULL): blocks returned so far
+ * over the stream's life. */
+int ext_growing_poll(ext_growing_stream *s, void *out, size_t out_cap, size_t *out_len,
+                     uint64_t *blocks_done);
+/* As ext_growing_poll, but first waits for every launched block. */
+int ext_growing_drain(ext_growing_stream *s, void *out, size_t out_cap, size_t *out_len,
+                      uint64_t *blocks_done);
+/* Algorithm 2's state: the next block l, its degree q_l, and the bytes per
+ * source taken by blocks 0 .. l-1 (any pointer may be NULL). */
+int ext_growing_state(const ext_growing_stream *s, uint64_t *next_block, uint64_t *next_q,
+                      uint64_t *consumed_bytes);
+/* Close: the incomplete block is dropped (Algorithm 2 outputs whole blocks
+ * only) and its size, the larger side's pending bytes in bits, reported in
+ * *dropped_bits (may be NULL); outputs not yet polled are discarded. */
+int ext_growing_close(ext_growing_stream *s, uint64_t *dropped_bits);
+
 enum { EXT_NOALLOC_MAX_BLOCKS = 4096 };
 int ext_growing_extract_noalloc(ext_growing *g, const void *x, const void *y, uint64_t n_bytes,
                                 uint64_t max_blocks, void *out, uint64_t out_cap,
@@ -342,10 +397,16 @@ int ext_batch_destroy(ext_batch *b);
  * pair completed so far on every channel in one persistent launch per base
  * size, while earlier cycles may still be on the GPU (at most max_inflight).
  * Outputs come back per channel, in block order, exactly once.
- * Admission: a channel holds at most its ring's worth of blocks between
- * received and polled, and a cycle takes at most stage_bytes of input and returns at most
- * outbox_bytes of output; beyond that ext_server_submit returns EXT_EAGAIN
- * and consumes nothing.  All calls are thread-safe.
+ * Admission: a channel is admitted by free device memory -- ext_server_open
+ * allocates the channel's two device rings only if they fit in the device's
+ * free memory (hipMemGetInfo) less device_reserve_bytes, and within
+ * rings_bytes_cap over all open channels, else returns EXT_EAGAIN with
+ * nothing allocated (retry once channels have closed).  Every other device
+ * buffer is allocated at create time, so a submission never needs more
+ * device memory: a channel holds at most its ring's worth of blocks between
+ * received and polled, and a cycle takes at most stage_bytes of input and
+ * returns at most outbox_bytes of output; beyond that ext_server_submit
+ * returns EXT_EAGAIN and consumes nothing.  All calls are thread-safe.
  */
 typedef struct ext_server ext_server;
 typedef struct {
@@ -375,6 +436,11 @@ typedef struct {
     uint32_t timing;        /* 1: time every cycle's phases on the GPU with events (the
                                gpu_ns, stage_ns and extract_ns stats); default 0 */
     uint32_t reserved;
+    uint64_t device_reserve_bytes; /* admission: device memory a channel open must leave
+                                      free (default 1 GiB) */
+    uint64_t rings_bytes_cap;      /* admission: device bytes the rings of all open
+                                      channels may hold together; 0 = no cap beyond free
+                                      memory (default 0) */
 } ext_server_config;
 typedef struct {
     uint64_t cycles, tiles, pairs, bytes_in;
@@ -389,13 +455,19 @@ typedef struct {
                                kernel's start to the end of the last */
     uint64_t stage_ns;      /* of which: staging the cycle's input and metadata */
     uint64_t extract_ns;    /* of which: the extraction launches (the rest: combine) */
+    uint64_t eagain_mem;    /* channel opens refused: rings beyond free device memory less
+                               the reserve, or beyond rings_bytes_cap */
+    uint64_t rings_bytes;   /* device bytes the open channels' rings hold now */
+    uint64_t free_bytes;    /* the device's free memory at the last channel open */
 } ext_server_stats;
 
 void ext_server_config_init(ext_server_config *c);
 /* cfg and p may be NULL (defaults); p->n_taps must be 0; p->autotune,
  * base_bits, groups, pairs_per_group, device and hip_stream apply. */
 int ext_server_create(const ext_server_config *cfg, const ext_params *p, ext_server **out);
-/* Open a channel; *channel receives its index.  EXT_EAGAIN: no free slot. */
+/* Open a channel; *channel receives its index.  EXT_EAGAIN: no free slot,
+ * or its rings do not fit in free device memory less the reserve or under
+ * rings_bytes_cap (nothing allocated). */
 int ext_server_open(ext_server *s, uint64_t n_bits, uint32_t m_bits, uint32_t *channel);
 int ext_server_submit(ext_server *s, uint32_t channel, const void *x, size_t x_len,
                       const void *y, size_t y_len);
@@ -473,6 +545,10 @@ typedef struct {
     double mean_gpu_us;             /* served mode: GPU time of a cycle, mean */
     double mean_tiles;              /* served mode: work-group tiles per cycle, mean */
     double mean_stage_us, mean_extract_us;  /* served mode: parts of mean_gpu_us */
+    uint64_t rings_bytes;           /* served mode: device bytes the channels' rings held
+                                       (admitted against free device memory) */
+    uint64_t free_bytes;            /* served mode: device free memory at the last open */
+    uint64_t eagain_mem;            /* served mode: channel opens refused for memory */
 } ext_sim_result;
 /* capture_len (may be NULL): per channel, bytes written to capture. */
 int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t *capture_len);

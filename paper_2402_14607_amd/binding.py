@@ -36,7 +36,9 @@ EXPORTED = (
     "ext_server_destroy", "ext_serve_simulate", "ext_server_ready",
     "ext_choose_params", "ext_block_error_log2", "ext_stream_error_log2", "ext_output_bits",
     "ext_growing_create", "ext_growing_blocks", "ext_growing_extract",
-    "ext_growing_extract_noalloc", "ext_growing_destroy",
+    "ext_growing_extract_noalloc", "ext_growing_destroy", "ext_growing_open",
+    "ext_growing_submit", "ext_growing_poll", "ext_growing_drain", "ext_growing_state",
+    "ext_growing_close",
     "ext_probe_valu_rate",
 )
 
@@ -98,6 +100,8 @@ class ServerConfig(ctypes.Structure):
         ("split_pairs", ctypes.c_uint32),
         ("timing", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("device_reserve_bytes", ctypes.c_uint64),
+        ("rings_bytes_cap", ctypes.c_uint64),
     ]
 
 
@@ -105,7 +109,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("cycles", "tiles", "pairs", "bytes_in", "eagain_ring", "eagain_stage",
                  "gpu_busy_ns", "split_pairs", "build_ns", "launch_ns", "max_cycle_ns",
-                 "gpu_ns", "stage_ns", "extract_ns")]
+                 "gpu_ns", "stage_ns", "extract_ns", "eagain_mem", "rings_bytes",
+                 "free_bytes")]
 
 
 class SimConfig(ctypes.Structure):
@@ -148,7 +153,8 @@ class SimResult(ctypes.Structure):
                 ("mean_build_us", ctypes.c_double), ("mean_launch_us", ctypes.c_double),
                 ("max_cycle_us", ctypes.c_double), ("mean_gpu_us", ctypes.c_double),
                 ("mean_tiles", ctypes.c_double), ("mean_stage_us", ctypes.c_double),
-                ("mean_extract_us", ctypes.c_double)]
+                ("mean_extract_us", ctypes.c_double), ("rings_bytes", ctypes.c_uint64),
+                ("free_bytes", ctypes.c_uint64), ("eagain_mem", ctypes.c_uint64)]
 
 
 _lib = None
@@ -211,6 +217,12 @@ def load() -> ctypes.CDLL:
         "ext_growing_extract": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
         "ext_growing_extract_noalloc": (ctypes.c_int, [vp, vp, vp, u64, u64, vp, u64, u64p]),
         "ext_growing_destroy": (ctypes.c_int, [vp]),
+        "ext_growing_open": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
+        "ext_growing_submit": (ctypes.c_int, [vp, vp, sz, vp, sz, u64p]),
+        "ext_growing_poll": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
+        "ext_growing_drain": (ctypes.c_int, [vp, vp, sz, szp, u64p]),
+        "ext_growing_state": (ctypes.c_int, [vp, u64p, u64p, u64p]),
+        "ext_growing_close": (ctypes.c_int, [vp, u64p]),
         "ext_probe_valu_rate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
         "ext_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
         "ext_server_destroy": (ctypes.c_int, [vp]),
@@ -626,10 +638,11 @@ class Growing:
     """One ext_growing: Algorithm 2's growing blocks (q_l = q1 + l * delta_steps * b)."""
 
     def __init__(self, n_e: int, q1: int, delta_steps: int, *, sample_bits: int = 8,
-                 device_memory: bool = True, stream=None, device: int = -1):
+                 device_memory: bool = True, stream=None, device: int = -1,
+                 device_bytes_cap: int = 0):
         self.lib = load()
         p = make_params(self.lib, device_memory=device_memory, stream=stream,
-                        sample_bits=sample_bits, device=device)
+                        sample_bits=sample_bits, device=device, device_bytes_cap=device_bytes_cap)
         self.handle = ctypes.c_void_p()
         _check(self.lib.ext_growing_create(n_e, q1, delta_steps, ctypes.byref(p),
                                            ctypes.byref(self.handle)), "ext_growing_create")
@@ -659,6 +672,10 @@ class Growing:
                "ext_growing_extract_noalloc")
         return k.value
 
+    def open_stream(self) -> "GrowingStream":
+        """Algorithm 2's online form on this handle (ext_growing_open)."""
+        return GrowingStream(self)
+
     def close(self):
         if self.handle:
             self.lib.ext_growing_destroy(self.handle)
@@ -669,6 +686,50 @@ class Growing:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class GrowingStream:
+    """One ext_growing_stream: Algorithm 2 on unbounded sources fed in chunks."""
+
+    def __init__(self, g: Growing):
+        self.lib = g.lib
+        self.g = g
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.ext_growing_open(g.handle, ctypes.byref(self.handle)), "ext_growing_open")
+
+    def submit(self, x, x_len: int, y, y_len: int) -> int:
+        """EXT_OK or EXT_EAGAIN (nothing consumed); raises on other errors."""
+        n = ctypes.c_uint64()
+        rc = self.lib.ext_growing_submit(self.handle, _ptr(x) if x_len else None, x_len,
+                                         _ptr(y) if y_len else None, y_len, ctypes.byref(n))
+        if rc == EXT_EAGAIN:
+            return rc
+        _check(rc, "ext_growing_submit")
+        return rc
+
+    def poll(self, out, out_cap: int, wait: bool = False):
+        """(bytes written, blocks returned so far)."""
+        n = ctypes.c_size_t()
+        done = ctypes.c_uint64()
+        f = self.lib.ext_growing_drain if wait else self.lib.ext_growing_poll
+        _check(f(self.handle, _ptr(out) if out_cap else None, out_cap, ctypes.byref(n),
+                 ctypes.byref(done)), "ext_growing_poll")
+        return n.value, done.value
+
+    def state(self) -> tuple[int, int, int]:
+        """(next block l, its degree q_l, bytes per source taken so far)."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.ext_growing_state(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)), "ext_growing_state")
+        return a.value, b.value, c.value
+
+    def close(self) -> int:
+        """Dropped bits of the incomplete block."""
+        d = ctypes.c_uint64()
+        if self.handle:
+            _check(self.lib.ext_growing_close(self.handle, ctypes.byref(d)), "ext_growing_close")
+            self.handle = ctypes.c_void_p()
+        return d.value
 
 
 def probe_valu_rate(device: int = -1) -> float:

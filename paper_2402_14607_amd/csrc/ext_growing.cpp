@@ -8,11 +8,18 @@
 // blocks into k one-pair streams of the batched kernel (one persistent
 // launch per base size) in the padded layout: block and output offsets are
 // then byte-granular, whatever q_l is.
+//
+// The online form (ext_growing_open / submit / poll / close) runs Algorithm 2
+// on unbounded sources: its state (the next block l, its degree q_l and the
+// bytes consumed so far, i of Algorithm 2) carries over from call to call,
+// the bytes of the block still incomplete wait in device buffers, and every
+// submission launches the blocks it completes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
 #include <map>
 #include <new>
 #include <tuple>
@@ -46,6 +53,8 @@ struct ext_growing {
     hipStream_t lanes[kLanes] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t joins[kLanes] = {};
+    hipStream_t copy = nullptr;  // online form: outputs back to the caller
+    std::vector<ext_growing_stream*> open_streams;
     int sticky = EXT_OK;
 };
 
@@ -66,6 +75,8 @@ void release_lanes(ext_growing* g) {
     }
     if (g->fork) (void)hipEventDestroy(g->fork);
     g->fork = nullptr;
+    if (g->copy) (void)hipStreamDestroy(g->copy);
+    g->copy = nullptr;
 }
 
 void free_scratch(ext_growing* g) {
@@ -196,7 +207,8 @@ int ext_growing_create(uint32_t n_e, uint32_t q1, uint32_t delta_steps, const ex
         delete g;
         return EXT_EDEVICE;
     }
-    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&g->copy, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < ext_growing::kLanes; ++i)
         ok = hipStreamCreateWithFlags(&g->lanes[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&g->joins[i], hipEventDisableTiming) == hipSuccess;
@@ -232,6 +244,126 @@ struct Tables {
     uint32_t* heads;
 };
 
+// One persistent launch of a planned call: the tiles [off, off + n) of one
+// (base size, work-group size) class.
+struct LaunchPlan {
+    uint32_t bw, threads, off, n, lds, grid;
+    uint64_t cost;  // sum of its tiles' costs
+};
+
+// A planned call: one one-pair stream and one tile per block, grouped into
+// launches.
+struct Planned {
+    std::vector<BatchStream> streams;
+    std::vector<BatchTile> tiles;
+    std::vector<LaunchPlan> launches;
+};
+
+// Plan k consecutive blocks of degrees q0, q0 + step, ... whose inputs start
+// at xs / ys and whose outputs start at os (device addresses).  May throw
+// std::bad_alloc.
+int plan_blocks(ext_growing* g, uint64_t q0, uint64_t k, const uint8_t* xs, const uint8_t* ys,
+                uint8_t* os, Planned* p) {
+    p->streams.clear();
+    p->tiles.clear();
+    p->launches.clear();
+    p->streams.reserve(k);
+    // launches: (base size, work-group size) -> tile list with cost
+    std::map<std::pair<uint32_t, uint32_t>, std::vector<std::pair<uint64_t, uint32_t>>> groups;
+    uint64_t q = q0, in_off = 0, out_off = 0;
+    for (uint64_t l = 0; l < k; ++l) {
+        if (q > 0xffffffffull) return EXT_ENOTSUP;
+        ExtShape s;
+        const int rc = plan_for(g, (uint32_t)q, &s);
+        if (rc) return rc;
+        p->streams.push_back(BatchStream{xs + in_off, ys + in_off, os + out_off, 1, s});
+        const uint64_t cost = ((uint64_t)s.np * s.groups + s.threads - 1) / s.threads * s.epg;
+        groups[{s.bw, s.threads}].push_back({cost, (uint32_t)l});
+        in_off += s.nbytes;
+        out_off += s.qbytes;
+        q += (uint64_t)g->delta_steps * g->b;
+    }
+    if (groups.size() > kMaxGroups) return EXT_ENOTSUP;
+    int cus = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
+    for (auto& kv : groups) {
+        auto& v = kv.second;
+        // longest tiles first, so the queue ends with short ones
+        std::stable_sort(v.begin(), v.end(),
+                         [](const auto& a, const auto& c) { return a.first > c.first; });
+        LaunchPlan ln{kv.first.first, kv.first.second, (uint32_t)p->tiles.size(),
+                      (uint32_t)v.size(), 0, 0, 0};
+        for (auto& t : v) {
+            ln.cost += t.first;
+            p->tiles.push_back(BatchTile{t.second, 1, 0, 0, 0, 0});
+            ln.lds = std::max(ln.lds, p->streams[t.second].shape.lds_words * 4);
+        }
+        int occ = 0;
+        if (qext::batch_occupancy(ln.bw, ln.threads, true, ln.lds, &occ) != hipSuccess || occ <= 0)
+            occ = 1;
+        ln.grid = (uint32_t)std::min<uint64_t>(ln.n, (uint64_t)cus * occ);
+        p->launches.push_back(ln);
+    }
+    return EXT_OK;
+}
+
+// Queue a planned call on g->stream: its tables (read from streams_src and
+// tiles_src, host memory that must stay untouched until the copies have run)
+// and zeroed queue heads into tab, then the launches on the lanes, forked
+// from and joined back into g->stream.  On a HIP error the work queued so
+// far is waited for and the handle's sticky error set.
+int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void* streams_src,
+                 const void* tiles_src) {
+    auto device_error = [&]() {
+        for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGetLastError();
+        return g->sticky = EXT_EDEVICE;
+    };
+    // the tables and the launches' zeroed queue heads, in stream order
+    // before the lanes fork (a copy, so that no launch needs a reset kernel)
+    static const uint32_t kZeroHeads[kMaxGroups] = {};
+    if (hipMemcpyAsync(tab.streams, streams_src, p.streams.size() * sizeof(BatchStream),
+                       hipMemcpyHostToDevice, g->stream) ||
+        hipMemcpyAsync(tab.tiles, tiles_src, p.tiles.size() * sizeof(BatchTile),
+                       hipMemcpyHostToDevice, g->stream) ||
+        hipMemcpyAsync(tab.heads, kZeroHeads, p.launches.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, g->stream))
+        return device_error();
+    // fork: the lanes start after the table copies (and the caller's work
+    // queued before this call); costliest launches first, each on the
+    // least loaded lane; join: the stream waits for every lane used
+    if (hipEventRecord(g->fork, g->stream) != hipSuccess) return device_error();
+    std::vector<size_t> order(p.launches.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
+        return p.launches[a].cost > p.launches[c].cost;
+    });
+    uint64_t load[ext_growing::kLanes] = {};
+    bool used[ext_growing::kLanes] = {};
+    for (size_t i : order) {
+        const LaunchPlan& ln = p.launches[i];
+        int lane = 0;
+        for (int l = 1; l < ext_growing::kLanes; ++l)
+            if (load[l] < load[lane]) lane = l;
+        if (!used[lane] && hipStreamWaitEvent(g->lanes[lane], g->fork, 0) != hipSuccess)
+            return device_error();
+        used[lane] = true;
+        load[lane] += ln.cost + 1;
+        if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams, tab.tiles + ln.off,
+                                       ln.n, tab.heads + i, nullptr, ln.grid, ln.lds,
+                                       g->lanes[lane]) != hipSuccess)
+            return device_error();
+    }
+    for (int l = 0; l < ext_growing::kLanes; ++l) {
+        if (!used[l]) continue;
+        if (hipEventRecord(g->joins[l], g->lanes[l]) != hipSuccess ||
+            hipStreamWaitEvent(g->stream, g->joins[l], 0) != hipSuccess)
+            return device_error();
+    }
+    return EXT_OK;
+}
+
 // Blocks 0 .. k-1 of x and y into out (ext_growing_extract); the launch
 // tables go to *fixed when given (nothing is allocated then), else to the
 // handle's scratch, grown on demand.
@@ -246,18 +378,12 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
     if (!x || !y || !out || out_cap < r.out_bytes) return EXT_EINVAL;
     if (fixed && r.k > qext::kNoAllocMaxBlocks) return EXT_ENOMEM;
     if (hipSetDevice(g->device) != hipSuccess) return EXT_EDEVICE;
-    int rc = EXT_OK;
-    std::vector<BatchStream> streams;
-    std::vector<BatchTile> tiles;
-    // launches: (base size, work-group size) -> tile list with cost
-    std::map<std::pair<uint32_t, uint32_t>, std::vector<std::pair<uint64_t, uint32_t>>> groups;
     try {
-        streams.reserve(r.k);
         Tables tab;
         if (fixed) {
             tab = *fixed;
         } else {
-            rc = grow(g, r.k, r.in_bytes, r.out_bytes);
+            const int rc = grow(g, r.k, r.in_bytes, r.out_bytes);
             if (rc) return rc;
             tab = Tables{g->d_streams, g->d_tiles, g->d_heads};
         }
@@ -265,98 +391,26 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
         const uint8_t* xs = host ? g->dx : (const uint8_t*)x;
         const uint8_t* ys = host ? g->dy : (const uint8_t*)y;
         uint8_t* os = host ? g->dout : (uint8_t*)out;
-        uint64_t q = g->q1, in_off = 0, out_off = 0;
-        for (uint64_t l = 0; l < r.k; ++l) {
-            ExtShape s;
-            rc = plan_for(g, (uint32_t)q, &s);
-            if (rc) return rc;
-            streams.push_back(BatchStream{xs + in_off, ys + in_off, os + out_off, 1, s});
-            const uint64_t cost = ((uint64_t)s.np * s.groups + s.threads - 1) / s.threads * s.epg;
-            groups[{s.bw, s.threads}].push_back({cost, (uint32_t)l});
-            in_off += s.nbytes;
-            out_off += s.qbytes;
-            q += (uint64_t)g->delta_steps * g->b;
-        }
-        if (groups.size() > kMaxGroups) return EXT_ENOTSUP;
+        Planned p;
+        int rc = plan_blocks(g, g->q1, r.k, xs, ys, os, &p);
+        if (rc) return rc;
         // from here on work is queued: every exit waits for the stream first,
         // so no copy still reads the caller's or these host buffers
-        auto device_error = [&]() {
-            for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
+        if (host) {
+            if (hipMemcpyAsync(g->dx, x, r.in_bytes, hipMemcpyHostToDevice, g->stream) ||
+                hipMemcpyAsync(g->dy, y, r.in_bytes, hipMemcpyHostToDevice, g->stream)) {
+                (void)hipStreamSynchronize(g->stream);
+                (void)hipGetLastError();
+                return g->sticky = EXT_EDEVICE;
+            }
+        }
+        rc = queue_blocks(g, p, tab, p.streams.data(), p.tiles.data());
+        if (rc) return rc;
+        if (host && hipMemcpyAsync(out, g->dout, r.out_bytes, hipMemcpyDeviceToHost, g->stream)) {
             (void)hipStreamSynchronize(g->stream);
             (void)hipGetLastError();
             return g->sticky = EXT_EDEVICE;
-        };
-        if (host) {
-            if (hipMemcpyAsync(g->dx, x, r.in_bytes, hipMemcpyHostToDevice, g->stream) ||
-                hipMemcpyAsync(g->dy, y, r.in_bytes, hipMemcpyHostToDevice, g->stream))
-                return device_error();
         }
-        int cus = 1;
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
-        struct L {
-            uint32_t bw, threads, off, n, lds, grid;
-            uint64_t cost;  // sum of its tiles' costs
-        };
-        std::vector<L> launches;
-        for (auto& kv : groups) {
-            auto& v = kv.second;
-            // longest tiles first, so the queue ends with short ones
-            std::stable_sort(v.begin(), v.end(),
-                             [](const auto& a, const auto& c) { return a.first > c.first; });
-            L ln{kv.first.first, kv.first.second, (uint32_t)tiles.size(), (uint32_t)v.size(), 0, 0, 0};
-            for (auto& t : v) {
-                ln.cost += t.first;
-                tiles.push_back(BatchTile{t.second, 1, 0, 0, 0, 0});
-                ln.lds = std::max(ln.lds, streams[t.second].shape.lds_words * 4);
-            }
-            int occ = 0;
-            if (qext::batch_occupancy(ln.bw, ln.threads, true, ln.lds, &occ) != hipSuccess || occ <= 0)
-                occ = 1;
-            ln.grid = (uint32_t)std::min<uint64_t>(ln.n, (uint64_t)cus * occ);
-            launches.push_back(ln);
-        }
-        // the tables and the launches' zeroed queue heads, in stream order
-        // before the lanes fork (a copy, so that no launch needs a reset kernel)
-        static const uint32_t kZeroHeads[kMaxGroups] = {};
-        if (hipMemcpyAsync(tab.streams, streams.data(), r.k * sizeof(BatchStream),
-                           hipMemcpyHostToDevice, g->stream) ||
-            hipMemcpyAsync(tab.tiles, tiles.data(), r.k * sizeof(BatchTile),
-                           hipMemcpyHostToDevice, g->stream) ||
-            hipMemcpyAsync(tab.heads, kZeroHeads, launches.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, g->stream))
-            return device_error();
-        // fork: the lanes start after the table copies (and the caller's work
-        // queued before this call); costliest launches first, each on the
-        // least loaded lane; join: the stream waits for every lane used
-        if (hipEventRecord(g->fork, g->stream) != hipSuccess) return device_error();
-        std::vector<size_t> order(launches.size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](size_t a, size_t c) { return launches[a].cost > launches[c].cost; });
-        uint64_t load[ext_growing::kLanes] = {};
-        bool used[ext_growing::kLanes] = {};
-        for (size_t i : order) {
-            const L& ln = launches[i];
-            int lane = 0;
-            for (int l = 1; l < ext_growing::kLanes; ++l)
-                if (load[l] < load[lane]) lane = l;
-            if (!used[lane] && hipStreamWaitEvent(g->lanes[lane], g->fork, 0) != hipSuccess)
-                return device_error();
-            used[lane] = true;
-            load[lane] += ln.cost + 1;
-            if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams,
-                                           tab.tiles + ln.off, ln.n, tab.heads + i, nullptr,
-                                           ln.grid, ln.lds, g->lanes[lane]) != hipSuccess)
-                return device_error();
-        }
-        for (int l = 0; l < ext_growing::kLanes; ++l) {
-            if (!used[l]) continue;
-            if (hipEventRecord(g->joins[l], g->lanes[l]) != hipSuccess ||
-                hipStreamWaitEvent(g->stream, g->joins[l], 0) != hipSuccess)
-                return device_error();
-        }
-        if (host && hipMemcpyAsync(out, g->dout, r.out_bytes, hipMemcpyDeviceToHost, g->stream))
-            return device_error();
         // the host vectors above are read by the copies: wait before they go
         if (hipStreamSynchronize(g->stream) != hipSuccess) return g->sticky = EXT_EDEVICE;
     } catch (const std::bad_alloc&) {
@@ -392,11 +446,481 @@ int ext_growing_extract_noalloc(ext_growing* g, const void* x, const void* y, ui
 int ext_growing_destroy(ext_growing* g) {
     if (!g) return EXT_EINVAL;
     (void)hipSetDevice(g->device);
+    while (!g->open_streams.empty()) (void)ext_growing_close(g->open_streams.back(), nullptr);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     release_lanes(g);
     free_scratch(g);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+    return EXT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// online form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kMaxLaunchBlocks = 1024;  // blocks per queued call (table size)
+constexpr size_t kTableBytes = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream)) +
+                               qext::round256(kMaxLaunchBlocks * sizeof(BatchTile));
+
+// One queued call of the online form: k blocks from block0 (degree q0), their
+// outputs at monotonic ring position opos.
+struct GLaunch {
+    uint64_t block0, k, q0;
+    uint64_t opos, obytes;
+    uint64_t taken = 0, taken_bytes = 0;  // blocks and bytes returned by poll
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct ext_growing_stream {
+    ext_growing* g = nullptr;
+    uint64_t step = 0;  // Delta * b, bits of degree added per block
+    // Algorithm 2's state: the next block l, its degree q_l, and i (bytes per
+    // source of blocks 0 .. l-1)
+    uint64_t next_block = 0, next_q = 0, consumed = 0;
+    uint64_t limit_base = 0;  // device_bytes_cap
+    // pending input on the device: double buffers, live bytes [head, tail)
+    uint8_t* xbuf[2] = {nullptr, nullptr};
+    uint8_t* ybuf[2] = {nullptr, nullptr};
+    int xcur = 0, ycur = 0;
+    uint64_t bcap = 0;
+    uint64_t xhead = 0, xtail = 0, yhead = 0, ytail = 0;
+    // outputs: byte ring; a call's outputs never wrap
+    uint8_t* oring = nullptr;
+    uint64_t ocap = 0;
+    uint64_t owrite = 0, oread = 0;  // monotonic positions
+    std::deque<GLaunch> inflight;
+    uint64_t launched = 0, returned = 0;
+    // device launch tables (queued calls run in stream order, so one set)
+    uint8_t* dtab = nullptr;
+    uint32_t* dheads = nullptr;
+    // pinned copies of the tables, two sets, each reused once its copy ran
+    uint8_t* ptab = nullptr;
+    hipEvent_t ptab_free[2] = {nullptr, nullptr};
+    int ptab_next = 0;
+    // pinned staging of host submissions
+    uint8_t* stage = nullptr;
+    uint64_t stage_bytes = 0;
+    hipEvent_t stage_free = nullptr;
+    Planned plan;
+};
+
+namespace {
+
+uint64_t block_bytes(const ext_growing_stream* s, uint64_t q) { return q * s->g->n_e / 8; }
+
+// Admission limit on the pending bytes of one side: the cap, bounded so that
+// their outputs (at most 1/n_e of them) fit in half the output ring, but
+// never below two blocks of the next degree.
+uint64_t limit_bytes(const ext_growing_stream* s) {
+    const uint64_t by_ring = s->ocap / 2 * s->g->n_e;
+    return std::max(std::min(s->limit_base, by_ring), 2 * block_bytes(s, s->next_q));
+}
+
+void free_stream(ext_growing_stream* s) {
+    for (GLaunch& L : s->inflight)
+        if (L.done) (void)hipEventDestroy(L.done);
+    s->inflight.clear();
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(s->xbuf[k]);
+        (void)hipFree(s->ybuf[k]);
+        if (s->ptab_free[k]) (void)hipEventDestroy(s->ptab_free[k]);
+    }
+    (void)hipFree(s->oring);
+    (void)hipFree(s->dtab);
+    (void)hipFree(s->dheads);
+    if (s->ptab) (void)hipHostFree(s->ptab);
+    if (s->stage) (void)hipHostFree(s->stage);
+    if (s->stage_free) (void)hipEventDestroy(s->stage_free);
+    delete s;
+}
+
+int sfail(ext_growing_stream* s) {
+    (void)hipGetLastError();
+    return s->g->sticky = EXT_EDEVICE;
+}
+
+// Whole blocks that `avail` more bytes per source complete from the state
+// (next_q), at most max_k; their input and output bytes.
+void complete_blocks(const ext_growing_stream* s, uint64_t avail, uint64_t max_k, uint64_t* k,
+                     uint64_t* in_bytes, uint64_t* out_bytes) {
+    uint64_t q = s->next_q, n = 0, ib = 0, ob = 0;
+    while (n < max_k) {
+        const uint64_t nb = block_bytes(s, q);
+        if (ib + nb > avail) break;
+        ib += nb;
+        ob += q / 8;
+        ++n;
+        q += s->step;
+    }
+    *k = n;
+    *in_bytes = ib;
+    *out_bytes = ob;
+}
+
+// The sequence of queued calls that k blocks from degree q0 make (at most
+// kMaxLaunchBlocks each), placed in the output ring from owrite: false if
+// they do not fit beside the unreturned outputs.  sizes receives (k, bytes)
+// per call and *end the ring position after the last.
+bool ring_fit(const ext_growing_stream* s, uint64_t q0, uint64_t k,
+              std::vector<std::pair<uint64_t, uint64_t>>* sizes, uint64_t* end) {
+    uint64_t pos = s->owrite, q = q0;
+    sizes->clear();
+    while (k) {
+        const uint64_t n = std::min(k, kMaxLaunchBlocks);
+        uint64_t ob = 0;
+        for (uint64_t j = 0; j < n; ++j, q += s->step) ob += q / 8;
+        if (ob > s->ocap) return false;
+        const uint64_t off = pos % s->ocap;
+        if (off + ob > s->ocap) pos += s->ocap - off;  // the call starts at the ring's front
+        if (pos + ob - s->oread > s->ocap) return false;
+        sizes->push_back({n, ob});
+        pos += ob;
+        k -= n;
+    }
+    *end = pos;
+    return true;
+}
+
+// Room for len more bytes after tail on one side: compact the live bytes to
+// the front of the other buffer, or grow both buffers (after waiting for the
+// queued work that reads them).
+int make_room(ext_growing_stream* s, uint8_t** buf, int* cur, uint64_t* head, uint64_t* tail,
+              uint64_t len) {
+    ext_growing* g = s->g;
+    const uint64_t live = *tail - *head;
+    if (*tail + len <= s->bcap) return EXT_OK;
+    if (live + len <= s->bcap) {
+        const int nxt = 1 - *cur;
+        if (live && hipMemcpyAsync(buf[nxt], buf[*cur] + *head, live, hipMemcpyDeviceToDevice,
+                                   g->stream) != hipSuccess)
+            return sfail(s);
+        *cur = nxt;
+        *head = 0;
+        *tail = live;
+        return EXT_OK;
+    }
+    return EXT_EAGAIN;  // the caller grows the buffers first
+}
+
+// Grow the pending buffers to at least `need` bytes per buffer.
+int grow_pending(ext_growing_stream* s, uint64_t need) {
+    ext_growing* g = s->g;
+    uint64_t cap = std::max<uint64_t>(2 * s->bcap, need);
+    cap = (cap + 255) / 256 * 256;
+    uint8_t* nx[2] = {nullptr, nullptr};
+    uint8_t* ny[2] = {nullptr, nullptr};
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k)
+        ok = hipMalloc((void**)&nx[k], cap) == hipSuccess &&
+             hipMalloc((void**)&ny[k], cap) == hipSuccess;
+    if (!ok) {
+        for (int k = 0; k < 2; ++k) {
+            (void)hipFree(nx[k]);
+            (void)hipFree(ny[k]);
+        }
+        (void)hipGetLastError();
+        return EXT_ENOMEM;
+    }
+    const uint64_t xl = s->xtail - s->xhead, yl = s->ytail - s->yhead;
+    if ((xl && hipMemcpyAsync(nx[0], s->xbuf[s->xcur] + s->xhead, xl, hipMemcpyDeviceToDevice,
+                              g->stream) != hipSuccess) ||
+        (yl && hipMemcpyAsync(ny[0], s->ybuf[s->ycur] + s->yhead, yl, hipMemcpyDeviceToDevice,
+                              g->stream) != hipSuccess) ||
+        hipStreamSynchronize(g->stream) != hipSuccess) {
+        for (int k = 0; k < 2; ++k) {
+            (void)hipFree(nx[k]);
+            (void)hipFree(ny[k]);
+        }
+        return sfail(s);
+    }
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(s->xbuf[k]);
+        (void)hipFree(s->ybuf[k]);
+        s->xbuf[k] = nx[k];
+        s->ybuf[k] = ny[k];
+    }
+    s->xcur = s->ycur = 0;
+    s->xhead = s->yhead = 0;
+    s->xtail = xl;
+    s->ytail = yl;
+    s->bcap = cap;
+    return EXT_OK;
+}
+
+// Queue the copy of one submission to the tails of the pending buffers; host
+// data go through pinned staging, reused once the previous copies have run.
+int append(ext_growing_stream* s, const void* x, uint64_t x_len, const void* y, uint64_t y_len) {
+    ext_growing* g = s->g;
+    uint8_t* xdst = s->xbuf[s->xcur] + s->xtail;
+    uint8_t* ydst = s->ybuf[s->ycur] + s->ytail;
+    if (g->params.mem_kind == EXT_MEM_DEVICE) {
+        if ((x_len && hipMemcpyAsync(xdst, x, x_len, hipMemcpyDeviceToDevice, g->stream)) ||
+            (y_len && hipMemcpyAsync(ydst, y, y_len, hipMemcpyDeviceToDevice, g->stream)))
+            return sfail(s);
+        return EXT_OK;
+    }
+    if (!x_len && !y_len) return EXT_OK;
+    if (hipEventSynchronize(s->stage_free) != hipSuccess) return sfail(s);
+    const uint64_t len = x_len + y_len;
+    if (s->stage_bytes < len) {
+        if (s->stage) (void)hipHostFree(s->stage);
+        s->stage = nullptr;
+        s->stage_bytes = 0;
+        if (hipHostMalloc((void**)&s->stage, len, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return EXT_ENOMEM;
+        }
+        s->stage_bytes = len;
+    }
+    if (x_len) memcpy(s->stage, x, x_len);
+    if (y_len) memcpy(s->stage + x_len, y, y_len);
+    if ((x_len && hipMemcpyAsync(xdst, s->stage, x_len, hipMemcpyHostToDevice, g->stream)) ||
+        (y_len &&
+         hipMemcpyAsync(ydst, s->stage + x_len, y_len, hipMemcpyHostToDevice, g->stream)) ||
+        hipEventRecord(s->stage_free, g->stream))
+        return sfail(s);
+    return EXT_OK;
+}
+
+// Launch every block the pending bytes complete, in calls of at most
+// kMaxLaunchBlocks blocks placed as ring_fit placed them.
+int launch_ready(ext_growing_stream* s) {
+    ext_growing* g = s->g;
+    uint64_t k, ib, ob;
+    complete_blocks(s, std::min(s->xtail - s->xhead, s->ytail - s->yhead), ~0ull, &k, &ib, &ob);
+    if (!k) return EXT_OK;
+    std::vector<std::pair<uint64_t, uint64_t>> sizes;
+    uint64_t end = 0;
+    if (!ring_fit(s, s->next_q, k, &sizes, &end)) return EXT_EAGAIN;  // checked by the caller
+    for (const auto& sz : sizes) {
+        const uint64_t n = sz.first, bytes = sz.second;
+        uint64_t pos = s->owrite;
+        const uint64_t off = pos % s->ocap;
+        if (off + bytes > s->ocap) pos += s->ocap - off;
+        const uint8_t* xp = s->xbuf[s->xcur] + s->xhead;
+        const uint8_t* yp = s->ybuf[s->ycur] + s->yhead;
+        int rc = plan_blocks(g, s->next_q, n, xp, yp, s->oring + pos % s->ocap, &s->plan);
+        if (rc) return rc;
+        // the pinned table set of the call before last is free once its copy ran
+        const int slot = s->ptab_next;
+        if (hipEventSynchronize(s->ptab_free[slot]) != hipSuccess) return sfail(s);
+        uint8_t* pt = s->ptab + slot * kTableBytes;
+        const size_t tiles_off = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream));
+        memcpy(pt, s->plan.streams.data(), s->plan.streams.size() * sizeof(BatchStream));
+        memcpy(pt + tiles_off, s->plan.tiles.data(), s->plan.tiles.size() * sizeof(BatchTile));
+        const Tables tab{(BatchStream*)s->dtab, (BatchTile*)(s->dtab + tiles_off), s->dheads};
+        rc = queue_blocks(g, s->plan, tab, pt, pt + tiles_off);
+        if (rc) return rc;
+        GLaunch L{s->next_block, n, s->next_q, pos, bytes};
+        if (hipEventRecord(s->ptab_free[slot], g->stream) != hipSuccess ||
+            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+            return sfail(s);
+        if (hipEventRecord(L.done, g->stream) != hipSuccess) {
+            (void)hipEventDestroy(L.done);
+            return sfail(s);
+        }
+        s->ptab_next = 1 - slot;
+        s->inflight.push_back(L);
+        s->owrite = pos + bytes;
+        uint64_t in = 0;
+        for (uint64_t j = 0; j < n; ++j) {
+            in += block_bytes(s, s->next_q);
+            s->next_q += s->step;
+        }
+        s->next_block += n;
+        s->consumed += in;
+        s->launched += n;
+        s->xhead += in;
+        s->yhead += in;
+    }
+    return EXT_OK;
+}
+
+int copy_out(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
+             uint64_t* blocks_done, bool wait) {
+    ext_growing* g = s->g;
+    size_t written = 0;
+    while (!s->inflight.empty()) {
+        GLaunch& L = s->inflight.front();
+        if (wait) {
+            if (hipEventSynchronize(L.done) != hipSuccess) return sfail(s);
+        } else {
+            const hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return sfail(s);
+        }
+        // whole blocks that fit
+        uint64_t n = 0, bytes = 0;
+        uint64_t q = L.q0 + L.taken * s->step;
+        while (L.taken + n < L.k && written + bytes + q / 8 <= out_cap) {
+            bytes += q / 8;
+            ++n;
+            q += s->step;
+        }
+        if (n) {
+            const uint8_t* src = s->oring + (L.opos + L.taken_bytes) % s->ocap;
+            const hipMemcpyKind kind = g->params.mem_kind == EXT_MEM_DEVICE
+                                           ? hipMemcpyDeviceToDevice
+                                           : hipMemcpyDeviceToHost;
+            if (hipMemcpyAsync((uint8_t*)out + written, src, bytes, kind, g->copy) != hipSuccess ||
+                hipStreamSynchronize(g->copy) != hipSuccess)
+                return sfail(s);
+            written += bytes;
+            L.taken += n;
+            L.taken_bytes += bytes;
+            s->returned += n;
+        }
+        if (L.taken < L.k) break;  // the caller's buffer is full
+        s->oread = L.opos + L.obytes;
+        (void)hipEventDestroy(L.done);
+        s->inflight.pop_front();
+    }
+    if (out_len) *out_len = written;
+    if (blocks_done) *blocks_done = s->returned;
+    return EXT_OK;
+}
+
+int genter(ext_growing_stream* s) {
+    if (!s) return EXT_EINVAL;
+    if (s->g->sticky) return s->g->sticky;
+    if (hipSetDevice(s->g->device) != hipSuccess) return EXT_EDEVICE;
+    return EXT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ext_growing_open(ext_growing* g, ext_growing_stream** out) {
+    if (!g || !out) return EXT_EINVAL;
+    *out = nullptr;
+    if (g->sticky) return g->sticky;
+    if (hipSetDevice(g->device) != hipSuccess) return EXT_EDEVICE;
+    ext_growing_stream* s = new (std::nothrow) ext_growing_stream;
+    if (!s) return EXT_ENOMEM;
+    s->g = g;
+    s->step = (uint64_t)g->delta_steps * g->b;
+    s->next_q = g->q1;
+    s->limit_base = g->params.device_bytes_cap ? g->params.device_bytes_cap : (256ull << 20);
+    // pending bytes: room for a few first blocks, grown on demand
+    s->bcap = std::max<uint64_t>(1ull << 20, 4 * block_bytes(s, g->q1));
+    s->bcap = (s->bcap + 255) / 256 * 256;
+    // outputs: twice what the admitted pending input can complete
+    s->ocap = std::min<uint64_t>(64ull << 20,
+                                 std::max<uint64_t>(1ull << 20, 2 * s->limit_base / g->n_e));
+    s->ocap = (s->ocap + 255) / 256 * 256;
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k)
+        ok = hipMalloc((void**)&s->xbuf[k], s->bcap) == hipSuccess &&
+             hipMalloc((void**)&s->ybuf[k], s->bcap) == hipSuccess &&
+             hipEventCreateWithFlags(&s->ptab_free[k], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->oring, s->ocap) == hipSuccess &&
+         hipMalloc((void**)&s->dtab, kTableBytes) == hipSuccess &&
+         hipMalloc((void**)&s->dheads, kMaxGroups * sizeof(uint32_t)) == hipSuccess &&
+         hipHostMalloc((void**)&s->ptab, 2 * kTableBytes, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&s->stage_free, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_stream(s);
+        return EXT_ENOMEM;
+    }
+    try {
+        g->open_streams.push_back(s);
+    } catch (const std::bad_alloc&) {
+        free_stream(s);
+        return EXT_ENOMEM;
+    }
+    *out = s;
+    return EXT_OK;
+}
+
+int ext_growing_submit(ext_growing_stream* s, const void* x, size_t x_len, const void* y,
+                       size_t y_len, uint64_t* blocks_launched) {
+    int rc = genter(s);
+    if (rc) return rc;
+    if ((x_len && !x) || (y_len && !y)) return EXT_EINVAL;
+    const uint64_t xl = s->xtail - s->xhead, yl = s->ytail - s->yhead;
+    // admission: pending bytes per side within the limit
+    const uint64_t lim = limit_bytes(s);
+    if (xl + x_len > lim || yl + y_len > lim) return EXT_EAGAIN;
+    try {
+        // the blocks this chunk completes: every degree planned (so a degree
+        // without modulus or plan refuses the chunk whole), outputs placed
+        uint64_t k, ib, ob;
+        complete_blocks(s, std::min(xl + x_len, yl + y_len), ~0ull, &k, &ib, &ob);
+        uint64_t q = s->next_q;
+        for (uint64_t j = 0; j < k; ++j, q += s->step) {
+            ExtShape sh;
+            if (q > 0xffffffffull) return EXT_ENOTSUP;
+            rc = plan_for(s->g, (uint32_t)q, &sh);
+            if (rc) return rc;
+        }
+        std::vector<std::pair<uint64_t, uint64_t>> sizes;
+        uint64_t end = 0;
+        if (k && !ring_fit(s, s->next_q, k, &sizes, &end)) return EXT_EAGAIN;
+        const uint64_t need = std::max(xl + x_len, yl + y_len);
+        if (need > s->bcap) {
+            rc = grow_pending(s, need);
+            if (rc) return rc;
+        }
+        rc = make_room(s, s->xbuf, &s->xcur, &s->xhead, &s->xtail, x_len);
+        if (rc) return rc;
+        rc = make_room(s, s->ybuf, &s->ycur, &s->yhead, &s->ytail, y_len);
+        if (rc) return rc;
+        rc = append(s, x, x_len, y, y_len);
+        if (rc) return rc;
+        s->xtail += x_len;
+        s->ytail += y_len;
+        rc = launch_ready(s);
+        if (rc) return rc;
+    } catch (const std::bad_alloc&) {
+        return EXT_ENOMEM;
+    }
+    if (blocks_launched) *blocks_launched = s->launched;
+    return EXT_OK;
+}
+
+int ext_growing_poll(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
+                     uint64_t* blocks_done) {
+    const int rc = genter(s);
+    if (rc) return rc;
+    if (!out && out_cap) return EXT_EINVAL;
+    return copy_out(s, out, out_cap, out_len, blocks_done, false);
+}
+
+int ext_growing_drain(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
+                      uint64_t* blocks_done) {
+    const int rc = genter(s);
+    if (rc) return rc;
+    if (!out && out_cap) return EXT_EINVAL;
+    return copy_out(s, out, out_cap, out_len, blocks_done, true);
+}
+
+int ext_growing_state(const ext_growing_stream* s, uint64_t* next_block, uint64_t* next_q,
+                      uint64_t* consumed_bytes) {
+    if (!s) return EXT_EINVAL;
+    if (next_block) *next_block = s->next_block;
+    if (next_q) *next_q = s->next_q;
+    if (consumed_bytes) *consumed_bytes = s->consumed;
+    return EXT_OK;
+}
+
+int ext_growing_close(ext_growing_stream* s, uint64_t* dropped_bits) {
+    if (!s) return EXT_EINVAL;
+    ext_growing* g = s->g;
+    const uint64_t px = s->xtail - s->xhead, py = s->ytail - s->yhead;
+    if (dropped_bits) *dropped_bits = 8 * std::max(px, py);
+    (void)hipSetDevice(g->device);
+    (void)hipStreamSynchronize(g->stream);
+    auto it = std::find(g->open_streams.begin(), g->open_streams.end(), s);
+    if (it != g->open_streams.end()) g->open_streams.erase(it);
+    free_stream(s);
     return EXT_OK;
 }
 

@@ -525,6 +525,8 @@ void ext_server_config_init(ext_server_config* c) {
     c->split_pairs = 1;
     c->max_descs = 1u << 16;
     c->poll_us = 0;
+    c->device_reserve_bytes = 1ull << 30;
+    c->rings_bytes_cap = 0;
 }
 
 int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_server** out) {
@@ -683,6 +685,32 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
     c.slice_items = slice_items;
     c.R = s->cfg.ring_blocks ? s->cfg.ring_blocks
                              : std::max<uint64_t>(128, s->cfg.ring_bytes / nb);
+    // admission by free device memory: the two rings must fit in what the
+    // device has free less the reserve, and under the cap on all rings
+    const uint64_t need = 2 * c.R * nb;
+    if (hipSetDevice(s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        c = Channel{};
+        return EXT_EDEVICE;
+    }
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            c = Channel{};
+            return EXT_EDEVICE;
+        }
+        s->stats.free_bytes = free_b;
+        const bool over_free = (uint64_t)free_b < s->cfg.device_reserve_bytes ||
+                               need > (uint64_t)free_b - s->cfg.device_reserve_bytes;
+        const bool over_cap = s->cfg.rings_bytes_cap &&
+                              s->stats.rings_bytes + need > s->cfg.rings_bytes_cap;
+        if (over_free || over_cap) {
+            s->stats.eagain_mem += 1;
+            c = Channel{};
+            return EXT_EAGAIN;
+        }
+    }
     try {
         c.out_ring.resize(c.R * qb);
         c.ready_ns.resize(c.R);
@@ -698,6 +726,7 @@ int ext_server_open(ext_server* s, uint64_t n_bits, uint32_t m_bits, uint32_t* c
         return EXT_ENOMEM;
     }
     c.open = true;
+    s->stats.rings_bytes += need;
     s->table_version += 1;
     *channel = ci;
     return EXT_OK;
@@ -847,6 +876,7 @@ int ext_server_close(ext_server* s, uint32_t channel, uint64_t* dropped_bits) {
     (void)hipFree(c.ring_x);
     (void)hipFree(c.ring_y);
     c.ring_x = c.ring_y = nullptr;
+    s->stats.rings_bytes -= 2 * c.R * c.nb;
     return EXT_OK;
 }
 

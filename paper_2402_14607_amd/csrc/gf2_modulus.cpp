@@ -14,7 +14,9 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -49,44 +51,49 @@ struct SparseModulus {
 };
 
 // Fold the part of `a` of degree >= m down with t^m = sum_{e in low} t^e,
-// 64 coefficients at a time from the top.  Requires every low exponent
-// <= m - 64 or a final bit-level pass handles the rest.
-void reduce(Poly& a, const SparseModulus& P) {
+// whole words at a time: H = a >> m is cleared from `a` and H * t^e added
+// for every low exponent e; repeated while the sum still reaches degree m
+// (twice for moduli whose taps lie far below m).
+void reduce(Poly& a, const SparseModulus& P, Poly& hi) {
     const uint32_t m = P.m;
+    const size_t n = a.size();
+    const uint32_t ws = m >> 6, bs = m & 63;
     for (;;) {
         const int d = degree(a);
         if (d < (int)m) return;
-        // take the top chunk [lo_bit, d] with at most 64 bits and lo_bit >= m
-        const uint32_t lo_bit = std::max<int>((int)m, d - 63);
-        const uint32_t width = (uint32_t)d - lo_bit + 1;
-        // extract chunk
-        const uint32_t w0 = lo_bit >> 6, b0 = lo_bit & 63;
-        uint64_t chunk = a[w0] >> b0;
-        if (b0 && w0 + 1 < a.size()) chunk |= a[w0 + 1] << (64 - b0);
-        if (width < 64) chunk &= (1ull << width) - 1;
-        // clear it
-        for (uint32_t k = 0; k < width; ++k) {
-            const uint32_t bit = lo_bit + k;
-            a[bit >> 6] &= ~(1ull << (bit & 63));
+        const size_t hw = (size_t)(d - (int)m) / 64 + 1;  // words of H
+        for (size_t i = 0; i < hw; ++i) {
+            const size_t s = ws + i;
+            uint64_t v = a[s] >> bs;
+            if (bs && s + 1 < n) v |= a[s + 1] << (64 - bs);
+            hi[i] = v;
         }
-        // add chunk * t^(lo_bit - m) * (sum t^e)
+        // clear bits >= m
+        if (bs) a[ws] &= (1ull << bs) - 1;
+        for (size_t i = ws + (bs ? 1 : 0); i < n; ++i) a[i] = 0;
         for (uint32_t e : P.low) {
-            const uint32_t pos = lo_bit - m + e;
-            const uint32_t pw = pos >> 6, pb = pos & 63;
-            a[pw] ^= chunk << pb;
-            if (pb && pw + 1 < a.size()) a[pw + 1] ^= chunk >> (64 - pb);
+            const uint32_t ew = e >> 6, eb = e & 63;
+            if (eb == 0) {
+                for (size_t i = 0; i < hw; ++i) a[ew + i] ^= hi[i];
+            } else {
+                for (size_t i = 0; i < hw; ++i) {
+                    a[ew + i] ^= hi[i] << eb;
+                    a[ew + i + 1] ^= hi[i] >> (64 - eb);
+                }
+            }
         }
     }
 }
 
-void square_mod(Poly& a, const SparseModulus& P, Poly& tmp) {
+// a <- a^2 mod P (deg a < m); tmp and hi hold 2 * words(m) + 2 words.
+void square_mod(Poly& a, const SparseModulus& P, Poly& tmp, Poly& hi) {
     const size_t nw = (P.m + 63) / 64;
-    std::fill(tmp.begin(), tmp.end(), 0);
     for (size_t i = 0; i < nw; ++i) {
         tmp[2 * i] = interleave_zeros((uint32_t)a[i]);
         tmp[2 * i + 1] = interleave_zeros((uint32_t)(a[i] >> 32));
     }
-    reduce(tmp, P);
+    std::fill(tmp.begin() + 2 * nw, tmp.end(), 0);
+    reduce(tmp, P, hi);
     std::copy(tmp.begin(), tmp.begin() + nw, a.begin());
 }
 
@@ -138,29 +145,35 @@ std::vector<uint32_t> prime_factors(uint32_t m) {
     return r;
 }
 
+// Rabin's test along one squaring chain t, t^2, t^4, ... mod P: the values
+// t^(2^(m/r)) for the primes r | m are kept on the way to t^(2^m), and their
+// gcds with P are taken only when t^(2^m) = t holds (nearly every reducible
+// candidate fails that first).
 bool rabin(const SparseModulus& P) {
     const uint32_t m = P.m;
     if (m == 1) return true;
     const size_t nw = (m + 63) / 64 + 1;
-    Poly tmp(2 * nw + 2);
+    Poly tmp(2 * nw + 2), hi(2 * nw + 2);
     Poly full(nw, 0);
     full[m >> 6] |= 1ull << (m & 63);
     for (uint32_t e : P.low) full[e >> 6] ^= 1ull << (e & 63);
-    auto t_pow2 = [&](uint32_t k) {
-        Poly h(nw, 0);
-        h[0] = 2;  // t
-        for (uint32_t i = 0; i < k; ++i) square_mod(h, P, tmp);
-        return h;
-    };
-    for (uint32_t r : prime_factors(m)) {
-        Poly h = t_pow2(m / r);
-        h[0] ^= 2;
-        if (degree(h) < 0) return false;
-        if (gcd_degree(h, full) != 0) return false;
+    const std::vector<uint32_t> primes = prime_factors(m);
+    std::vector<Poly> kept(primes.size());
+    Poly h(nw, 0);
+    h[0] = 2;  // t
+    for (uint32_t i = 1; i <= m; ++i) {
+        square_mod(h, P, tmp, hi);
+        for (size_t k = 0; k < primes.size(); ++k)
+            if (i == m / primes[k]) kept[k] = h;
     }
-    Poly h = t_pow2(m);
     h[0] ^= 2;
-    return degree(h) < 0;
+    if (degree(h) >= 0) return false;
+    for (Poly& g : kept) {
+        g[0] ^= 2;  // t^(2^(m/r)) - t
+        if (degree(g) < 0) return false;
+        if (gcd_degree(g, full) != 0) return false;
+    }
+    return true;
 }
 
 // ---- sieve: irreducible polynomials of degree <= 12 and powers of t ------
@@ -233,12 +246,6 @@ bool sieved_out(uint32_t m, const std::vector<uint32_t>& low) {
     return false;
 }
 
-bool check_candidate(uint32_t m, const std::vector<uint32_t>& low) {
-    if (sieved_out(m, low)) return false;
-    SparseModulus P{m, low};
-    return rabin(P);
-}
-
 }  // namespace
 
 bool modulus_is_irreducible(uint32_t m, const uint32_t* taps, uint32_t n_taps) {
@@ -247,23 +254,62 @@ bool modulus_is_irreducible(uint32_t m, const uint32_t* taps, uint32_t n_taps) {
     return rabin(P);
 }
 
-bool search_modulus(uint32_t m, std::vector<uint32_t>* taps) {
-    if (m < 2) return false;
-    if (m % 8 != 0) {
-        for (uint32_t a = 1; 2 * a <= m; ++a)
-            if (check_candidate(m, {a, 0})) {
-                *taps = {a};
+namespace {
+
+// Candidates in the convention's order (trinomials when m % 8 != 0, then
+// pentanomials by a, b, c), sieved serially; the survivors go through
+// Rabin's test in batches on worker threads, and the first irreducible one
+// in order wins.
+bool search_ordered(uint32_t m, std::vector<uint32_t>* taps) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const unsigned nthr = std::max(1u, std::min(hw ? hw : 1u, 16u));
+    std::vector<std::vector<uint32_t>> batch;
+    const size_t batch_cap = 4 * nthr;
+    auto run_batch = [&]() -> bool {
+        std::vector<uint8_t> ok(batch.size(), 0);
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (;;) {
+                const size_t i = next.fetch_add(1);
+                if (i >= batch.size()) return;
+                SparseModulus P{m, batch[i]};
+                ok[i] = rabin(P) ? 1 : 0;
+            }
+        };
+        std::vector<std::thread> th;
+        for (unsigned t = 1; t < nthr && t < batch.size(); ++t) th.emplace_back(work);
+        work();
+        for (auto& t : th) t.join();
+        for (size_t i = 0; i < batch.size(); ++i)
+            if (ok[i]) {
+                taps->assign(batch[i].begin(), batch[i].end() - 1);  // drop the 0
                 return true;
             }
+        batch.clear();
+        return false;
+    };
+    auto offer = [&](std::vector<uint32_t> low) -> bool {
+        if (sieved_out(m, low)) return false;
+        batch.push_back(std::move(low));
+        return batch.size() >= batch_cap && run_batch();
+    };
+    if (m % 8 != 0) {
+        for (uint32_t a = 1; 2 * a <= m; ++a)
+            if (offer({a, 0})) return true;
+        if (!batch.empty() && run_batch()) return true;
     }
     for (uint32_t a = 3; a < m; ++a)
         for (uint32_t b = 2; b < a; ++b)
             for (uint32_t c = 1; c < b; ++c)
-                if (check_candidate(m, {a, b, c, 0})) {
-                    *taps = {a, b, c};
-                    return true;
-                }
-    return false;
+                if (offer({a, b, c, 0})) return true;
+    return !batch.empty() && run_batch();
+}
+
+}  // namespace
+
+bool search_modulus(uint32_t m, std::vector<uint32_t>* taps) {
+    if (m < 2) return false;
+    return search_ordered(m, taps);
 }
 
 // Conventional modulus of degree m: the library's table when it has the

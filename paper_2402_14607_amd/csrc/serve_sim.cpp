@@ -367,6 +367,9 @@ extern "C" int ext_serve_simulate(const ext_sim_config* cfg, ext_sim_result* res
             res->mean_tiles = st.cycles ? (double)st.tiles / st.cycles : 0.0;
             res->mean_stage_us = st.cycles ? st.stage_ns / 1e3 / st.cycles : 0.0;
             res->mean_extract_us = st.cycles ? st.extract_ns / 1e3 / st.cycles : 0.0;
+            res->rings_bytes = st.rings_bytes;
+            res->free_bytes = st.free_bytes;
+            res->eagain_mem = st.eagain_mem;
         }
     }
     if (capture_len)

@@ -120,3 +120,177 @@ def test_growing_limits_and_errors(dev):
         n_e, q1, d, b = bad
         with pytest.raises(binding.ExtError):
             binding.Growing(n_e, q1, d, sample_bits=b)
+
+
+# ---------------------------------------------------------------------------
+# online form: Algorithm 2 on unbounded sources fed in chunks
+# ---------------------------------------------------------------------------
+def oracle_blocks_parallel(x, y, n_e, q1, delta_steps, b, k):
+    """Outputs of blocks 0..k-1, one oracle call per block on host threads."""
+    import concurrent.futures as cf
+    import os
+
+    sched = orc_params.schedule(q1, delta_steps, b, n_e, k)
+
+    def one(item):
+        start, size, q = item
+        lo, hi = start * b // 8, (start + size) * b // 8
+        return oracle.ext_blocks(x[lo:hi], y[lo:hi], q * n_e, q)
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(threads) as pool:
+        return np.concatenate(list(pool.map(one, sched)))
+
+
+def feed(dev, st, x, y, rng, device_memory, chunk_blocks_bytes, poll_cap=1 << 16):
+    """Feed x and y to a growing stream in random chunk sizes (each side its
+    own sequence, sometimes both in one call), polling now and then and on
+    EXT_EAGAIN; returns (concatenated output, EAGAIN count)."""
+    import torch
+
+    if device_memory:
+        xs = torch.from_numpy(x).to(dev)
+        ys = torch.from_numpy(y).to(dev)
+        obuf = torch.empty(poll_cap, dtype=torch.uint8, device=dev)
+    else:
+        xs, ys = x, y
+        obuf = np.empty(poll_cap, dtype=np.uint8)
+    outs, px, py, eagain = [], 0, 0, 0
+
+    def poll(wait=False):
+        while True:
+            n, _ = st.poll(obuf, poll_cap, wait=wait)
+            if not n:
+                return
+            outs.append((obuf[:n].cpu().numpy() if device_memory else obuf[:n]).copy())
+
+    while px < x.size or py < y.size:
+        cap = max(2, chunk_blocks_bytes(st))
+        cx = int(min(x.size - px, rng.integers(1, cap)))
+        cy = int(min(y.size - py, rng.integers(1, cap)))
+        mode = int(rng.integers(0, 3))  # 0: X only, 1: Y only, 2: both in one call
+        if mode == 0 or cy == 0:
+            cy = 0
+        if mode == 1 or cx == 0:
+            cx = 0
+        if cx == 0 and cy == 0:
+            continue
+        rc = st.submit(xs[px:px + cx] if cx else None, cx, ys[py:py + cy] if cy else None, cy)
+        if rc == binding.EXT_EAGAIN:
+            eagain += 1
+            poll(wait=True)
+            continue
+        px += cx
+        py += cy
+        if rng.integers(0, 4) == 0:
+            poll()
+    poll(wait=True)
+    return (np.concatenate(outs) if outs else np.zeros(0, np.uint8)), eagain
+
+
+GROWING_STREAMS = [  # n_e, q1, Delta, b, blocks -- the first runs q_l past 4096 (to 5184)
+    (3, 80, 1, 16, 320),
+    (71, 80, 1, 16, 40),
+    (4, 64, 2, 8, 120),
+]
+
+
+@pytest.mark.parametrize("n_e,q1,delta_steps,b,k", GROWING_STREAMS, ids=lambda v: str(v))
+def test_growing_stream_random_chunks(dev, n_e, q1, delta_steps, b, k):
+    sched = orc_params.schedule(q1, delta_steps, b, n_e, k)
+    total = sum(size for _, size, _ in sched) * b // 8
+    next_block = (q1 + k * delta_steps * b) * n_e // 8
+    tail = next_block // 3  # part of block k: pending at the end, dropped at close
+    rng = np.random.Generator(np.random.PCG64(4000 + q1 + n_e + k))
+    x = rng.integers(0, 256, total + tail, dtype=np.uint8)
+    y = rng.integers(0, 256, total + tail, dtype=np.uint8)
+    say("growing stream n_e=%d q1=%d delta=%d b=%d: %d blocks (q up to %d), %d bytes per source"
+        % (n_e, q1, delta_steps, b, k, sched[-1][2], total + tail))
+    want = oracle_blocks_parallel(x, y, n_e, q1, delta_steps, b, k)
+    m_k = orc_params.output_bits(q1, delta_steps, b, k)
+    assert want.size * 8 == m_k == binding.output_bits(q1, delta_steps, b, k)
+    for device_memory in (False, True):
+        say("  device_memory=%s" % device_memory)
+        with binding.Growing(n_e, q1, delta_steps, sample_bits=b,
+                             device_memory=device_memory) as g:
+            st = g.open_stream()
+
+            def chunk_cap(s):
+                _, q, _ = s.state()
+                return 3 * q * n_e // 8  # up to three blocks of the current size
+
+            got, _ = feed(dev, st, x, y, rng, device_memory, chunk_cap)
+            l, q, consumed = st.state()
+            dropped = st.close()
+        assert l == k and q == q1 + k * delta_steps * b and consumed == total
+        assert dropped == 8 * tail
+        assert got.size * 8 == m_k
+        assert np.array_equal(got, want)
+
+
+def test_growing_stream_delta_zero_is_algorithm_one(dev):
+    """Delta = 0 in small chunks: the plain form's bytes (Algorithm 1)."""
+    import torch
+
+    n_e, q, pairs = 71, 80, 300
+    rng = np.random.Generator(np.random.PCG64(515))
+    x = rng.integers(0, 256, pairs * n_e * q // 8, dtype=np.uint8)
+    y = rng.integers(0, 256, pairs * n_e * q // 8, dtype=np.uint8)
+    with binding.Growing(n_e, q, 0, sample_bits=16, device_memory=False) as g:
+        st = g.open_stream()
+        got, _ = feed(dev, st, x, y, rng, False, lambda s: 700)
+        assert st.close() == 0
+    out = torch.zeros(pairs * q // 8, dtype=torch.uint8, device=dev)
+    with binding.Extractor(n_e * q, q, device_memory=True,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        ex.extract(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev), out, pairs)
+        ex.sync()
+    assert np.array_equal(got, out.cpu().numpy())
+
+
+def test_growing_stream_admission(dev):
+    """A small device_bytes_cap: one side far ahead is refused with EXT_EAGAIN
+    and nothing consumed; the stream still produces every block."""
+    n_e, q1, d, b, k = 4, 64, 1, 8, 60
+    sched = orc_params.schedule(q1, d, b, n_e, k)
+    total = sum(size for _, size, _ in sched) * b // 8
+    rng = np.random.Generator(np.random.PCG64(616))
+    x = rng.integers(0, 256, total, dtype=np.uint8)
+    y = rng.integers(0, 256, total, dtype=np.uint8)
+    want = oracle_blocks_parallel(x, y, n_e, q1, d, b, k)
+    with binding.Growing(n_e, q1, d, sample_bits=b, device_memory=False,
+                         device_bytes_cap=4096) as g:
+        st = g.open_stream()
+        # all of X at once is more than the cap allows (and than two blocks)
+        assert st.submit(x, x.size, None, 0) == binding.EXT_EAGAIN
+        assert st.state() == (0, q1, 0)
+        got, eagain = feed(dev, st, x, y, rng, False, lambda s: 5000)
+        assert st.close() == 0
+    assert np.array_equal(got, want)
+
+
+def test_growing_stream_poll_whole_blocks_and_errors(dev):
+    """poll returns whole blocks only (a buffer smaller than the next block's
+    output gets nothing); a stream closed before any block drops its bytes."""
+    n_e, q1, d, b = 2, 256, 1, 32
+    rng = np.random.Generator(np.random.PCG64(717))
+    sched = orc_params.schedule(q1, d, b, n_e, 5)
+    total = sum(size for _, size, _ in sched) * b // 8
+    x = rng.integers(0, 256, total, dtype=np.uint8)
+    y = rng.integers(0, 256, total, dtype=np.uint8)
+    want = oracle_blocks_parallel(x, y, n_e, q1, d, b, 5)
+    with binding.Growing(n_e, q1, d, sample_bits=b, device_memory=False) as g:
+        st = g.open_stream()
+        assert st.submit(x, x.size, y, y.size) == binding.EXT_OK
+        small = np.zeros(q1 // 8 - 1, dtype=np.uint8)
+        n, done = st.poll(small, small.size, wait=True)
+        assert n == 0 and done == 0
+        buf = np.zeros(want.size, dtype=np.uint8)
+        n, done = st.poll(buf, buf.size, wait=True)
+        assert n == want.size and done == 5
+        assert np.array_equal(buf, want)
+        assert st.close() == 0
+        st2 = g.open_stream()
+        assert st2.submit(x[:100], 100, y[:40], 40) == binding.EXT_OK
+        assert st2.state() == (0, q1, 0)
+        assert st2.close() == 800

@@ -276,3 +276,43 @@ def test_close_with_pending_partial_block_while_others_stream(dev):
     for c, w in zip(chans, live):
         out = np.concatenate(got[c] + [rest[c]])
         assert np.array_equal(out, plain(w.n_bits, w.m_bits, w.x, w.y))
+
+
+def test_admission_by_free_device_memory(dev):
+    """Channels are admitted by device memory: with a reserve above what the
+    device has free every open is refused with EXT_EAGAIN and nothing is
+    allocated; under a cap on all rings the fourth channel waits until one
+    closes, and the admitted channels' outputs equal the plain form's."""
+    import torch
+
+    free, total = torch.cuda.mem_get_info()
+    say("device memory: %.1f GiB free of %.1f GiB" % (free / 2**30, total / 2**30))
+    with binding.Server(config=binding.server_config(device_reserve_bytes=total + 1)) as srv:
+        for n, m in ((2048, 512), (65536, 16384)):
+            with pytest.raises(binding.ExtError) as e:
+                srv.open(n, m)
+            assert e.value.code == binding.EXT_EAGAIN
+        st = srv.stats()
+        assert st["eagain_mem"] == 2 and st["rings_bytes"] == 0
+        assert 0 < st["free_bytes"] <= total
+    ring = 2 * 128 * (2048 // 8)  # two rings of 128 blocks of 256 bytes
+    cfg = binding.server_config(ring_blocks=128, rings_bytes_cap=3 * ring)
+    w = inputs.plain_workload(2048, 512, 100, 990, 991)
+    with binding.Server(config=cfg) as srv:
+        chans = [srv.open(2048, 512) for _ in range(3)]
+        with pytest.raises(binding.ExtError) as e:
+            srv.open(2048, 512)
+        assert e.value.code == binding.EXT_EAGAIN
+        st = srv.stats()
+        assert st["eagain_mem"] == 1 and st["rings_bytes"] == 3 * ring
+        assert srv.close_channel(chans[1]) == 0
+        assert srv.stats()["rings_bytes"] == 2 * ring
+        c = srv.open(2048, 512)  # admitted now
+        chans = [chans[0], chans[2], c]
+        assert srv.stats()["rings_bytes"] == 3 * ring
+        for ch in chans:
+            assert srv.submit(ch, w.x, w.y) == binding.EXT_OK
+        got = drain(srv, chans, {ch: 100 * 64 for ch in chans})
+    want = plain(2048, 512, w.x, w.y)
+    for ch in chans:
+        assert np.array_equal(got[ch], want)

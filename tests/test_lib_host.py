@@ -43,11 +43,17 @@ def test_default_modulus_every_byte_multiple_degree():
 
 
 def test_default_modulus_matches_oracle_table():
+    """Every degree the oracle's table holds that the library's built-in table
+    holds too (the multiples of 8 up to 8192, among them Algorithm 2's
+    degrees 80, 96, ..., 5184 at b = 16, and 16384), found by two independent
+    searches; then the library's run-time search, for degrees outside its
+    table, against the oracle's."""
     table = oracle._read_table()
-    for m in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384):
+    common = [m for m in table if (m % 8 == 0 and m <= 8192) or m == 16384]
+    assert len(common) > 300 and max(m for m in common if m <= 8192) >= 5184
+    for m in common:
         assert binding.default_modulus(m) == table[m], m
-    # run-time search for degrees outside the built-in table
-    for m in (32, 96, 160, 192, 224, 320, 384, 768, 1536):
+    for m in (3, 5, 17, 33, 41, 57, 63):
         assert binding.default_modulus(m) == table[m], m
 
 
