@@ -31,7 +31,22 @@
 
 using qext::BatchStream;
 using qext::BatchTile;
+using qext::CombineJob;
 using qext::ExtShape;
+
+namespace {
+
+// Launch plan of one degree: the whole-block shape when one work-group can
+// hold a block, and the slice geometry (elements per slice) used for blocks
+// too large for that, or large enough that slicing fills more of the GPU.
+struct DegreePlan {
+    ExtShape whole{};
+    bool whole_ok = false;
+    ExtShape sliced{};  // the padded element geometry of the degree, n_e of the block
+    uint32_t slice_elems = 0;  // 0: the degree cannot be sliced
+};
+
+}  // namespace
 
 struct ext_growing {
     uint32_t n_e = 0, q1 = 0, delta_steps = 0, b = 8;
@@ -39,12 +54,16 @@ struct ext_growing {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    std::map<uint32_t, ExtShape> shapes;  // plan per degree
-    // device scratch, grown on demand
+    std::map<uint32_t, DegreePlan> plans;  // plan per degree
+    // device scratch of the prefix call, grown on demand
     BatchStream* d_streams = nullptr;
     BatchTile* d_tiles = nullptr;
+    CombineJob* d_jobs = nullptr;
     uint32_t* d_heads = nullptr;
-    uint64_t cap_blocks = 0;
+    uint64_t cap_blocks = 0, cap_tiles = 0, cap_jobs = 0;
+    // partial sums of sliced blocks (every call of the handle, in stream order)
+    uint32_t* d_part = nullptr;
+    uint64_t cap_part = 0;
     uint8_t *dx = nullptr, *dy = nullptr, *dout = nullptr;  // host-memory mode
     uint64_t cap_in = 0, cap_out = 0;
     // the launches of one call (one per base size) are independent: they run
@@ -82,15 +101,20 @@ void release_lanes(ext_growing* g) {
 void free_scratch(ext_growing* g) {
     (void)hipFree(g->d_streams);
     (void)hipFree(g->d_tiles);
+    (void)hipFree(g->d_jobs);
     (void)hipFree(g->d_heads);
+    (void)hipFree(g->d_part);
     (void)hipFree(g->dx);
     (void)hipFree(g->dy);
     (void)hipFree(g->dout);
     g->d_streams = nullptr;
     g->d_tiles = nullptr;
+    g->d_jobs = nullptr;
     g->d_heads = nullptr;
+    g->d_part = nullptr;
     g->dx = g->dy = g->dout = nullptr;
-    g->cap_blocks = g->cap_in = g->cap_out = 0;
+    g->cap_blocks = g->cap_tiles = g->cap_jobs = g->cap_part = 0;
+    g->cap_in = g->cap_out = 0;
 }
 
 // Block geometry of the first k blocks: q_l, input offset and output offset.
@@ -113,37 +137,110 @@ Geo geometry(const ext_growing* g, uint64_t n_bytes, uint64_t max_blocks) {
     return r;
 }
 
-int plan_for(ext_growing* g, uint32_t q, ExtShape* out) {
-    auto it = g->shapes.find(q);
-    if (it != g->shapes.end()) {
+// Most LDS words a slice may take (its two staged element ranges and the
+// partial sum), and slot words per lane of the padded staging.
+constexpr uint32_t kSliceLdsWords = 12288;
+
+int plan_for(ext_growing* g, uint32_t q, DegreePlan* out) {
+    auto it = g->plans.find(q);
+    if (it != g->plans.end()) {
         *out = it->second;
         return EXT_OK;
     }
     std::vector<uint32_t> taps;
     if (!qext::default_modulus(q, &taps)) return EXT_ENOTSUP;
     qext::PlanKnobs knobs{g->params.base_bits / 32, 0, 0, g->params.threads, 1};
-    ExtShape s;
-    if (!qext::plan_shape(q, g->n_e, taps.data(), (uint32_t)taps.size(), knobs, &s))
-        return EXT_ENOTSUP;
-    g->shapes[q] = s;
-    *out = s;
+    DegreePlan d;
+    d.whole_ok = qext::plan_shape(q, g->n_e, taps.data(), (uint32_t)taps.size(), knobs, &d.whole);
+    // slices: the degree's geometry for one element, then the block's n_e
+    ExtShape u;
+    if (qext::plan_shape(q, 1, taps.data(), (uint32_t)taps.size(), knobs, &u)) {
+        u.n_e = g->n_e;
+        u.nw = u.qw * g->n_e;
+        u.nbytes = (uint32_t)((uint64_t)g->n_e * q / 8);
+        // one round of items per slice, within the LDS and staging budgets
+        uint32_t es = std::max<uint32_t>(1u, u.threads / u.np);
+        const uint32_t by_lds =
+            (2 * u.qw + 2 * qext::kPadSlack) < kSliceLdsWords
+                ? (kSliceLdsWords - 2 * u.qw - 2 * qext::kPadSlack) / (2 * u.qw)
+                : 0u;
+        const uint32_t by_regs = qext::kPadRegs * u.threads / u.qw;
+        es = std::min({es, by_lds, by_regs, g->n_e});
+        if (es > 0) {
+            const uint32_t parts = (g->n_e + es - 1) / es;
+            d.slice_elems = (g->n_e + parts - 1) / parts;  // even slices
+            d.sliced = u;
+        }
+    }
+    if (!d.whole_ok && !d.slice_elems) return EXT_ENOTSUP;
+    g->plans[q] = d;
+    *out = d;
     return EXT_OK;
 }
 
-int grow(ext_growing* g, uint64_t k, uint64_t in_bytes, uint64_t out_bytes) {
+// Whether a block of degree plan d is computed in slices: when no single
+// work-group can hold it, or when its items fill more than two rounds of a
+// work-group's lanes (slices then spread it over the GPU).
+bool use_slices(const DegreePlan& d, bool allow) {
+    if (!d.whole_ok) return true;
+    if (!allow || !d.slice_elems) return false;
+    return (uint64_t)d.whole.np * d.whole.n_e > 2ull * d.whole.threads;
+}
+
+// Device tables of the prefix call, grown to at least the given counts.
+int grow_tables(ext_growing* g, uint64_t streams, uint64_t tiles, uint64_t jobs) {
     bool ok = true;
-    if (k > g->cap_blocks) {
+    if (streams > g->cap_blocks) {
         (void)hipFree(g->d_streams);
-        (void)hipFree(g->d_tiles);
         g->d_streams = nullptr;
+        ok = hipMalloc((void**)&g->d_streams, streams * sizeof(BatchStream)) == hipSuccess;
+        g->cap_blocks = ok ? streams : 0;
+    }
+    if (ok && tiles > g->cap_tiles) {
+        (void)hipFree(g->d_tiles);
         g->d_tiles = nullptr;
-        ok = hipMalloc((void**)&g->d_streams, k * sizeof(BatchStream)) == hipSuccess &&
-             hipMalloc((void**)&g->d_tiles, k * sizeof(BatchTile)) == hipSuccess;
-        g->cap_blocks = ok ? k : 0;
+        ok = hipMalloc((void**)&g->d_tiles, tiles * sizeof(BatchTile)) == hipSuccess;
+        g->cap_tiles = ok ? tiles : 0;
+    }
+    if (ok && jobs > g->cap_jobs) {
+        (void)hipFree(g->d_jobs);
+        g->d_jobs = nullptr;
+        ok = hipMalloc((void**)&g->d_jobs, jobs * sizeof(CombineJob)) == hipSuccess;
+        g->cap_jobs = ok ? jobs : 0;
     }
     if (ok && !g->d_heads)
         ok = hipMalloc((void**)&g->d_heads, kMaxGroups * sizeof(uint32_t)) == hipSuccess;
-    if (ok && g->params.mem_kind == EXT_MEM_HOST && in_bytes > g->cap_in) {
+    if (!ok) {
+        (void)hipGetLastError();
+        return EXT_ENOMEM;
+    }
+    return EXT_OK;
+}
+
+// The handle's partial-sum buffer, grown to at least `words` (after the
+// queued work that may use the old one).
+int grow_part(ext_growing* g, uint64_t words) {
+    if (words <= g->cap_part) return EXT_OK;
+    if (hipStreamSynchronize(g->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return g->sticky = EXT_EDEVICE;
+    }
+    const uint64_t want = std::max<uint64_t>(words, 2 * g->cap_part);
+    (void)hipFree(g->d_part);
+    g->d_part = nullptr;
+    g->cap_part = 0;
+    if (hipMalloc((void**)&g->d_part, want * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return EXT_ENOMEM;
+    }
+    g->cap_part = want;
+    return EXT_OK;
+}
+
+// Input and output staging of the prefix call in host-memory mode.
+int grow_io(ext_growing* g, uint64_t in_bytes, uint64_t out_bytes) {
+    bool ok = true;
+    if (g->params.mem_kind == EXT_MEM_HOST && in_bytes > g->cap_in) {
         (void)hipFree(g->dx);
         (void)hipFree(g->dy);
         g->dx = g->dy = nullptr;
@@ -159,7 +256,6 @@ int grow(ext_growing* g, uint64_t k, uint64_t in_bytes, uint64_t out_bytes) {
     }
     if (!ok) {
         (void)hipGetLastError();
-        free_scratch(g);
         return EXT_ENOMEM;
     }
     return EXT_OK;
@@ -241,6 +337,7 @@ namespace {
 struct Tables {
     BatchStream* streams;
     BatchTile* tiles;
+    CombineJob* jobs;
     uint32_t* heads;
 };
 
@@ -251,53 +348,86 @@ struct LaunchPlan {
     uint64_t cost;  // sum of its tiles' costs
 };
 
-// A planned call: one one-pair stream and one tile per block, grouped into
-// launches.
+// A planned call: one one-pair stream per block, one tile per whole block or
+// one per slice of a sliced block, grouped into launches; one combine job per
+// sliced block, whose parts take part_words words.
 struct Planned {
     std::vector<BatchStream> streams;
     std::vector<BatchTile> tiles;
     std::vector<LaunchPlan> launches;
+    std::vector<CombineJob> jobs;
+    uint64_t part_words = 0;
+    uint32_t combine_lds = 0;
 };
 
 // Plan k consecutive blocks of degrees q0, q0 + step, ... whose inputs start
-// at xs / ys and whose outputs start at os (device addresses).  May throw
-// std::bad_alloc.
+// at xs / ys and whose outputs start at os (device addresses); allow_slices
+// false plans whole blocks only (EXT_ENOTSUP for a block one work-group
+// cannot hold).  May throw std::bad_alloc.
 int plan_blocks(ext_growing* g, uint64_t q0, uint64_t k, const uint8_t* xs, const uint8_t* ys,
-                uint8_t* os, Planned* p) {
+                uint8_t* os, bool allow_slices, Planned* p) {
     p->streams.clear();
     p->tiles.clear();
     p->launches.clear();
+    p->jobs.clear();
+    p->part_words = 0;
+    p->combine_lds = 0;
     p->streams.reserve(k);
-    // launches: (base size, work-group size) -> tile list with cost
-    std::map<std::pair<uint32_t, uint32_t>, std::vector<std::pair<uint64_t, uint32_t>>> groups;
+    // launches: (base size, work-group size) -> tiles with cost
+    struct Group {
+        std::vector<std::pair<uint64_t, BatchTile>> tiles;
+        uint32_t lds = 0;
+    };
+    std::map<std::pair<uint32_t, uint32_t>, Group> groups;
     uint64_t q = q0, in_off = 0, out_off = 0;
     for (uint64_t l = 0; l < k; ++l) {
         if (q > 0xffffffffull) return EXT_ENOTSUP;
-        ExtShape s;
-        const int rc = plan_for(g, (uint32_t)q, &s);
+        DegreePlan d;
+        const int rc = plan_for(g, (uint32_t)q, &d);
         if (rc) return rc;
+        const bool sliced = use_slices(d, allow_slices);
+        if (sliced && (!allow_slices || !d.slice_elems)) return EXT_ENOTSUP;
+        const ExtShape& s = sliced ? d.sliced : d.whole;
         p->streams.push_back(BatchStream{xs + in_off, ys + in_off, os + out_off, 1, s});
-        const uint64_t cost = ((uint64_t)s.np * s.groups + s.threads - 1) / s.threads * s.epg;
-        groups[{s.bw, s.threads}].push_back({cost, (uint32_t)l});
+        Group& gr = groups[{s.bw, s.threads}];
+        if (!sliced) {
+            const uint64_t cost = ((uint64_t)s.np * s.groups + s.threads - 1) / s.threads * s.epg;
+            gr.tiles.push_back({cost, BatchTile{(uint32_t)l, 1, 0, 0, 0, 0}});
+            gr.lds = std::max(gr.lds, s.lds_words * 4);
+        } else {
+            const uint32_t es = d.slice_elems, cw = 2 * s.qw;
+            const uint32_t n_parts = (s.n_e + es - 1) / es;
+            for (uint32_t e0 = 0, part = 0; e0 < s.n_e; e0 += es, ++part) {
+                const uint32_t ne = std::min(es, s.n_e - e0);
+                const uint64_t cost = ((uint64_t)s.np * ne + s.threads - 1) / s.threads;
+                gr.tiles.push_back({cost, BatchTile{(uint32_t)l, 1, 0, p->part_words + part * cw,
+                                                    e0, ne}});
+            }
+            gr.lds = std::max(gr.lds, (2 * (es * s.qw + qext::kPadSlack) + cw) * 4);
+            p->jobs.push_back(CombineJob{(uint32_t)l, n_parts, p->part_words, 0});
+            p->part_words += (uint64_t)n_parts * cw;
+            p->combine_lds = std::max(p->combine_lds, (3 * s.qw + s.dn) * 4);
+        }
         in_off += s.nbytes;
         out_off += s.qbytes;
         q += (uint64_t)g->delta_steps * g->b;
     }
     if (groups.size() > kMaxGroups) return EXT_ENOTSUP;
+    if (p->combine_lds > 65536) return EXT_ENOTSUP;
     int cus = 1;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
     for (auto& kv : groups) {
-        auto& v = kv.second;
+        auto& v = kv.second.tiles;
         // longest tiles first, so the queue ends with short ones
         std::stable_sort(v.begin(), v.end(),
                          [](const auto& a, const auto& c) { return a.first > c.first; });
         LaunchPlan ln{kv.first.first, kv.first.second, (uint32_t)p->tiles.size(),
-                      (uint32_t)v.size(), 0, 0, 0};
+                      (uint32_t)v.size(), kv.second.lds, 0, 0};
         for (auto& t : v) {
             ln.cost += t.first;
-            p->tiles.push_back(BatchTile{t.second, 1, 0, 0, 0, 0});
-            ln.lds = std::max(ln.lds, p->streams[t.second].shape.lds_words * 4);
+            p->tiles.push_back(t.second);
         }
+        if (ln.lds > 65536) return EXT_ENOTSUP;
         int occ = 0;
         if (qext::batch_occupancy(ln.bw, ln.threads, true, ln.lds, &occ) != hipSuccess || occ <= 0)
             occ = 1;
@@ -307,13 +437,14 @@ int plan_blocks(ext_growing* g, uint64_t q0, uint64_t k, const uint8_t* xs, cons
     return EXT_OK;
 }
 
-// Queue a planned call on g->stream: its tables (read from streams_src and
-// tiles_src, host memory that must stay untouched until the copies have run)
-// and zeroed queue heads into tab, then the launches on the lanes, forked
-// from and joined back into g->stream.  On a HIP error the work queued so
-// far is waited for and the handle's sticky error set.
+// Queue a planned call on g->stream: its tables (read from host memory at
+// streams_src, tiles_src and jobs_src, which must stay untouched until the
+// copies have run) and zeroed queue heads into tab, then the launches on the
+// lanes, forked from and joined back into g->stream, then the combine step of
+// the sliced blocks on g->stream (their parts in g->d_part).  On a HIP error
+// the work queued so far is waited for and the handle's sticky error set.
 int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void* streams_src,
-                 const void* tiles_src) {
+                 const void* tiles_src, const void* jobs_src) {
     auto device_error = [&]() {
         for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
         (void)hipStreamSynchronize(g->stream);
@@ -327,6 +458,9 @@ int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void
                        hipMemcpyHostToDevice, g->stream) ||
         hipMemcpyAsync(tab.tiles, tiles_src, p.tiles.size() * sizeof(BatchTile),
                        hipMemcpyHostToDevice, g->stream) ||
+        (!p.jobs.empty() &&
+         hipMemcpyAsync(tab.jobs, jobs_src, p.jobs.size() * sizeof(CombineJob),
+                        hipMemcpyHostToDevice, g->stream)) ||
         hipMemcpyAsync(tab.heads, kZeroHeads, p.launches.size() * sizeof(uint32_t),
                        hipMemcpyHostToDevice, g->stream))
         return device_error();
@@ -351,7 +485,7 @@ int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void
         used[lane] = true;
         load[lane] += ln.cost + 1;
         if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams, tab.tiles + ln.off,
-                                       ln.n, tab.heads + i, nullptr, ln.grid, ln.lds,
+                                       ln.n, tab.heads + i, g->d_part, ln.grid, ln.lds,
                                        g->lanes[lane]) != hipSuccess)
             return device_error();
     }
@@ -361,12 +495,20 @@ int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void
             hipStreamWaitEvent(g->stream, g->joins[l], 0) != hipSuccess)
             return device_error();
     }
+    if (!p.jobs.empty()) {
+        int cus = 1;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(p.jobs.size(), (uint64_t)cus * 4);
+        if (qext::launch_combine_padded(tab.streams, tab.jobs, (uint32_t)p.jobs.size(), g->d_part,
+                                        grid, p.combine_lds, g->stream) != hipSuccess)
+            return device_error();
+    }
     return EXT_OK;
 }
 
 // Blocks 0 .. k-1 of x and y into out (ext_growing_extract); the launch
-// tables go to *fixed when given (nothing is allocated then), else to the
-// handle's scratch, grown on demand.
+// tables go to *fixed when given (nothing is allocated then, and every block
+// must fit one work-group), else to the handle's scratch, grown on demand.
 int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_bytes,
                    uint64_t max_blocks, void* out, uint64_t out_cap, uint64_t* n_blocks,
                    const Tables* fixed) {
@@ -379,21 +521,27 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
     if (fixed && r.k > qext::kNoAllocMaxBlocks) return EXT_ENOMEM;
     if (hipSetDevice(g->device) != hipSuccess) return EXT_EDEVICE;
     try {
-        Tables tab;
-        if (fixed) {
-            tab = *fixed;
-        } else {
-            const int rc = grow(g, r.k, r.in_bytes, r.out_bytes);
-            if (rc) return rc;
-            tab = Tables{g->d_streams, g->d_tiles, g->d_heads};
-        }
         const bool host = g->params.mem_kind == EXT_MEM_HOST;
+        if (!fixed) {
+            const int rc = grow_io(g, r.in_bytes, r.out_bytes);
+            if (rc) return rc;
+        }
         const uint8_t* xs = host ? g->dx : (const uint8_t*)x;
         const uint8_t* ys = host ? g->dy : (const uint8_t*)y;
         uint8_t* os = host ? g->dout : (uint8_t*)out;
         Planned p;
-        int rc = plan_blocks(g, g->q1, r.k, xs, ys, os, &p);
+        int rc = plan_blocks(g, g->q1, r.k, xs, ys, os, !fixed, &p);
         if (rc) return rc;
+        Tables tab;
+        if (fixed) {
+            tab = *fixed;
+        } else {
+            rc = grow_tables(g, p.streams.size(), p.tiles.size(), p.jobs.size());
+            if (rc) return rc;
+            rc = grow_part(g, p.part_words);
+            if (rc) return rc;
+            tab = Tables{g->d_streams, g->d_tiles, g->d_jobs, g->d_heads};
+        }
         // from here on work is queued: every exit waits for the stream first,
         // so no copy still reads the caller's or these host buffers
         if (host) {
@@ -404,7 +552,7 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
                 return g->sticky = EXT_EDEVICE;
             }
         }
-        rc = queue_blocks(g, p, tab, p.streams.data(), p.tiles.data());
+        rc = queue_blocks(g, p, tab, p.streams.data(), p.tiles.data(), p.jobs.data());
         if (rc) return rc;
         if (host && hipMemcpyAsync(out, g->dout, r.out_bytes, hipMemcpyDeviceToHost, g->stream)) {
             (void)hipStreamSynchronize(g->stream);
@@ -438,7 +586,7 @@ int ext_growing_extract_noalloc(ext_growing* g, const void* x, const void* y, ui
     uint8_t* base = (uint8_t*)qext::noalloc_scratch(g->device);
     if (!base) return EXT_EDEVICE;  // the per-device lookup at create time failed
     const Tables tab{(BatchStream*)(base + qext::kNoAllocStreamsOff),
-                     (BatchTile*)(base + qext::kNoAllocTilesOff),
+                     (BatchTile*)(base + qext::kNoAllocTilesOff), nullptr,
                      (uint32_t*)(base + qext::kNoAllocHeadsOff)};
     return extract_blocks(g, x, y, n_bytes, max_blocks, out, out_cap, n_blocks, &tab);
 }
@@ -462,9 +610,11 @@ int ext_growing_destroy(ext_growing* g) {
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr uint64_t kMaxLaunchBlocks = 1024;  // blocks per queued call (table size)
-constexpr size_t kTableBytes = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream)) +
-                               qext::round256(kMaxLaunchBlocks * sizeof(BatchTile));
+constexpr uint64_t kMaxLaunchBlocks = 1024;  // blocks per queued call
+constexpr uint64_t kMaxLaunchTiles = 16384;  // tiles per queued call (slices count each)
+constexpr size_t kTilesOff = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream));
+constexpr size_t kJobsOff = kTilesOff + qext::round256(kMaxLaunchTiles * sizeof(BatchTile));
+constexpr size_t kTableBytes = kJobsOff + qext::round256(kMaxLaunchBlocks * sizeof(CombineJob));
 
 // One queued call of the online form: k blocks from block0 (degree q0), their
 // outputs at monotonic ring position opos.
@@ -513,6 +663,13 @@ struct ext_growing_stream {
 namespace {
 
 uint64_t block_bytes(const ext_growing_stream* s, uint64_t q) { return q * s->g->n_e / 8; }
+
+// Blocks per queued call: a block has at most n_e slices, so the call's tiles
+// stay within kMaxLaunchTiles.
+uint64_t call_blocks(const ext_growing_stream* s) {
+    return std::max<uint64_t>(1, std::min<uint64_t>(kMaxLaunchBlocks,
+                                                    kMaxLaunchTiles / s->g->n_e));
+}
 
 // Admission limit on the pending bytes of one side: the cap, bounded so that
 // their outputs (at most 1/n_e of them) fit in half the output ring, but
@@ -564,7 +721,7 @@ void complete_blocks(const ext_growing_stream* s, uint64_t avail, uint64_t max_k
 }
 
 // The sequence of queued calls that k blocks from degree q0 make (at most
-// kMaxLaunchBlocks each), placed in the output ring from owrite: false if
+// call_blocks each), placed in the output ring from owrite: false if
 // they do not fit beside the unreturned outputs.  sizes receives (k, bytes)
 // per call and *end the ring position after the last.
 bool ring_fit(const ext_growing_stream* s, uint64_t q0, uint64_t k,
@@ -572,7 +729,7 @@ bool ring_fit(const ext_growing_stream* s, uint64_t q0, uint64_t k,
     uint64_t pos = s->owrite, q = q0;
     sizes->clear();
     while (k) {
-        const uint64_t n = std::min(k, kMaxLaunchBlocks);
+        const uint64_t n = std::min(k, call_blocks(s));
         uint64_t ob = 0;
         for (uint64_t j = 0; j < n; ++j, q += s->step) ob += q / 8;
         if (ob > s->ocap) return false;
@@ -689,7 +846,7 @@ int append(ext_growing_stream* s, const void* x, uint64_t x_len, const void* y, 
 }
 
 // Launch every block the pending bytes complete, in calls of at most
-// kMaxLaunchBlocks blocks placed as ring_fit placed them.
+// call_blocks blocks placed as ring_fit placed them.
 int launch_ready(ext_growing_stream* s) {
     ext_growing* g = s->g;
     uint64_t k, ib, ob;
@@ -705,17 +862,21 @@ int launch_ready(ext_growing_stream* s) {
         if (off + bytes > s->ocap) pos += s->ocap - off;
         const uint8_t* xp = s->xbuf[s->xcur] + s->xhead;
         const uint8_t* yp = s->ybuf[s->ycur] + s->yhead;
-        int rc = plan_blocks(g, s->next_q, n, xp, yp, s->oring + pos % s->ocap, &s->plan);
+        int rc = plan_blocks(g, s->next_q, n, xp, yp, s->oring + pos % s->ocap, true, &s->plan);
+        if (rc) return rc;
+        if (s->plan.tiles.size() > kMaxLaunchTiles) return EXT_ENOTSUP;
+        rc = grow_part(g, s->plan.part_words);
         if (rc) return rc;
         // the pinned table set of the call before last is free once its copy ran
         const int slot = s->ptab_next;
         if (hipEventSynchronize(s->ptab_free[slot]) != hipSuccess) return sfail(s);
         uint8_t* pt = s->ptab + slot * kTableBytes;
-        const size_t tiles_off = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream));
         memcpy(pt, s->plan.streams.data(), s->plan.streams.size() * sizeof(BatchStream));
-        memcpy(pt + tiles_off, s->plan.tiles.data(), s->plan.tiles.size() * sizeof(BatchTile));
-        const Tables tab{(BatchStream*)s->dtab, (BatchTile*)(s->dtab + tiles_off), s->dheads};
-        rc = queue_blocks(g, s->plan, tab, pt, pt + tiles_off);
+        memcpy(pt + kTilesOff, s->plan.tiles.data(), s->plan.tiles.size() * sizeof(BatchTile));
+        memcpy(pt + kJobsOff, s->plan.jobs.data(), s->plan.jobs.size() * sizeof(CombineJob));
+        const Tables tab{(BatchStream*)s->dtab, (BatchTile*)(s->dtab + kTilesOff),
+                         (CombineJob*)(s->dtab + kJobsOff), s->dheads};
+        rc = queue_blocks(g, s->plan, tab, pt, pt + kTilesOff, pt + kJobsOff);
         if (rc) return rc;
         GLaunch L{s->next_block, n, s->next_q, pos, bytes};
         if (hipEventRecord(s->ptab_free[slot], g->stream) != hipSuccess ||
@@ -856,9 +1017,9 @@ int ext_growing_submit(ext_growing_stream* s, const void* x, size_t x_len, const
         complete_blocks(s, std::min(xl + x_len, yl + y_len), ~0ull, &k, &ib, &ob);
         uint64_t q = s->next_q;
         for (uint64_t j = 0; j < k; ++j, q += s->step) {
-            ExtShape sh;
+            DegreePlan d;
             if (q > 0xffffffffull) return EXT_ENOTSUP;
-            rc = plan_for(s->g, (uint32_t)q, &sh);
+            rc = plan_for(s->g, (uint32_t)q, &d);
             if (rc) return rc;
         }
         std::vector<std::pair<uint64_t, uint64_t>> sizes;

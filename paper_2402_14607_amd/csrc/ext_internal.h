@@ -69,9 +69,10 @@ struct BatchStream {
 // One work-group's worth of a batch: npw consecutive pairs of a stream,
 // whose blocks start at pair slot in_pair0 of the stream's x and y, and
 // whose outputs go to byte out_off of the stream's out.  When n_items is
-// nonzero the tile is one slice of the single pair in_pair0: its items
-// [item0, item0 + n_items) in element-major order, whose partial unreduced
-// sum goes to word out_off of the launch's part buffer instead.
+// nonzero the tile is one slice of the single pair in_pair0 -- its items
+// [item0, item0 + n_items) in element-major order, or for a padded shape its
+// elements [item0, item0 + n_items) -- whose partial unreduced sum goes to
+// word out_off of the launch's part buffer instead.
 struct BatchTile {
     uint32_t stream;
     uint32_t npw;
@@ -83,7 +84,8 @@ struct BatchTile {
 
 // One sliced pair to finish: XOR n_parts consecutive parts (2qw words each)
 // starting at word part_word0 of the part buffer, reduce, and store the
-// output at byte out_byte0 (a multiple of 4) of the stream's out.
+// output at byte out_byte0 of the stream's out (a multiple of 4 unless the
+// shape is padded).
 struct CombineJob {
     uint32_t stream;
     uint32_t n_parts;
@@ -144,6 +146,14 @@ hipError_t launch_batch_noreset(uint32_t bw, uint32_t threads, bool padded,
 hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, uint32_t n_jobs,
                           const uint32_t* part, uint32_t grid, uint32_t lds_bytes,
                           hipStream_t stream);
+
+// As launch_combine for jobs of padded shapes, whose parts come from
+// element slices (BatchTile with n_items elements from item0) and whose
+// outputs may start at any byte; lds_bytes: (3qw + dn) * 4 of the largest
+// shape among the jobs.
+hipError_t launch_combine_padded(const BatchStream* streams, const CombineJob* jobs,
+                                 uint32_t n_jobs, const uint32_t* part, uint32_t grid,
+                                 uint32_t lds_bytes, hipStream_t stream);
 
 // Queue the VALU issue-rate probe: blocks x kThreads lanes, each running
 // iters * 16 * 9 VALU operations; out holds blocks * kThreads words.

@@ -237,12 +237,16 @@ __device__ __forceinline__ uint4 region_chunk(const uint8_t* __restrict__ src, u
 //   2. Every lane gathers its slot words of both sides into registers with
 //      funnel shifts; after a barrier it writes them to xs and ys.
 // Ends with a barrier.
-__device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* __restrict__ xb,
-                                             const uint8_t* __restrict__ yb, uint32_t* xs,
-                                             uint32_t* ys, uint32_t npw) {
+// (The element count, words and bytes per element and bytes per block come
+// as scalars, so that a slice of a block -- n_e of its elements -- stages
+// through the same code.)
+__device__ __forceinline__ void stage_padded_core(uint32_t qw, uint32_t qb, uint32_t n_e,
+                                                  uint32_t nbytes, const uint8_t* __restrict__ xb,
+                                                  const uint8_t* __restrict__ yb, uint32_t* xs,
+                                                  uint32_t* ys, uint32_t npw) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t nw = sh.nw, qw = sh.qw, qb = sh.qbytes, n_e = sh.n_e;
-    const uint32_t len = npw * sh.nbytes, total = npw * nw;
+    const uint32_t nw = qw * n_e;
+    const uint32_t len = npw * nbytes, total = npw * nw;
     const uint32_t lead_x = (uint32_t)((uintptr_t)xb & 15u), lead_y = (uint32_t)((uintptr_t)yb & 15u);
     const uint32_t nx = (lead_x + len + 15u) >> 4, ny = (lead_y + len + 15u) >> 4;
     uint32_t* raw_x = ys;  // X's raw bytes, in the ys area
@@ -275,7 +279,7 @@ __device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* 
     for (uint32_t r = 0; r < kPadRegs; ++r) {
         if (tid + r * nt < total) {
             if (4u * w < qb) {
-                const uint32_t o = j * sh.nbytes + e * qb + 4u * w;  // byte in the region
+                const uint32_t o = j * nbytes + e * qb + 4u * w;  // byte in the region
                 const uint32_t cnt = qb - 4u * w < 4u ? qb - 4u * w : 4u;  // >= 1
                 const uint32_t keep = cnt < 4u ? (1u << (8u * cnt)) - 1u : ~0u;
                 const uint32_t ox = o + lead_x, oy = o + lead_y;
@@ -309,6 +313,12 @@ __device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* 
         }
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void stage_padded(const ExtShape& sh, const uint8_t* __restrict__ xb,
+                                             const uint8_t* __restrict__ yb, uint32_t* xs,
+                                             uint32_t* ys, uint32_t npw) {
+    stage_padded_core(sh.qw, sh.qbytes, sh.n_e, sh.nbytes, xb, yb, xs, ys, npw);
 }
 
 // reduce_store for padded shapes (q need not be a multiple of 32): C_hi = C >> q is first gathered
@@ -498,6 +508,51 @@ __device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t
     for (uint32_t i = tid; i < cw; i += nt) part[i] = cs[i];
 }
 
+// One slice of one block pair of a padded shape, for blocks too large for
+// one work-group: elements [e0, e0 + ne) (block bytes [e0 q/8, (e0 + ne) q/8),
+// any alignment), every sub-product of each.  They are staged in the padded
+// layout (2 (ne qw + kPadSlack) words of LDS), the slice's part of the
+// unreduced sum (2qw words, the other slices' parts XOR to the rest) is
+// stored at part, and combine_padded_kernel adds the parts, reduces and
+// stores the pair.  Ends after the last global store, without a barrier.
+template <int BW>
+__device__ __forceinline__ void extract_slice_padded(const ExtShape& sh,
+                                                     const uint8_t* __restrict__ xb,
+                                                     const uint8_t* __restrict__ yb,
+                                                     uint32_t* __restrict__ part, uint32_t e0,
+                                                     uint32_t ne, uint32_t* lds) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = blockDim.x;
+    const uint32_t qw = sh.qw, cw = 2 * qw, qb = sh.qbytes;
+    const uint32_t area = ne * qw + kPadSlack;
+    uint32_t* xs = lds;        // [ne][qw] (staged X elements)
+    uint32_t* ys = xs + area;  // [ne][qw] (staged Y elements)
+    uint32_t* cs = ys + area;  // [2qw] partial unreduced sum
+
+    for (uint32_t i = tid; i < cw; i += nt) cs[i] = 0;
+    stage_padded_core(qw, qb, ne, ne * qb, xb + (uint64_t)e0 * qb, yb + (uint64_t)e0 * qb, xs,
+                      ys, 1);  // ends with a barrier
+
+    const uint32_t lmask = (1u << sh.levels) - 1u;
+    const uint32_t n_items = ne * sh.np;
+    for (uint32_t it = tid; it < n_items; it += nt) {
+        const uint32_t e = it / sh.np;
+        const uint32_t p = it - e * sh.np;
+        uint32_t hi_mask, mid_mask;
+        path_masks(p, sh.levels, hi_mask, mid_mask);
+        uint32_t acc[2 * BW];
+#pragma unroll
+        for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
+        uint32_t xo[BW], yo[BW];
+        form_operand<BW>(xo, xs + e * qw, hi_mask, mid_mask);
+        form_operand<BW>(yo, ys + e * qw, hi_mask, mid_mask);
+        clmul_acc<BW>(xo, yo, acc);
+        scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cw; i += nt) part[i] = cs[i];
+}
+
 // Plain form: work-group g takes pairs [g*ppw, (g+1)*ppw) of one stream.
 // PAD: the shape is padded (q not a multiple of 32).
 template <int BW, bool PAD>
@@ -517,7 +572,8 @@ ext_ip_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
 // (stream, first pair, pair count; or one slice of one pair) shared by many
 // streams of different shapes.  Each work-group takes the next tile with one atomic add on the
 // queue head and stops once the head passes n_tiles, so every wave exits.
-// PAD: every stream of the launch has a padded shape (no slices then).
+// PAD: every stream of the launch has a padded shape (slices of a padded
+// shape are element ranges).
 template <int BW, bool PAD>
 __global__ void __launch_bounds__(kMaxThreads)
 ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __restrict__ tiles,
@@ -534,11 +590,15 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         const ExtShape& sh = st.shape;  // read in place (a local copy would go to scratch)
         const uint8_t* xb = st.x + tile.in_pair0 * sh.nbytes;
         const uint8_t* yb = st.y + tile.in_pair0 * sh.nbytes;
-        if (!PAD && tile.n_items)  // one slice of one pair; out_off is its part's word offset
-            extract_slice<BW>(sh, reinterpret_cast<const uint32_t*>(xb),
-                              reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
-                              tile.item0, tile.n_items, lds);
-        else
+        if (tile.n_items) {  // one slice of one pair; out_off is its part's word offset
+            if constexpr (PAD)  // elements [item0, item0 + n_items)
+                extract_slice_padded<BW>(sh, xb, yb, part + tile.out_off, tile.item0,
+                                         tile.n_items, lds);
+            else  // items [item0, item0 + n_items)
+                extract_slice<BW>(sh, reinterpret_cast<const uint32_t*>(xb),
+                                  reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
+                                  tile.item0, tile.n_items, lds);
+        } else
             extract_group<BW, PAD>(sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
@@ -596,6 +656,30 @@ combine_kernel(const BatchStream* __restrict__ streams, const CombineJob* __rest
         }
         __syncthreads();
         reduce_store(sh, lds, lds + cw, reinterpret_cast<uint32_t*>(st.out + job.out_byte0), 1);
+        __syncthreads();  // lds is reused by the next job
+    }
+}
+
+// Padded shapes' sliced pairs: as combine_kernel, with the reduction and the
+// byte-granular store of padded shapes.  Job outputs may start at any byte
+// (out_byte0).  lds holds 3qw + dn words of the largest shape among the jobs.
+__global__ void __launch_bounds__(kThreads)
+combine_padded_kernel(const BatchStream* __restrict__ streams, const CombineJob* __restrict__ jobs,
+                      uint32_t n_jobs, const uint32_t* __restrict__ part) {
+    extern __shared__ uint32_t lds[];
+    for (uint32_t jb = blockIdx.x; jb < n_jobs; jb += gridDim.x) {
+        const CombineJob job = jobs[jb];
+        const BatchStream& st = streams[job.stream];
+        const ExtShape& sh = st.shape;
+        const uint32_t cw = 2 * sh.qw;
+        const uint32_t* src = part + job.part_word0;
+        for (uint32_t i = threadIdx.x; i < cw; i += blockDim.x) {
+            uint32_t v = 0;
+            for (uint32_t k = 0; k < job.n_parts; ++k) v ^= src[(uint64_t)k * cw + i];
+            lds[i] = v;
+        }
+        __syncthreads();
+        reduce_store_padded(sh, lds, lds + cw, lds + cw + sh.qw, st.out + job.out_byte0, 1);
         __syncthreads();  // lds is reused by the next job
     }
 }
@@ -782,6 +866,16 @@ hipError_t launch_combine(const BatchStream* streams, const CombineJob* jobs, ui
     if (grid == 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(combine_kernel, dim3(grid), dim3(kThreads), lds_bytes, stream, streams, jobs,
                        n_jobs, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine_padded(const BatchStream* streams, const CombineJob* jobs,
+                                 uint32_t n_jobs, const uint32_t* part, uint32_t grid,
+                                 uint32_t lds_bytes, hipStream_t stream) {
+    if (n_jobs == 0) return hipSuccess;
+    if (grid == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(combine_padded_kernel, dim3(grid), dim3(kThreads), lds_bytes, stream,
+                       streams, jobs, n_jobs, part);
     return hipGetLastError();
 }
 

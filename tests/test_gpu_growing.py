@@ -60,6 +60,9 @@ CASES = [  # n_e, q1, Delta, b, blocks
     (3, 64, 2, 8, 50),
     (71, 80, 1, 16, 12),
     (5, 256, 1, 32, 20),
+    # 71 elements of 1024..1328 bits: blocks computed in element slices over
+    # several work-groups, then combined
+    (71, 1024, 1, 16, 20),
 ]
 
 
@@ -192,6 +195,9 @@ GROWING_STREAMS = [  # n_e, q1, Delta, b, blocks -- the first runs q_l past 4096
     (3, 80, 1, 16, 320),
     (71, 80, 1, 16, 40),
     (4, 64, 2, 8, 120),
+    # the paper's 71 elements to q = 1984: from about q = 1100 on, blocks are
+    # computed in element slices (beyond about 1800 no single work-group could)
+    (71, 80, 1, 16, 120),
 ]
 
 
