@@ -91,24 +91,20 @@ typedef struct {
     uint32_t threads;           /* work-group size, 0 = 256; 1024 shortens the critical
                                    path of shapes with more than 256 items per pair */
     uint32_t kernel;            /* plain and streaming forms: EXT_KERNEL_AUTO (default),
-                                   EXT_KERNEL_WORD (word-level Karatsuba kernel),
+                                   EXT_KERNEL_WORD (word-level Karatsuba kernel) or
                                    EXT_KERNEL_BITSLICE (32 pairs per work-group bit-sliced
-                                   across pairs; fields of at most 128 bits) or
-                                   EXT_KERNEL_BSK (bit-sliced Karatsuba: 32 pairs per
-                                   work-group, fields of 512, 1024 or 2048 bits, x and y
-                                   16-byte aligned); a kernel that does not take the
-                                   shape gives EXT_ENOTSUP.  All give the same bytes.
-                                   AUTO takes the bit-sliced kernel for fields of 16 to
-                                   128 bits that 16 divides with at least 30 elements per
-                                   block and the bit-sliced Karatsuba kernel where it
-                                   measured faster (both listed in the design notes), or,
-                                   with autotune set, whichever applicable kernel times
-                                   fastest for the shape.  The batched, served and
-                                   growing forms run the word-level kernel: they answer
-                                   the bit-sliced kernels with EXT_ENOTSUP */
+                                   across pairs; fields of at most 128 bits, else
+                                   EXT_ENOTSUP).  Both give the same bytes.  AUTO takes
+                                   the bit-sliced kernel for fields of 16 to 128 bits
+                                   that 16 divides with at least 30 elements per block
+                                   (where it measured faster), or, with autotune set,
+                                   whichever of the two times faster for the shape.
+                                   The batched, served and growing forms run the
+                                   word-level kernel: they answer EXT_KERNEL_BITSLICE
+                                   with EXT_ENOTSUP */
     uint32_t reserved[2];
 } ext_params;
-enum { EXT_KERNEL_AUTO = 0, EXT_KERNEL_WORD = 1, EXT_KERNEL_BITSLICE = 2, EXT_KERNEL_BSK = 3 };
+enum { EXT_KERNEL_AUTO = 0, EXT_KERNEL_WORD = 1, EXT_KERNEL_BITSLICE = 2 };
 
 /* Fill *p with defaults (b = 8, conventional modulus, host memory, a stream
  * of the library's own, 256 MiB cap, current device). */

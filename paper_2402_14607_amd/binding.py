@@ -43,7 +43,7 @@ EXPORTED = (
 )
 
 EXT_SIM_SERVED = 0
-KERNEL_AUTO, KERNEL_WORD, KERNEL_BITSLICE, KERNEL_BSK = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_WORD, KERNEL_BITSLICE = 0, 1, 2
 EXT_SIM_PLAIN = 1
 
 

@@ -13,7 +13,6 @@
 #include <vector>
 
 #include "../../include/qrng_ext.h"
-#include "ext_bsk.h"
 #include "ext_internal.h"
 #include "gf2_modulus.h"
 
@@ -138,7 +137,7 @@ struct ext_ctx {
     uint32_t b = 8;
     std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
     ExtShape shape{};
-    uint32_t kind = qext::kKindWord;    // kernel of the plain/streaming launches
+    bool bitslice = false;  // plain/streaming launches take the bit-sliced kernel
     uint32_t kernel = EXT_KERNEL_AUTO;  // ext_params.kernel, for streams of other shapes
     uint32_t mem_kind = EXT_MEM_HOST;
     hipStream_t stream = nullptr;
@@ -172,7 +171,7 @@ struct ext_stream {
     uint64_t nb = 0;  // bytes per block
     uint64_t qb = 0;  // output bytes per block
     ExtShape shape{};       // launch plan of the stream's (n, m)
-    uint32_t kind = qext::kKindWord;  // kernel of the stream's launches
+    bool bitslice = false;  // the stream's launches take the bit-sliced kernel
     // pending input on the device: double buffers, live bytes [head, tail)
     uint8_t* xbuf[2] = {nullptr, nullptr};
     uint8_t* ybuf[2] = {nullptr, nullptr};
@@ -219,21 +218,19 @@ int enter(ext_ctx* c) {
 
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
-int launch(ext_ctx* c, const ExtShape& shape, uint32_t kind, const void* x, const void* y,
+int launch(ext_ctx* c, const ExtShape& shape, bool bitslice, const void* x, const void* y,
            void* out, uint64_t n_pairs) {
-    const uint8_t* xs = (const uint8_t*)x;
-    const uint8_t* ys = (const uint8_t*)y;
-    if (kind == qext::kKindBitslice)
-        HIP_TRY(c, qext::launch_bitslice(shape, xs, ys, (uint8_t*)out, n_pairs, c->stream));
-    else if (kind == qext::kKindBsk)
-        HIP_TRY(c, qext::launch_bsk(shape, xs, ys, (uint8_t*)out, n_pairs, c->stream));
+    if (bitslice)
+        HIP_TRY(c, qext::launch_bitslice(shape, (const uint8_t*)x, (const uint8_t*)y,
+                                         (uint8_t*)out, n_pairs, c->stream));
     else
-        HIP_TRY(c, qext::launch_extract(shape, xs, ys, (uint8_t*)out, n_pairs, c->stream));
+        HIP_TRY(c, qext::launch_extract(shape, (const uint8_t*)x, (const uint8_t*)y,
+                                        (uint8_t*)out, n_pairs, c->stream));
     return EXT_OK;
 }
 
 int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
-    return launch(c, c->shape, c->kind, x, y, out, n_pairs);
+    return launch(c, c->shape, c->bitslice, x, y, out, n_pairs);
 }
 
 // The bit-sliced kernel applies to fields up to kBitsliceMaxQ bits and
@@ -255,56 +252,14 @@ bool bitslice_preferred(const ExtShape& s) {
     return s.q % 16 == 0 && s.q >= 16 && s.q <= 128 && s.n_e >= 30;
 }
 
-// The bit-sliced Karatsuba kernel: fields of 512, 1024 or 2048 bits, taps at
-// most q/2, blocks below 4 GiB.  *k receives its shape.
-bool bsk_applies(uint64_t n_bits, uint32_t m_bits, const std::vector<uint32_t>& taps,
-                 ExtShape* k) {
-    qext::BskGeom g;
-    if (!qext::bsk_geom(m_bits, &g) || n_bits / 8 > 0xffffffffull) return false;
-    for (uint32_t t : taps)
-        if (2 * t > m_bits) return false;
-    *k = ExtShape{};
-    k->q = m_bits;
-    k->qw = m_bits / 32;
-    k->n_e = (uint32_t)(n_bits / m_bits);
-    k->nw = k->qw * k->n_e;
-    k->n_taps = (uint32_t)taps.size();
-    for (size_t i = 0; i < taps.size(); ++i) k->taps[i] = taps[i];
-    k->qbytes = m_bits / 8;
-    k->nbytes = (uint32_t)(n_bits / 8);
-    k->align = 16;  // 16-byte staging loads
-    k->threads = g.threads;
-    k->lds_words = g.total;
-    return true;
-}
-
-// EXT_KERNEL_AUTO's choice of the bit-sliced Karatsuba kernel without
-// autotuning (the shapes where it measured faster than the word-level kernel).
-bool bsk_preferred(const ExtShape& k) {
-    (void)k;
-    return false;
-}
-
 // The launch plan of (n_bits, m_bits, taps) for ext_params.kernel `kernel`
-// without autotuning: the word-level plan from the knobs, and which kernel
-// takes the shape (the AUTO rule, or asked for).  *bsh receives the
-// bit-sliced kernel's shape, *bs_ok whether it applies, *ksh and *bsk_ok the
-// same for the bit-sliced Karatsuba kernel.  EXT_ENOTSUP when no kernel takes
-// the shape.
+// without autotuning: the word-level plan from the knobs, and whether the
+// bit-sliced kernel takes the shape (the AUTO rule, or asked for).  *bsh
+// receives the bit-sliced kernel's shape, *bs_ok whether it applies.
+// EXT_ENOTSUP when no kernel takes the shape.
 int plan_kernel(uint64_t n_bits, uint32_t m_bits, const std::vector<uint32_t>& taps,
-                const qext::PlanKnobs& knobs, uint32_t kernel, ExtShape* shape, uint32_t* kind,
-                ExtShape* bsh, bool* bs_ok, ExtShape* ksh, bool* bsk_ok) {
-    *ksh = ExtShape{};
-    *bsk_ok = kernel != EXT_KERNEL_WORD && kernel != EXT_KERNEL_BITSLICE &&
-              bsk_applies(n_bits, m_bits, taps, ksh);
-    if (kernel == EXT_KERNEL_BSK) {
-        *bs_ok = false;
-        *bsh = ExtShape{};
-        if (!*bsk_ok) return EXT_ENOTSUP;
-        *shape = *ksh;
-        *kind = qext::kKindBsk;
-        return EXT_OK;
-    }
+                const qext::PlanKnobs& knobs, uint32_t kernel, ExtShape* shape, bool* bitslice,
+                ExtShape* bsh, bool* bs_ok) {
     const uint32_t n_e = (uint32_t)(n_bits / m_bits);
     const bool planned = qext::plan_shape(m_bits, n_e, taps.data(), (uint32_t)taps.size(), knobs,
                                           shape);
@@ -323,18 +278,13 @@ int plan_kernel(uint64_t n_bits, uint32_t m_bits, const std::vector<uint32_t>& t
         bs = ok && (kernel == EXT_KERNEL_BITSLICE || !planned || bitslice_preferred(*bsh));
     }
     if (kernel == EXT_KERNEL_BITSLICE && !bs) return EXT_ENOTSUP;
-    const bool bsk = !bs && *bsk_ok && (!planned || bsk_preferred(*ksh));
-    if (!bs && !bsk && !planned) return EXT_ENOTSUP;
-    if (bsk) {
-        *shape = *ksh;
-    } else if (bs) {
+    if (!bs && !planned) return EXT_ENOTSUP;
+    if (bs) {
         if (planned) shape->align = 1;  // byte gathers
         else *shape = *bsh;
     }
-    *kind = bs ? qext::kKindBitslice : bsk ? qext::kKindBsk : qext::kKindWord;
-    // (autotuning may still pick the word-level plan where both exist)
+    *bitslice = bs;
     *bs_ok = ok && planned;
-    *bsk_ok = *bsk_ok && planned;
     return EXT_OK;
 }
 
@@ -401,7 +351,7 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
     if (n_bits == 0 || m_bits == 0 || n_bits % m_bits || m_bits % b) return EXT_EINVAL;
     if (p->mem_kind != EXT_MEM_HOST && p->mem_kind != EXT_MEM_DEVICE) return EXT_EINVAL;
     if (n_bits / m_bits > 0xffffffffull) return EXT_EINVAL;
-    if (p->kernel > EXT_KERNEL_BSK) return EXT_EINVAL;
+    if (p->kernel > EXT_KERNEL_BITSLICE) return EXT_EINVAL;
     std::vector<uint32_t> taps;
     if (p->n_taps == 0) {
         try {
@@ -421,23 +371,17 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
     } else {
         return EXT_EINVAL;
     }
-    ExtShape shape, bsh, ksh, wsh;
+    ExtShape shape, bsh;
     qext::PlanKnobs knobs{p->base_bits / 32, p->groups, p->pairs_per_group, p->threads};
     if (p->base_bits % 32) return EXT_EINVAL;
-    uint32_t kind = qext::kKindWord;
-    bool bs_ok = false, bsk_ok = false;
-    const int prc = plan_kernel(n_bits, m_bits, taps, knobs, p->kernel, &shape, &kind, &bsh,
-                                &bs_ok, &ksh, &bsk_ok);
+    bool bs = false, bs_ok = false;
+    const int prc = plan_kernel(n_bits, m_bits, taps, knobs, p->kernel, &shape, &bs, &bsh, &bs_ok);
     if (prc) return prc;
-    // AUTO with autotune: a timing once the stream exists decides between the
-    // word-level plan (wsh) and the bit-sliced kernels that take the shape
-    const bool tune_kernel = (bs_ok || bsk_ok) && p->kernel == EXT_KERNEL_AUTO && p->autotune;
-    if (tune_kernel && !qext::plan_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
-                                         (uint32_t)taps.size(), knobs, &wsh))
-        return EXT_ENOTSUP;
+    // AUTO with autotune: a timing once the stream exists decides
+    const bool tune_kernel = bs_ok && p->kernel == EXT_KERNEL_AUTO && p->autotune;
     ext_ctx* c = new (std::nothrow) ext_ctx;
     if (!c) return EXT_ENOMEM;
-    c->kind = kind;
+    c->bitslice = bs;
     c->kernel = p->kernel;
     c->n_bits = n_bits;
     c->m_bits = m_bits;
@@ -471,23 +415,17 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         return EXT_EDEVICE;
     }
     if (tune_kernel) {
-        uint32_t chosen = qext::kKindWord;
-        if (qext::choose_kernel(bs_ok ? &bsh : nullptr, bsk_ok ? &ksh : nullptr, wsh, c->stream,
-                                &chosen) != hipSuccess) {
+        bool use_bs = false;
+        if (qext::choose_kernel(bsh, c->stream, &use_bs) != hipSuccess) {
             (void)hipStreamDestroy(c->copy_stream);
             if (c->own_stream) (void)hipStreamDestroy(c->stream);
             delete c;
             return EXT_EDEVICE;
         }
-        c->kind = chosen;
-        if (chosen == qext::kKindBsk) {
-            c->shape = ksh;
-        } else {
-            c->shape = wsh;
-            if (chosen == qext::kKindBitslice) c->shape.align = 1;  // byte gathers
-        }
+        c->bitslice = use_bs;
+        if (use_bs) c->shape.align = 1;
     }
-    if (p->autotune && c->kind == qext::kKindWord) {
+    if (p->autotune && !c->bitslice) {
         qext::PlanKnobs tuned;
         ExtShape ts;
         if (qext::autotune_shape(m_bits, (uint32_t)(n_bits / m_bits), taps.data(),
@@ -519,19 +457,7 @@ int ext_get_modulus(const ext_ctx* c, uint32_t* exps, uint32_t cap, uint32_t* n)
 int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
     if (!c || !buf || cap == 0) return EXT_EINVAL;
     const ExtShape& s = c->shape;
-    if (c->kind == qext::kKindBsk) {
-        qext::BskGeom g;
-        qext::bsk_geom(s.q, &g);
-        snprintf(buf, cap,
-                 "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"kernel\": \"bsk\", "
-                 "\"pairs_per_workgroup\": 32, \"threads\": %u, \"lds_bytes\": %u, "
-                 "\"karatsuba_levels\": %u, \"subproducts\": %u, \"base_planes\": 256, "
-                 "\"materialized_operands\": %u, \"tiles_per_task\": %u}",
-                 (unsigned long long)c->n_bits, c->m_bits, s.n_e, g.threads, g.total * 4,
-                 g.levels, g.np, g.n_leaf, qext::kBskIters);
-        return EXT_OK;
-    }
-    if (c->kind == qext::kKindBitslice) {
+    if (c->bitslice) {
         uint32_t ec = 0, npos = 0, subs = 0, fold = 0;
         qext::bitslice_describe(s, &ec, &npos, &subs, &fold);
         snprintf(buf, cap,
@@ -680,7 +606,7 @@ int ext_stream_open(ext_ctx* c, uint64_t n_bits, uint32_t m_bits, ext_stream** o
     if (!n_bits) n_bits = c->n_bits;
     if (!m_bits) m_bits = c->m_bits;
     ExtShape shape = c->shape;
-    uint32_t kind = c->kind;
+    bool bitslice = c->bitslice;
     if (n_bits != c->n_bits || m_bits != c->m_bits) {
         // a shape of its own: the context's modulus when the field is the
         // context's, else the conventional one of degree m; the default plan
@@ -696,10 +622,10 @@ int ext_stream_open(ext_ctx* c, uint64_t n_bits, uint32_t m_bits, ext_stream** o
                 return EXT_ENOMEM;
             }
         }
-        ExtShape bsh, ksh;
-        bool bs_ok = false, bsk_ok = false;
-        rc = plan_kernel(n_bits, m_bits, taps, qext::PlanKnobs{}, c->kernel, &shape, &kind, &bsh,
-                         &bs_ok, &ksh, &bsk_ok);
+        ExtShape bsh;
+        bool bs_ok = false;
+        rc = plan_kernel(n_bits, m_bits, taps, qext::PlanKnobs{}, c->kernel, &shape, &bitslice,
+                         &bsh, &bs_ok);
         if (rc) return rc;
     }
     ext_stream* s = new (std::nothrow) ext_stream;
@@ -708,7 +634,7 @@ int ext_stream_open(ext_ctx* c, uint64_t n_bits, uint32_t m_bits, ext_stream** o
     s->nb = n_bits / 8;
     s->qb = m_bits / 8;
     s->shape = shape;
-    s->kind = kind;
+    s->bitslice = bitslice;
     // every side holds at most cap bytes of pending input plus one block
     s->buf_bytes = ((c->cap + s->nb - 1) / s->nb + 1) * s->nb;
     // room for as many outputs as the pending input could produce, times two
@@ -805,7 +731,7 @@ int launch_ready(ext_stream* s) {
         const uint8_t* xp = s->xbuf[s->xcur] + s->xhead;
         const uint8_t* yp = s->ybuf[s->ycur] + s->yhead;
         if (((uintptr_t)xp | (uintptr_t)yp) & (s->shape.align - 1)) return EXT_EINVAL;
-        int rc = launch(c, s->shape, s->kind, xp, yp, s->oring + pos * s->qb, k);
+        int rc = launch(c, s->shape, s->bitslice, xp, yp, s->oring + pos * s->qb, k);
         if (rc) return rc;
         Launch L{pos, k, 0, nullptr};
         HIP_TRY(c, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));

@@ -7,7 +7,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -142,24 +141,45 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
 }
 
 namespace {
-std::map<TuneKey, uint32_t> g_kernel_cache;
+std::map<TuneKey, bool> g_kernel_cache;
+}  // namespace
 
-// Milliseconds per pair of `run` (three launches after one warm-up) over
-// `pairs` pairs of synthetic blocks of nb bytes, outputs of qb bytes.
-hipError_t time_per_pair(uint64_t pairs, uint64_t nb, uint64_t qb, uint64_t seed,
-                         hipStream_t stream,
-                         const std::function<hipError_t(const uint8_t*, const uint8_t*, uint8_t*)>& run,
-                         float* per_pair) {
+// Word-level plan (tuned by autotune_shape) against the bit-sliced kernel:
+// time per pair of each over synthetic blocks, the faster one wins.
+hipError_t choose_kernel(const ExtShape& bs, hipStream_t stream, bool* use_bitslice) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const TuneKey key{dev, bs.q, bs.n_e, bs.n_taps, bs.n_taps > 0 ? bs.taps[0] : 0,
+                      bs.n_taps > 1 ? bs.taps[1] : 0, bs.n_taps > 2 ? bs.taps[2] : 0};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_kernel_cache.find(key);
+        if (it != g_kernel_cache.end()) {
+            *use_bitslice = it->second;
+            return hipSuccess;
+        }
+    }
+    PlanKnobs knobs;
+    float word_per_pair = 0;
+    e = autotune_shape(bs.q, bs.n_e, bs.taps, bs.n_taps, stream, &knobs, &word_per_pair);
+    if (e != hipSuccess) return e;
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const uint64_t nb = bs.nbytes;
+    uint64_t pairs = (uint64_t)cus * 8 * 32;  // ~8 work-groups of 32 pairs per CU
+    pairs = std::max<uint64_t>(32, std::min<uint64_t>(pairs, (64ull << 20) / nb));
     uint8_t *dx = nullptr, *dy = nullptr, *dout = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<uint8_t> host(pairs * nb);
-    std::mt19937_64 rng(seed);
+    std::mt19937_64 rng(0x5eed ^ bs.q ^ (uint64_t)bs.n_e << 32);
     for (auto& b : host) b = (uint8_t)rng();
-    hipError_t e;
+    float bs_per_pair = 1e30f;
     do {
         if ((e = hipMalloc((void**)&dx, pairs * nb)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&dy, pairs * nb)) != hipSuccess) break;
-        if ((e = hipMalloc((void**)&dout, pairs * qb)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&dout, pairs * bs.qbytes)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(dx, host.data(), pairs * nb, hipMemcpyHostToDevice, stream)) !=
             hipSuccess)
             break;
@@ -168,84 +188,26 @@ hipError_t time_per_pair(uint64_t pairs, uint64_t nb, uint64_t qb, uint64_t seed
             break;
         if ((e = hipEventCreate(&e0)) != hipSuccess) break;
         if ((e = hipEventCreate(&e1)) != hipSuccess) break;
-        if ((e = run(dx, dy, dout)) != hipSuccess) break;
+        auto run = [&] { return launch_bitslice(bs, dx, dy, dout, pairs, stream); };
+        if ((e = run()) != hipSuccess) break;
         if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run(dx, dy, dout);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
         if (e != hipSuccess) break;
         if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0;
         if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        *per_pair = ms / 3.0f / (float)pairs;
+        bs_per_pair = ms / 3.0f / (float)pairs;
     } while (false);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(dx);
     (void)hipFree(dy);
     (void)hipFree(dout);
-    return e;
-}
-}  // namespace
-
-// The word-level plan (tuned by autotune_shape) against the bit-sliced
-// kernels that apply: time per pair of each over synthetic blocks (about
-// eight work-groups of 32 pairs per CU), the fastest wins.
-hipError_t choose_kernel(const ExtShape* bs, const ExtShape* bsk, const ExtShape& word,
-                         hipStream_t stream, uint32_t* kind) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    const TuneKey key{dev, word.q, word.n_e, word.n_taps, word.n_taps > 0 ? word.taps[0] : 0,
-                      word.n_taps > 1 ? word.taps[1] : 0, word.n_taps > 2 ? word.taps[2] : 0};
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_kernel_cache.find(key);
-        if (it != g_kernel_cache.end()) {
-            *kind = it->second;
-            return hipSuccess;
-        }
-    }
-    PlanKnobs knobs;
-    float best = 0;
-    e = autotune_shape(word.q, word.n_e, word.taps, word.n_taps, stream, &knobs, &best);
-    if (e != hipSuccess) return e;
-    uint32_t choice = kKindWord;
-    int cus = 0;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-        return e;
-    const uint64_t nb = word.nbytes, qb = word.q / 8;
-    uint64_t pairs = (uint64_t)cus * 8 * 32;  // ~8 work-groups of 32 pairs per CU
-    pairs = std::max<uint64_t>(32, std::min<uint64_t>(pairs, (64ull << 20) / nb));
-    const uint64_t seed = 0x5eed ^ word.q ^ (uint64_t)word.n_e << 32;
-    if (bs) {
-        float t = 1e30f;
-        e = time_per_pair(pairs, nb, qb, seed, stream,
-                          [&](const uint8_t* x, const uint8_t* y, uint8_t* o) {
-                              return launch_bitslice(*bs, x, y, o, pairs, stream);
-                          },
-                          &t);
-        if (e != hipSuccess) return e;
-        if (t < best) {
-            best = t;
-            choice = kKindBitslice;
-        }
-    }
-    if (bsk) {
-        float t = 1e30f;
-        e = time_per_pair(pairs, nb, qb, seed, stream,
-                          [&](const uint8_t* x, const uint8_t* y, uint8_t* o) {
-                              return launch_bsk(*bsk, x, y, o, pairs, stream);
-                          },
-                          &t);
-        if (e != hipSuccess) return e;
-        if (t < best) {
-            best = t;
-            choice = kKindBsk;
-        }
-    }
-    *kind = choice;
+    *use_bitslice = bs_per_pair < word_per_pair;
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_kernel_cache[key] = choice;
+    g_kernel_cache[key] = *use_bitslice;
     return hipSuccess;
 }
 
@@ -315,9 +277,8 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
     ext_params_init(&def);
     if (!p) p = &def;
     if (p->n_taps) return EXT_EINVAL;  // batches use the conventional modulus of each m
-    if (p->kernel > EXT_KERNEL_BSK) return EXT_EINVAL;
-    if (p->kernel == EXT_KERNEL_BITSLICE || p->kernel == EXT_KERNEL_BSK)
-        return EXT_ENOTSUP;  // word-level kernels only
+    if (p->kernel > EXT_KERNEL_BITSLICE) return EXT_EINVAL;
+    if (p->kernel == EXT_KERNEL_BITSLICE) return EXT_ENOTSUP;  // word-level kernels only
     ext_batch* b = new (std::nothrow) ext_batch;
     if (!b) return EXT_ENOMEM;
     int dev = p->device;

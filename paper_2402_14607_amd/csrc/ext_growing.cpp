@@ -276,9 +276,8 @@ int ext_growing_create(uint32_t n_e, uint32_t q1, uint32_t delta_steps, const ex
     if (n_e == 0 || q1 == 0 || q1 % 8 || q1 % b || ((uint64_t)delta_steps * b) % 8 || p->n_taps)
         return EXT_EINVAL;
     if (p->mem_kind != EXT_MEM_HOST && p->mem_kind != EXT_MEM_DEVICE) return EXT_EINVAL;
-    if (p->kernel > EXT_KERNEL_BSK) return EXT_EINVAL;
-    if (p->kernel == EXT_KERNEL_BITSLICE || p->kernel == EXT_KERNEL_BSK)
-        return EXT_ENOTSUP;  // word-level kernels only
+    if (p->kernel > EXT_KERNEL_BITSLICE) return EXT_EINVAL;
+    if (p->kernel == EXT_KERNEL_BITSLICE) return EXT_ENOTSUP;  // word-level kernels only
     if (p->base_bits % 32) return EXT_EINVAL;
     ext_growing* g = new (std::nothrow) ext_growing;
     if (!g) return EXT_ENOMEM;

@@ -112,17 +112,9 @@ hipError_t launch_batch(uint32_t bw, uint32_t threads, bool padded, const BatchS
 hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                           hipStream_t stream, PlanKnobs* best, float* best_ms);
 
-// The kernels of the plain and streaming forms.
-constexpr uint32_t kKindWord = 0;      // word-level Karatsuba kernel (ext_kernels.hip)
-constexpr uint32_t kKindBitslice = 1;  // bit-sliced kernel for q <= 128 (ext_bitslice.hip)
-constexpr uint32_t kKindBsk = 2;       // bit-sliced Karatsuba kernel (ext_bsk.hip)
-
-// Autotuned choice among the word-level kernel (its best plan; word is the
-// word-level shape of the field and element count) and the bit-sliced
-// kernels whose shapes are given (null: not applicable): the fastest per pair
-// over synthetic blocks, cached per device and shape.
-hipError_t choose_kernel(const ExtShape* bitslice_shape, const ExtShape* bsk_shape,
-                         const ExtShape& word, hipStream_t stream, uint32_t* kind);
+// Autotuned choice between the word-level kernel (its best plan) and the
+// bit-sliced kernel for a shape the latter applies to; cached per device.
+hipError_t choose_kernel(const ExtShape& bitslice_shape, hipStream_t stream, bool* use_bitslice);
 
 // One byte range to move from a staging buffer into a device ring.
 struct ScatterDesc {
@@ -180,13 +172,6 @@ void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* ti
                        uint32_t* element_subsets, uint32_t* folded);
 hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
                            uint64_t n_pairs, hipStream_t stream);
-
-// Bit-sliced Karatsuba kernel (ext_bsk.hip): 32 block pairs per work-group,
-// q = 512, 1024 or 2048, every tap at most q/2; x and y 16-byte aligned, out
-// 4-byte aligned; blocks and outputs contiguous (nbytes, q/8 apart).
-hipError_t launch_bsk(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
-                      uint64_t n_pairs, hipStream_t stream);
-uint32_t bsk_lds_words(uint32_t q);
 
 // Resident work-groups per CU of the batched kernel at this LDS size.
 hipError_t batch_occupancy(uint32_t bw, uint32_t threads, bool padded, uint32_t lds_bytes,

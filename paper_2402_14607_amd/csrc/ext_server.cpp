@@ -542,10 +542,9 @@ int ext_server_create(const ext_server_config* cfg, const ext_params* p, ext_ser
         cfg->stage_bytes == 0 ||
         cfg->outbox_bytes < 4 || cfg->max_tiles == 0 || cfg->max_descs < 4 ||
         cfg->max_inflight == 0 || cfg->max_inflight > ext_server::kMaxInflight ||
-        p->kernel > EXT_KERNEL_BSK)
+        p->kernel > EXT_KERNEL_BITSLICE)
         return EXT_EINVAL;
-    if (p->kernel == EXT_KERNEL_BITSLICE || p->kernel == EXT_KERNEL_BSK)
-        return EXT_ENOTSUP;  // word-level kernels only
+    if (p->kernel == EXT_KERNEL_BITSLICE) return EXT_ENOTSUP;  // word-level kernels only
     ext_server* s = new (std::nothrow) ext_server;
     if (!s) return EXT_ENOMEM;
     s->cfg = *cfg;

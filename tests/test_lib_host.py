@@ -91,13 +91,12 @@ def test_strerror_and_bad_arguments():
 
 def test_word_only_forms_refuse_the_bitsliced_kernel():
     """The batched, served and growing forms run the word-level kernel: a
-    request for either bit-sliced one is EXT_ENOTSUP, an unknown kernel value
+    request for the bit-sliced one is EXT_ENOTSUP, an unknown kernel value
     EXT_EINVAL, both answered before any device call."""
     import ctypes
 
     lib = binding.load()
-    for kernel, want in ((binding.KERNEL_BITSLICE, binding.EXT_ENOTSUP),
-                         (binding.KERNEL_BSK, binding.EXT_ENOTSUP), (4, binding.EXT_EINVAL)):
+    for kernel, want in ((binding.KERNEL_BITSLICE, binding.EXT_ENOTSUP), (3, binding.EXT_EINVAL)):
         p = binding.make_params(lib, kernel=kernel)
         h = ctypes.c_void_p()
         item = binding.BatchItem()
