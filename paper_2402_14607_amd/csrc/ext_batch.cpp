@@ -4,13 +4,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
 #include <random>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -36,6 +41,168 @@ struct TuneKey {
 
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<PlanKnobs, float>> g_tune_cache;
+std::map<TuneKey, bool> g_kernel_cache;
+
+// ---- persisted results --------------------------------------------------
+// The tuner's results outlive the process in a JSON file: an array with one
+// object per line, either a plan ("entry": "plan": the knobs and the time
+// per pair) or a kernel choice ("entry": "kernel": 1 = bit-sliced), keyed by
+// the device ("gfx950:256": architecture and compute units), q, n_e and the
+// modulus.  The file is $QRNG_EXT_TUNE_CACHE, else
+// $XDG_CACHE_HOME/qrng_ext/autotune.json, else ~/.cache/qrng_ext/autotune.json;
+// an empty QRNG_EXT_TUNE_CACHE turns persistence off.  It is read when a
+// device first looks a shape up and rewritten (temporary file + rename)
+// after every new timing; concurrent writers: the last one wins.
+struct TuneEntry {
+    std::string dev;
+    uint32_t q, n_e, n_taps, t[3];
+    bool plan;  // else a kernel choice
+    PlanKnobs knobs;
+    float ms;
+    bool bitslice;
+};
+std::vector<TuneEntry> g_file;  // the file's entries (and ours since)
+std::string g_file_path;
+bool g_file_read = false;
+std::map<int, std::string> g_dev_tags;
+
+std::string tune_cache_path() {
+    const char* e = getenv("QRNG_EXT_TUNE_CACHE");
+    if (e) return std::string(e);
+    const char* x = getenv("XDG_CACHE_HOME");
+    if (x && *x) return std::string(x) + "/qrng_ext/autotune.json";
+    const char* h = getenv("HOME");
+    if (h && *h) return std::string(h) + "/.cache/qrng_ext/autotune.json";
+    return std::string();
+}
+
+std::string device_tag(int dev) {
+    auto it = g_dev_tags.find(dev);
+    if (it != g_dev_tags.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string tag = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string arch(prop.gcnArchName);
+        const size_t colon = arch.find(':');  // drop feature suffixes (":sramecc+:xnack-")
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+        tag = arch + ":" + std::to_string(prop.multiProcessorCount);
+    } else {
+        (void)hipGetLastError();
+    }
+    g_dev_tags[dev] = tag;
+    return tag;
+}
+
+// (lock held) read the file once per path
+void read_tune_file() {
+    const std::string path = tune_cache_path();
+    if (g_file_read && path == g_file_path) return;
+    g_file_read = true;
+    g_file_path = path;
+    g_file.clear();
+    if (path.empty()) return;
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        TuneEntry t{};
+        char dev[64] = {0}, kind[16] = {0};
+        int used = 0;
+        if (sscanf(line,
+                   " {\"device\": \"%63[^\"]\", \"q\": %u, \"n_e\": %u, \"n_taps\": %u, "
+                   "\"taps\": [%u, %u, %u], \"entry\": \"%15[^\"]\",%n",
+                   dev, &t.q, &t.n_e, &t.n_taps, &t.t[0], &t.t[1], &t.t[2], kind, &used) != 8 ||
+            t.n_taps > 3)
+            continue;
+        t.dev = dev;
+        const char* rest = line + used;
+        if (!strcmp(kind, "plan")) {
+            t.plan = true;
+            if (sscanf(rest, " \"base_words\": %u, \"groups\": %u, \"ppw\": %u, \"threads\": %u, "
+                             "\"ms_per_pair\": %g",
+                       &t.knobs.base_words, &t.knobs.groups, &t.knobs.ppw, &t.knobs.threads,
+                       &t.ms) != 5)
+                continue;
+        } else if (!strcmp(kind, "kernel")) {
+            unsigned v = 0;
+            if (sscanf(rest, " \"bitslice\": %u", &v) != 1) continue;
+            t.plan = false;
+            t.bitslice = v != 0;
+        } else {
+            continue;
+        }
+        g_file.push_back(t);
+    }
+    fclose(f);
+}
+
+// (lock held) rewrite the file with every entry
+void write_tune_file() {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    // create the directory (one level is enough for the default paths'
+    // qrng_ext folder; ~/.cache itself normally exists)
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        const std::string dir = path.substr(0, slash);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "[\n");
+    for (size_t i = 0; i < g_file.size(); ++i) {
+        const TuneEntry& t = g_file[i];
+        fprintf(f,
+                "{\"device\": \"%s\", \"q\": %u, \"n_e\": %u, \"n_taps\": %u, "
+                "\"taps\": [%u, %u, %u], \"entry\": \"%s\", ",
+                t.dev.c_str(), t.q, t.n_e, t.n_taps, t.t[0], t.t[1], t.t[2],
+                t.plan ? "plan" : "kernel");
+        if (t.plan)
+            fprintf(f,
+                    "\"base_words\": %u, \"groups\": %u, \"ppw\": %u, \"threads\": %u, "
+                    "\"ms_per_pair\": %.6g}",
+                    t.knobs.base_words, t.knobs.groups, t.knobs.ppw, t.knobs.threads, t.ms);
+        else
+            fprintf(f, "\"bitslice\": %u}", t.bitslice ? 1u : 0u);
+        fprintf(f, "%s\n", i + 1 < g_file.size() ? "," : "");
+    }
+    fprintf(f, "]\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) (void)rename(tmp.c_str(), path.c_str());
+    else (void)remove(tmp.c_str());
+}
+
+// (lock held) the file's entry for key (plan or kernel choice), if any
+const TuneEntry* find_tune_entry(const TuneKey& key, bool plan) {
+    read_tune_file();
+    const std::string tag = device_tag(key.device);
+    for (const TuneEntry& t : g_file)
+        if (t.plan == plan && t.dev == tag && t.q == key.q && t.n_e == key.n_e &&
+            t.n_taps == key.n_taps && t.t[0] == key.t0 && t.t[1] == key.t1 && t.t[2] == key.t2)
+            return &t;
+    return nullptr;
+}
+
+// (lock held) record a new result and rewrite the file
+void add_tune_entry(const TuneKey& key, bool plan, const PlanKnobs& knobs, float ms,
+                    bool bitslice) {
+    read_tune_file();
+    TuneEntry t{};
+    t.dev = device_tag(key.device);
+    t.q = key.q;
+    t.n_e = key.n_e;
+    t.n_taps = key.n_taps;
+    t.t[0] = key.t0;
+    t.t[1] = key.t1;
+    t.t[2] = key.t2;
+    t.plan = plan;
+    t.knobs = knobs;
+    t.ms = ms;
+    t.bitslice = bitslice;
+    g_file.push_back(t);
+    write_tune_file();
+}
 
 }  // namespace
 
@@ -53,6 +220,12 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune_cache.find(key);
+        if (it == g_tune_cache.end()) {
+            const TuneEntry* t = find_tune_entry(key, true);
+            ExtShape chk;
+            if (t && plan_shape(q, n_e, taps, n_taps, t->knobs, &chk))
+                it = g_tune_cache.emplace(key, std::make_pair(t->knobs, t->ms)).first;
+        }
         if (it != g_tune_cache.end()) {
             *best = it->second.first;
             if (best_ms) *best_ms = it->second.second;
@@ -137,12 +310,9 @@ hipError_t autotune_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32
     if (best_ms) *best_ms = best_t;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = {*best, best_t};
+    add_tune_entry(key, true, *best, best_t, false);
     return hipSuccess;
 }
-
-namespace {
-std::map<TuneKey, bool> g_kernel_cache;
-}  // namespace
 
 // Word-level plan (tuned by autotune_shape) against the bit-sliced kernel:
 // time per pair of each over synthetic blocks, the faster one wins.
@@ -155,6 +325,10 @@ hipError_t choose_kernel(const ExtShape& bs, hipStream_t stream, bool* use_bitsl
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_kernel_cache.find(key);
+        if (it == g_kernel_cache.end()) {
+            const TuneEntry* t = find_tune_entry(key, false);
+            if (t) it = g_kernel_cache.emplace(key, t->bitslice).first;
+        }
         if (it != g_kernel_cache.end()) {
             *use_bitslice = it->second;
             return hipSuccess;
@@ -208,6 +382,7 @@ hipError_t choose_kernel(const ExtShape& bs, hipStream_t stream, bool* use_bitsl
     *use_bitslice = bs_per_pair < word_per_pair;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_kernel_cache[key] = *use_bitslice;
+    add_tune_entry(key, false, PlanKnobs{}, 0.f, *use_bitslice);
     return hipSuccess;
 }
 
@@ -235,6 +410,13 @@ struct ext_batch {
     uint32_t* d_heads = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the launches (one per base size) run concurrently: launch 0 on stream,
+    // the others on side streams forked from and joined back into it, so that
+    // each one's drain tail overlaps the next one's work
+    static constexpr int kSides = 7;
+    hipStream_t side[kSides] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSides] = {};
     uint64_t total_pairs = 0;
     double total_bitmacs = 0;
     int sticky = EXT_OK;
@@ -246,6 +428,14 @@ void batch_free(ext_batch* b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int i = 0; i < ext_batch::kSides; ++i) {
+        if (b->side[i]) {
+            (void)hipStreamSynchronize(b->side[i]);
+            (void)hipStreamDestroy(b->side[i]);
+        }
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     (void)hipFree(b->d_streams);
     (void)hipFree(b->d_tiles);
     (void)hipFree(b->d_heads);
@@ -254,13 +444,32 @@ void batch_free(ext_batch* b) {
 }
 
 int enqueue(ext_batch* b) {
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const size_t n = b->groups.size();
+    // fork: launch gi > 0 runs on side stream (gi - 1) % kSides after the
+    // work queued on stream so far; join: stream waits for every side
+    const bool forked = n > 1 && b->fork;
+    if (forked && hipEventRecord(b->fork, b->stream) != hipSuccess) return EXT_EDEVICE;
+    bool used[ext_batch::kSides] = {};
+    for (size_t gi = 0; gi < n; ++gi) {
         const auto& g = b->groups[gi];
+        hipStream_t st = b->stream;
+        if (forked && gi > 0) {
+            const int k = (int)((gi - 1) % ext_batch::kSides);
+            st = b->side[k];
+            if (!used[k] && hipStreamWaitEvent(st, b->fork, 0) != hipSuccess) return EXT_EDEVICE;
+            used[k] = true;
+        }
         hipError_t e = qext::launch_batch(g.bw, g.threads, g.padded != 0, b->d_streams,
                                           b->d_tiles + g.tile_off,
                                           g.n_tiles,
-                                          b->d_heads + gi, g.grid, g.lds_bytes, b->stream);
+                                          b->d_heads + gi, g.grid, g.lds_bytes, st);
         if (e != hipSuccess) return EXT_EDEVICE;
+    }
+    for (int k = 0; k < ext_batch::kSides; ++k) {
+        if (!used[k]) continue;
+        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->join[k], 0) != hipSuccess)
+            return EXT_EDEVICE;
     }
     return EXT_OK;
 }
@@ -400,6 +609,17 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
         (void)hipGetLastError();
         batch_free(b);
         return EXT_ENOMEM;
+    }
+    if (b->groups.size() > 1) {
+        bool sides = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; sides && k < ext_batch::kSides; ++k)
+            sides = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+        if (!sides) {
+            (void)hipGetLastError();
+            batch_free(b);
+            return EXT_EDEVICE;
+        }
     }
     // capture the submission once; ext_batch_run replays it
     if (!b->groups.empty()) {

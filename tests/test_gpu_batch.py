@@ -175,3 +175,63 @@ def test_wide_workgroups_large_field(dev):
         ex.extract(x, y, out, 3)
         ex.sync()
     assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_autotune_results_persist_across_processes(dev, tmp_path, monkeypatch):
+    """The tuner writes its result to the JSON cache file named by
+    QRNG_EXT_TUNE_CACHE (valid JSON, the chosen plan), and a fresh process
+    takes the plan from that file instead of timing: after the entry is
+    rewritten to another valid plan, the new process's plan is the rewritten
+    one, and its output still equals the oracle's."""
+    import os
+    import subprocess
+    import sys
+
+    path = tmp_path / "autotune.json"
+    monkeypatch.setenv("QRNG_EXT_TUNE_CACHE", str(path))
+    n, m = 3072, 768  # a shape no other test tunes
+    with binding.Extractor(n, m, device_memory=True, autotune=True) as ex:
+        plan = json.loads(ex.describe())
+    entries = json.loads(path.read_text())
+    mine = [e for e in entries if e["q"] == m and e["n_e"] == n // m and e["entry"] == "plan"]
+    assert len(mine) == 1
+    e = mine[0]
+    assert (e["base_words"] * 32, e["groups"], e["ppw"], e["threads"]) == (
+        plan["base_bits"], plan["element_groups"], plan["pairs_per_workgroup"], plan["threads"])
+    say("tuned plan %r" % e)
+    # rewrite the entry to another plan the planner accepts
+    other = dict(e)
+    # q = 768 is 24 words: base products of 3 or 6 words (3 or 2 Karatsuba levels)
+    other["base_words"] = 3 if e["base_words"] != 3 else 6
+    other["groups"], other["ppw"] = 1, 0
+    lines = path.read_text().splitlines()
+    lines = [json.dumps(other) + ("," if ln.rstrip().endswith(",") else "")
+             if '"q": %d, "n_e": %d' % (m, n // m) in ln and '"plan"' in ln else ln
+             for ln in lines]
+    path.write_text("\n".join(lines) + "\n")
+    code = (
+        "import json, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "import numpy as np, torch\n"
+        "import oracle\n"
+        "from paper_2402_14607_amd import binding, inputs\n"
+        "w = inputs.plain_workload(%d, %d, 50, 5, 6)\n"
+        "dev = torch.device('cuda:0')\n"
+        "out = torch.empty(50 * %d // 8, dtype=torch.uint8, device=dev)\n"
+        "with binding.Extractor(%d, %d, device_memory=True, autotune=True,\n"
+        "                       stream=torch.cuda.current_stream(dev).cuda_stream) as ex:\n"
+        "    ex.extract(torch.from_numpy(w.x).to(dev), torch.from_numpy(w.y).to(dev), out, 50)\n"
+        "    ex.sync()\n"
+        "    print(ex.describe())\n"
+        "ok = np.array_equal(out.cpu().numpy(), oracle.ext_blocks(w.x, w.y, %d, %d))\n"
+        "print('PARITY', ok)\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), n, m, m, n, m, n, m)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=110,
+                         env=dict(os.environ))
+    say(res.stdout + res.stderr[-2000:])
+    assert res.returncode == 0
+    lines = [ln for ln in res.stdout.splitlines() if ln.startswith("{")]
+    plan2 = json.loads(lines[-1])
+    assert plan2["base_bits"] == other["base_words"] * 32
+    assert plan2["element_groups"] == 1
+    assert "PARITY True" in res.stdout
