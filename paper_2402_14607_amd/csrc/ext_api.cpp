@@ -458,15 +458,15 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
     if (!c || !buf || cap == 0) return EXT_EINVAL;
     const ExtShape& s = c->shape;
     if (c->bitslice) {
-        uint32_t ec = 0, npos = 0, subs = 0, fold = 0;
-        qext::bitslice_describe(s, &ec, &npos, &subs, &fold);
+        uint32_t ec = 0, levels = 0, piece = 0, subs = 0;
+        qext::bitslice_describe(s, &ec, &levels, &piece, &subs);
         snprintf(buf, cap,
                  "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"kernel\": \"bitslice\", "
                  "\"pairs_per_workgroup\": 32, \"threads\": %d, \"lds_bytes\": %u, "
-                 "\"chunk_elements\": %u, \"tile_positions\": %u, \"element_subsets\": %u, "
-                 "\"folded_tiles\": %u}",
+                 "\"chunk_elements\": %u, \"karatsuba_levels\": %u, \"piece_planes\": %u, "
+                 "\"element_subsets\": %u}",
                  (unsigned long long)c->n_bits, c->m_bits, (uint32_t)(c->n_bits / c->m_bits),
-                 qext::kThreads, qext::bitslice_lds_words(s) * 4, ec, npos, subs, fold);
+                 qext::kThreads, qext::bitslice_lds_words(s) * 4, ec, levels, piece, subs);
         return EXT_OK;
     }
     snprintf(buf, cap,

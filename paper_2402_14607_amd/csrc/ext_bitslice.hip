@@ -2,68 +2,85 @@
 // elements per block, such as the paper's own point (71 elements of F_2^80).
 //
 // A word-level product of q <= 128 bits spends most of its issue slots on
-// shifts and masks (a 96-bit schoolbook product: 7 of 19).  Here a work-group
-// takes 32 block pairs and transposes them so that bit p of a 32-bit "plane"
-// word belongs to pair p: plane (e, j) holds bit j of element e of all 32
-// pairs.  The carry-less product of every element pair is then
+// shifts and masks.  Here a work-group takes 32 block pairs and transposes
+// them so that bit p of a 32-bit "plane" word belongs to pair p: plane (e, j)
+// holds bit j of element e of all 32 pairs.  A carry-less product of planes
 //     c[t] ^= x[j] & y[t - j]      (one v_bitop3_b32 per (j, t), 32 pairs at once)
-// with no shift and no mask, summed over the elements as the paper's inner
-// product (Def. 3.2) asks, reduced modulo P plane by plane, and transposed
-// back into q-bit outputs.
+// needs no shift and no mask.  The element products are summed as the
+// inner product of Def. 3.2 asks, reduced modulo P plane by plane, and
+// transposed back into q-bit outputs.
 //
-// The 32 pairs' blocks are one contiguous region per side.  The elements are
-// taken in chunks of ec; for each chunk a work-group (256 lanes)
-//   1. stages the chunk's bytes of both sides in LDS as they are, with
-//      16-byte loads (issued after the products of the chunk before, when
-//      the raw area is free);
-//   2. transposes them: item (side, word w, element) gathers word w of the
-//      element of the 32 pairs, transposes the 32x32 bit matrix in registers
-//      and writes 32 planes (zero at or above q); Y planes have zero margins
-//      before (kYLo) and after (kYHi);
-//   3. multiplies: lane (16x16 tile position (j-block, t-block offset),
-//      element subset) accumulates the tile's output planes in registers
-//      (x[j] for 16 j, y[t - j] from two windows of 16 and 15 planes) over
-//      its elements of the chunk, keeping the sums across chunks.
-// After the last chunk the lanes XOR their sums into the shared sum C (LDS
-// atomics); then C is reduced modulo P, one output plane per lane (two
-// folding passes, taps at most q/2); lane w transposes planes 32w .. 32w+31 back
-// into word w of the 32 outputs, and the work-group stores its npw*q/8 bytes.
+// Products.  The q-plane operands are split by L Karatsuba levels into
+// pieces of h = q / 2^L planes.  Sub-product s = (s_1 .. s_L), each digit lo,
+// hi or lo+hi, multiplies the matching piece combinations of x and y
+// (h x h planes: h^2 AND-XORs); 3^L of them replace the q^2 schoolbook terms
+// (q = 80, L = 2: 9 x 400 = 3600 instead of 6400).  Every lane owns one
+// sub-product and an element subset, keeps its 2h - 1 product planes in
+// registers across all elements (the inner product's sum commutes with the
+// Karatsuba recombination, which therefore runs once per 32 pairs), and
+// forms its operands from the element's planes in LDS (XOR of 1, 2, 4 or 8
+// pieces).  Lanes are ordered by the number of lo+hi digits, so that most
+// waves form their operands from the same number of pieces.
+//
+// Transposes.  Item (side, half hp, word w) reads 32-bit word w of the
+// chunk's byte stream of the 16 pairs 16hp .. 16hp + 15 straight from memory
+// (buffer loads, bounds-checked against the work-group's region, so that
+// pairs past the last one read zero), transposes the 16 x 32 bit matrix
+// (both 16 x 16 halves at once) and writes its 16-bit halves of stream
+// planes 32w .. 32w + 31; a wave's 64 items are 64 consecutive words of one
+// side and one half, and the next item's loads are in flight while the
+// current one is transposed.  All elements of a block form one chunk when
+// their planes fit the LDS budget (the paper's point: 71 elements, 46 KB),
+// else the elements are taken in equal chunks.
+//
+// After the last chunk the lanes store their sums in LDS, the element
+// subsets' sums are added per sub-product, the sub-products recombined level
+// by level into the 2q - 1 product planes, reduced modulo P (two folding
+// passes, taps at most q/2), and lane (pair p, word w) gathers bit p of
+// planes 32w .. 32w + 31 into its output word.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <mutex>
+#include <unordered_map>
 
 #include "ext_internal.h"
 
 namespace qext {
 namespace {
 
-constexpr uint32_t kBsPairs = 32;   // pairs per work-group (bits of a plane)
-constexpr uint32_t kTile = 16;      // planes per tile side
-constexpr uint32_t kYLo = 16;       // zero Y planes before each element
-constexpr uint32_t kYHi = 32;       // zero Y planes after each element's jp planes
+constexpr uint32_t kBsPairs = 32;      // pairs per work-group (bits of a plane)
+constexpr uint32_t kMaxLevels = 3;
+constexpr uint32_t kMaxSub = 27;       // 3^kMaxLevels
+constexpr uint32_t kMaxPiece = 22;     // largest piece size h (registers: 4h - 1 per lane)
+constexpr uint32_t kLdsTarget = 53248;  // three work-groups on a CU's 160 KiB
+constexpr uint32_t kMaxTaps = 3;
+constexpr uint32_t kMaxIpl = 3;        // transpose items per lane per chunk (held in registers)
+// third word of a buffer resource: 32-bit data format, no swizzle, stride 0
+constexpr int kBufferConfig = 0x00020000;
+
+constexpr uint32_t pow3(uint32_t l) { return l == 0 ? 1u : 3u * pow3(l - 1); }
 
 __device__ __forceinline__ uint32_t bs_and_xor(uint32_t a, uint32_t b, uint32_t acc) {
     return __builtin_amdgcn_bitop3_b32(a, b, acc, 0x6A);  // (a & b) ^ acc
 }
 
-// One block-swap step of the 32x32 transpose: for rows r with bit J clear,
-// the columns of row r with bit J set are exchanged with the columns of row
-// r + J with bit J clear (M selects the columns with bit J clear).  Steps of
-// 16 and 8 move whole bytes (one v_perm_b32 per row); the others take a
-// shift and a bit select (v_bitop3_b32 0xD8: (a & ~m) | (b & m)) per row.
+// One block-swap step of a bit transpose: for rows r with bit J clear, the
+// columns of row r with bit J set are exchanged with the columns of row
+// r + J with bit J clear (M selects the columns with bit J clear).  The step
+// of 8 moves whole bytes (one v_perm_b32 per row); the others take a shift
+// and a bit select (v_bitop3_b32 0xD8: (a & ~m) | (b & m)) per row.
 __device__ __forceinline__ uint32_t bs_select(uint32_t a, uint32_t b, uint32_t m) {
     return __builtin_amdgcn_bitop3_b32(a, b, m, 0xD8);
 }
 
-template <int J, uint32_t M>
-__device__ __forceinline__ void transpose_step(uint32_t (&a)[32]) {
+template <int J, uint32_t M, int N>
+__device__ __forceinline__ void transpose_step(uint32_t (&a)[N]) {
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
+    for (int r = 0; r < N; ++r) {
         if (r & J) continue;
         const uint32_t lo = a[r], hi = a[r + J];
-        if constexpr (J == 16) {
-            a[r] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);      // lo.b0 lo.b1 hi.b0 hi.b1
-            a[r + J] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);  // lo.b2 lo.b3 hi.b2 hi.b3
-        } else if constexpr (J == 8) {
+        if constexpr (J == 8) {
             a[r] = __builtin_amdgcn_perm(hi, lo, 0x06020400u);      // lo.b0 hi.b0 lo.b2 hi.b2
             a[r + J] = __builtin_amdgcn_perm(hi, lo, 0x07030501u);  // lo.b1 hi.b1 lo.b3 hi.b3
         } else {
@@ -73,32 +90,14 @@ __device__ __forceinline__ void transpose_step(uint32_t (&a)[32]) {
     }
 }
 
-// In place: on entry bit c of a[r] is element (r, c); on exit bit r of a[c]
-// is element (r, c).
-__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
-    transpose_step<16, 0x0000FFFFu>(a);
+// 16 rows, both 16-bit halves at once: on entry bit c of a[r] is element
+// (r, c) of a 16 x 32 matrix; on exit bit r of the low half of a[c] is
+// element (r, c) and bit r of the high half is element (r, 16 + c).
+__device__ __forceinline__ void transpose16(uint32_t (&a)[16]) {
     transpose_step<8, 0x00FF00FFu>(a);
     transpose_step<4, 0x0F0F0F0Fu>(a);
     transpose_step<2, 0x33333333u>(a);
     transpose_step<1, 0x55555555u>(a);
-}
-
-// (hi:lo) >> (s mod 32); s = 0 gives lo
-__device__ __forceinline__ uint32_t bs_funnel(uint32_t hi, uint32_t lo, uint32_t s) {
-    return __builtin_amdgcn_alignbit(hi, lo, s);
-}
-
-// Bytes [16k - lead, 16k - lead + 16) of the region [src, src + len)
-// (lead = src & 15) one by one, zero outside it: for the units that straddle
-// an end of the region, so that no access leaves it.
-__device__ __forceinline__ uint4 bs_edge_unit(const uint8_t* __restrict__ src, uint32_t len,
-                                           uint32_t lead, uint32_t k) {
-    uint32_t v[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t b = 0; b < 16u; ++b) {
-        const uint32_t rb = 16u * k + b;
-        if (rb >= lead && rb < lead + len) v[b >> 2] |= (uint32_t)src[rb - lead] << (8u * (b & 3u));
-    }
-    return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 // n / d for n, d < 2^16 with m = bs_recip(d): for d >= 2, m = 2^32/d + e
@@ -107,359 +106,534 @@ __device__ __forceinline__ uint4 bs_edge_unit(const uint8_t* __restrict__ src, u
 __host__ __device__ inline uint32_t bs_recip(uint32_t d) {
     return d <= 1 ? 0u : (uint32_t)(0xffffffffull / d) + 1u;
 }
-__device__ __forceinline__ uint32_t bs_div(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
+__device__ __forceinline__ uint32_t bs_div(uint32_t n, uint32_t m) {
+    return m ? __umulhi(n, m) : n;
+}
 
-constexpr uint32_t kElemsPerLane = 3;  // elements per product lane per chunk
-constexpr uint32_t kStageRegs = 4;     // 16-byte staging loads per lane per chunk
-constexpr uint32_t kChunkBytes = 240;  // most bytes of one pair's chunk (units <= 16)
-constexpr uint32_t kChunkElems = 128;  // most elements per chunk (LDS stays below 56 KiB)
-constexpr uint32_t kPadBlock = kTile + 1;  // LDS words per 16 planes (one pad word)
-constexpr uint32_t kRawSkew = 16;          // extra words before side Y's raw bytes (banks)
+// Number of lo+hi digits of sub-product s (base-3 digits, 2 = lo+hi).
+__host__ __device__ inline uint32_t bs_sums(uint32_t s, uint32_t levels) {
+    uint32_t n = 0;
+    for (uint32_t l = 0; l < levels; ++l, s /= 3) n += s % 3 == 2 ? 1u : 0u;
+    return n;
+}
 
-// LDS word of plane m of an element laid out in blocks of 16 planes and one
-// pad word: tiles of different j-blocks, t-blocks and elements fall in
-// different banks.
-__host__ __device__ constexpr uint32_t bs_pad(uint32_t m) { return kPadBlock * (m >> 4) + (m & 15u); }
-
-// Whether the diagonal tiles are folded (one lane takes both triangles).  It
-// saves a sixth of the products at q = 80 but holds 16 more registers per
-// lane; measured on MI355X over q = 32 .. 112, it pays from q = 96 on.
-__host__ __device__ constexpr bool bs_fold(uint32_t q) { return q % kTile == 0 && q >= 96; }
-
-// Geometry of the kernel for (q, n_e) and a work-group of nt lanes, computed
-// once per launch on the host and passed to the kernel.  Elements are
-// processed in chunks of ec: each chunk's bytes are staged raw, transposed
-// into planes, multiplied.
+// Geometry of a launch for (q, n_e), computed once on the host and passed
+// to the kernel by value.
 struct BsGeom {
-    uint32_t qb, qw, jp, xs, ys;
-    uint32_t jb_n, tb_n, reach, n_pos;  // product tiles: positions (j-block, offset)
-    uint32_t fold;                      // 1: q % 16 == 0, diagonal tiles carry the last offset
-    uint32_t subsets, ec, units;        // element subsets, chunk elements, 16-byte units
-    uint32_t raw, xp, yp, cp, zp, ot, total;  // LDS word offsets and size
+    uint32_t qb, qw, es;       // bytes, words per element; LDS words per element's planes
+    uint32_t levels, h, n_sub, subsets;
+    uint32_t ec;               // elements per chunk (the last chunk may hold fewer)
+    uint32_t xp, yp;           // chunk phase: LDS word offsets of the X and Y planes
+    uint32_t ss;               // end phase: words per lane-sum row [n_sub][2h - 1] (odd)
+    uint32_t pa, pb, zp;       // end phase: recombination buffers, Z
+    uint32_t total;            // LDS words
+    uint32_t rcp_q;            // bs_recip(q)
+    uint8_t order[kMaxSub];    // lane rank -> sub-product (fewest lo+hi digits first)
 };
 
-inline BsGeom bs_geom(uint32_t q, uint32_t n_e, uint32_t nt) {
-    BsGeom g;
+// The layout of (q, n_e) with L levels and chunks of ec elements.
+BsGeom bs_layout(uint32_t q, uint32_t n_e, uint32_t levels, uint32_t ec) {
+    BsGeom g{};
     g.qb = q / 8;
     g.qw = (q + 31) / 32;
-    g.jp = (q + kTile - 1) / kTile * kTile;
-    g.xs = g.jp / kTile * kPadBlock;                    // X: planes 0 .. jp - 1
-    // Y: planes -kYLo .. jp + kYHi - 1, element stride odd so that the plane
-    // writes of up to 32 elements fall in different banks
-    g.ys = (kYLo + g.jp + kYHi) / kTile * kPadBlock + 1;
-    g.jb_n = g.jp / kTile;
-    g.tb_n = (2 * q - 1 + kTile - 1) / kTile;
-    // t-block tb = jb + dt covers t - j from 16 dt - 15 to 16 dt + 15, so dt
-    // runs to (q + 14) / 16.  When 16 divides q, the tile at dt = 0 needs only
-    // j <= t and the one at dt = q/16 only j > t: one lane takes both halves
-    // (256 operations, like a full tile), and dt runs to q/16 - 1.
-    g.fold = bs_fold(q) ? 1u : 0u;
-    g.reach = g.fold ? q / kTile : (q + 14) / kTile + 1;
-    g.n_pos = g.jb_n * g.reach;           // at most 72 (q = 120)
-    uint32_t s = nt / g.n_pos;
-    if (s == 0) s = 1;
-    if (s > n_e) s = n_e;
-    uint32_t ec = s * kElemsPerLane;
-    if (ec > n_e) ec = n_e;
-    if (ec > kChunkBytes / g.qb) ec = kChunkBytes / g.qb;
-    if (ec > kChunkElems) ec = kChunkElems;
-    // the largest chunk whose layout fits 40 KiB (four work-groups on a CU's
-    // 160 KiB) while it still holds an element for every subset, and 64 KiB
-    for (;;) {
-        g.ec = ec;
-        g.units = (ec * g.qb + 14) / 16 + 1;  // covers ec*qb bytes at any offset mod 16
-        g.raw = 0;                            // [2 sides][32 pairs][4*units], sides kRawSkew
-        g.xp = 2 * kBsPairs * 4 * g.units + kRawSkew + 4;  // words apart, + 4 slack words
-        g.yp = g.xp + ec * g.xs;              // X planes [ec][xs]
-        g.cp = g.yp + ec * g.ys;              // Y planes [ec][ys], plane k at bs_pad(kYLo + k)
-        g.zp = g.cp + 2 * g.jp + kTile;       // C [2 jp + kTile]
-        g.ot = g.zp + g.jp;                   // Z [jp]
-        g.total = g.ot + kBsPairs * g.qw;     // outputs [32][qw]
-        if ((g.total * 4u <= 40960u || ec <= s) && g.total * 4u <= 65536u) break;
-        if (ec == 1) break;
-        --ec;
-    }
-    if (s > ec) s = ec;
-    g.subsets = s;
+    g.es = q + 1;  // odd: consecutive elements' planes fall in different banks
+    g.levels = levels;
+    g.h = q >> levels;
+    g.n_sub = pow3(levels);
+    g.subsets = kThreads / g.n_sub;
+    uint32_t k = 0;
+    for (uint32_t c = 0; c <= levels; ++c)
+        for (uint32_t s = 0; s < g.n_sub; ++s)
+            if (bs_sums(s, levels) == c) g.order[k++] = (uint8_t)s;
+    g.ec = ec < n_e ? ec : n_e;
+    g.xp = 0;
+    g.yp = g.ec * g.es;
+    const uint32_t chunk_total = 2 * g.ec * g.es;
+    // end phase: lane sums [subset][ss] from word 0, the subset sums at pa
+    // after them; once those are added up, the lane sums are dead and the
+    // recombination's second buffer pb and Z (padded to whole words of
+    // planes) reuse their words
+    g.ss = (g.n_sub * (2 * g.h - 1)) | 1u;
+    g.pa = g.subsets * g.ss;
+    g.pb = 0;
+    g.zp = g.n_sub * 2 * g.h;
+    const uint32_t end_total = g.pa + g.n_sub * 2 * g.h;
+    g.total = end_total > chunk_total ? end_total : chunk_total;
+    g.rcp_q = bs_recip(q);
     return g;
 }
 
-// Work-group of nt = 256 lanes over npw <= 32 pairs from pair0; the pairs'
-// blocks form one contiguous region of npw*nbytes bytes per side.
-// FOLD: the kernel for shapes with bs_fold(q) (two 16-plane sums per lane).
-// Four work-groups per CU (4 waves per SIMD): FOLD = false needs no more than
-// 128 VGPRs; FOLD = true spills a few registers outside the inner loops.
-template <bool FOLD>
-__global__ void __launch_bounds__(kThreads, 4)
+// Estimated wave64 instructions issued per 32 pairs of a layout: the
+// product rounds (per active wave, h^2 AND-XORs plus the XORs and, at half
+// weight, the LDS reads forming the operands of the wave's most-pieced
+// lane), the transposes (one wave per 63 words of each side and half of a
+// chunk's stream), and the end phase.
+double bs_cost(const BsGeom& g, uint32_t n_e) {
+    double round = 0.0;
+    const uint32_t lanes = g.n_sub * g.subsets;
+    for (uint32_t w = 0; w * 64 < lanes; ++w) {
+        const uint32_t last = (w * 64 + 63 < lanes ? w * 64 + 63 : lanes - 1) / g.subsets;
+        const uint32_t pieces = 1u << bs_sums(g.order[last], g.levels);
+        round += g.h * g.h + 2.0 * g.h * (pieces - 1) + g.h * pieces + 16.0;
+    }
+    const uint32_t q = g.qb * 8;
+    auto chunk = [&](uint32_t e) {
+        const uint32_t words = (e * q + 31) / 32;
+        return ((e + g.subsets - 1) / g.subsets) * round + 4.0 * ((words + 62) / 63) * 240.0 +
+               200.0;
+    };
+    const double end = 4.0 * (2.0 * g.h + 2.0 * g.subsets) + 2.0 * 200.0;
+    return (n_e / g.ec) * chunk(g.ec) + (n_e % g.ec ? chunk(n_e % g.ec) : 0.0) + end;
+}
+
+// The layout the kernel runs for (q, n_e): over the Karatsuba depths whose
+// pieces fit the registers (8 <= h <= kMaxPiece, or h = q below 8), the
+// cheapest by bs_cost, each depth with the fewest equal chunks whose planes
+// fit kLdsTarget and whose words fit kMaxIpl items per lane.
+BsGeom bs_search(uint32_t q, uint32_t n_e) {
+    BsGeom best{};
+    double best_cost = 0.0;
+    bool have = false;
+    for (uint32_t levels = 0; levels <= kMaxLevels; ++levels) {
+        if (q % (1u << levels) || (q >> levels) > kMaxPiece) continue;
+        if (levels > 0 && (q >> levels) < 8) break;
+        uint32_t ec = n_e;
+        while (ec > 1 && (bs_layout(q, n_e, levels, ec).total * 4 > kLdsTarget ||
+                          (ec * q + 31) / 32 > 63 * kMaxIpl)) {
+            const uint32_t chunks = (n_e + ec - 1) / ec + 1;
+            ec = (n_e + chunks - 1) / chunks;
+        }
+        const BsGeom g = bs_layout(q, n_e, levels, ec);
+        const double cost = bs_cost(g, n_e);
+        if (!have || cost < best_cost) best = g, best_cost = cost, have = true;
+    }
+    return best;
+}
+
+// bs_search, remembered per (q, n_e) for the life of the process.
+BsGeom bs_geom(uint32_t q, uint32_t n_e) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, BsGeom> seen;
+    const uint64_t key = (uint64_t)q << 32 | n_e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = seen.find(key);
+    if (it == seen.end()) it = seen.emplace(key, bs_search(q, n_e)).first;
+    return it->second;
+}
+
+// One task (a chunk of one 32-pair group) as the transposes see it.  The
+// chunk's byte stream of each side and half (pairs 16*half .. 16*half + 15)
+// is cut into waves of 63 words: lane l < 63 of item-wave (side, half, j)
+// transposes word w = 63j + l, lane 63 loads word 63j + 63 only to hand it
+// to lane 62.  Item-wave iw = wave + 4m (m < nw) of the work-group's four
+// waves has (side, half) = iw / nw and j = iw mod nw, so every lane holds nw
+// items, nw <= kMaxIpl.
+struct BsTask {
+    const uint8_t* base_x;  // dword holding the first byte of each side's region
+    const uint8_t* base_y;
+    uint32_t nrec_x, nrec_y;  // buffer lengths: lead + region bytes, whole dwords
+    uint32_t lead_x, lead_y;  // first byte's offset in its dword
+    uint32_t eoff;            // the chunk's first byte in a block
+    uint32_t bits, words, nw; // the chunk's stream bits and words; item-waves per (side, half)
+};
+
+__device__ __forceinline__ BsTask bs_task(const uint8_t* x, const uint8_t* y, uint64_t n_pairs,
+                                          uint32_t nbytes, uint32_t q, uint32_t ec, uint32_t n_e,
+                                          uint32_t group, uint32_t chunk) {
+    BsTask t;
+    const uint64_t pair0 = (uint64_t)group * kBsPairs;
+    const uint32_t npw = n_pairs - pair0 < kBsPairs ? (uint32_t)(n_pairs - pair0) : kBsPairs;
+    const uint32_t len = npw * nbytes;
+    const uintptr_t ax = (uintptr_t)(x + pair0 * nbytes), ay = (uintptr_t)(y + pair0 * nbytes);
+    t.lead_x = (uint32_t)(ax & 3u);
+    t.lead_y = (uint32_t)(ay & 3u);
+    t.base_x = (const uint8_t*)(ax - t.lead_x);
+    t.base_y = (const uint8_t*)(ay - t.lead_y);
+    t.nrec_x = (t.lead_x + len + 3) & ~3u;
+    t.nrec_y = (t.lead_y + len + 3) & ~3u;
+    const uint32_t e_cnt = (chunk + 1) * ec <= n_e ? ec : n_e - chunk * ec;
+    t.eoff = chunk * ec * (q / 8);
+    t.bits = e_cnt * q;
+    t.words = (t.bits + 31) / 32;
+    t.nw = (t.words + 62) / 63;
+    return t;
+}
+
+// Byte offset of row p's chunk stream (p = 0..15 of half hf) in its side's buffer.
+__device__ __forceinline__ uint32_t bs_row(const BsTask& t, uint32_t nbytes, bool side_y,
+                                           uint32_t hf, uint32_t p) {
+    return (side_y ? t.lead_y : t.lead_x) + (hf * 16u + p) * nbytes + t.eoff;
+}
+
+// Loads the task's items into r: for each row, the dword word w starts in,
+// from a buffer that starts at the row's first dword (the lanes' offsets
+// are just 4w).  The buffer is bounds-checked against the region's end, so
+// rows of pairs past the last read zero.
+template <uint32_t IPL>
+__device__ __forceinline__ void bs_load_task(const BsTask& t, uint32_t nbytes, uint32_t wave,
+                                             uint32_t lane, uint32_t (&r)[IPL][16]) {
+#pragma unroll
+    for (uint32_t m = 0; m < IPL; ++m) {
+        if (m >= t.nw) break;
+        const uint32_t iw = wave + 4u * m;
+        const uint32_t sh2 = iw / t.nw, j = iw - sh2 * t.nw;
+        const bool side_y = (sh2 >> 1) != 0;
+        const uint8_t* base = side_y ? t.base_y : t.base_x;
+        const uint32_t nrec = side_y ? t.nrec_y : t.nrec_x;
+        const uint32_t w = 63u * j + lane;
+#pragma unroll
+        for (uint32_t p = 0; p < 16; ++p) {
+            // row start and length as scalars (the resource must be uniform)
+            const uint32_t row = bs_row(t, nbytes, side_y, sh2 & 1u, p);
+            const uint32_t rs = __builtin_amdgcn_readfirstlane(row & ~3u);
+            const uint32_t n = __builtin_amdgcn_readfirstlane(nrec > rs ? nrec - rs : 0u);
+            const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(base + rs), (short)0, (int)n, kBufferConfig);
+            r[m][p] = __builtin_amdgcn_raw_buffer_load_b32(res, 4u * w, 0, 0);
+        }
+    }
+}
+
+// Transposes the task's items and writes their 16-bit halves of stream
+// planes 32w .. 32w + 31 (plane b is bit b mod q of element b / q) in
+// groups of 8 (q is a multiple of 8).  A row's word straddles the lane's
+// dword and the next lane's (DPP wave shift: lane l reads lane l + 1).
+template <uint32_t IPL>
+__device__ __forceinline__ void bs_put_task(const BsTask& t, uint32_t nbytes, uint32_t wave,
+                                            uint32_t lane, const uint32_t (&r)[IPL][16],
+                                            uint32_t* xp, uint32_t* yp, uint32_t es, uint32_t q,
+                                            uint32_t rcp_q) {
+#pragma unroll
+    for (uint32_t m = 0; m < IPL; ++m) {
+        if (m >= t.nw) break;
+        const uint32_t iw = wave + 4u * m;
+        const uint32_t sh2 = iw / t.nw, j = iw - sh2 * t.nw;
+        const bool side_y = (sh2 >> 1) != 0;
+        const uint32_t w = 63u * j + lane;
+        uint32_t a[16];
+#pragma unroll
+        for (uint32_t p = 0; p < 16; ++p) {
+            const uint32_t next = __builtin_amdgcn_update_dpp(0u, r[m][p], 0x130, 0xf, 0xf, false);
+            const uint32_t row = bs_row(t, nbytes, side_y, sh2 & 1u, p);
+            a[p] = __builtin_amdgcn_alignbit(next, r[m][p], (row & 3u) * 8u);
+        }
+        if (lane == 63 || w >= t.words) continue;
+        transpose16(a);  // a[i]: plane i (low half), plane 16 + i (high half)
+        uint16_t* planes = reinterpret_cast<uint16_t*>(side_y ? yp : xp) + (sh2 & 1u);
+#pragma unroll
+        for (uint32_t gi = 0; gi < 4; ++gi) {
+            const uint32_t b = 32u * w + 8u * gi;
+            if (b < t.bits) {
+                const uint32_t e = bs_div(b, rcp_q);
+                uint16_t* dst = planes + 2 * (e * es + (b - e * q));
+#pragma unroll
+                for (uint32_t i = 0; i < 8; ++i) {
+                    const uint32_t v = a[8 * (gi & 1u) + i];
+                    dst[2 * i] = (uint16_t)(gi < 2 ? v : v >> 16);
+                }
+            }
+        }
+    }
+}
+
+// Piece offset (planes) of combination c of a sub-product whose lo+hi
+// levels are the set bits of summask: bit i of c selects the i-th of them.
+template <uint32_t H, uint32_t L>
+__device__ __forceinline__ uint32_t bs_piece_off(uint32_t p0, uint32_t summask, uint32_t c) {
+    uint32_t p = p0;
+#pragma unroll
+    for (uint32_t b = 0; b < L; ++b)
+        if (summask >> b & 1u) {
+            if (c & 1u) p |= 1u << b;
+            c >>= 1;
+        }
+    return p * H;
+}
+
+// cp[idx] if on, else 0, reading cp[0] instead: the read is always in range.
+__device__ __forceinline__ uint32_t bs_term(const uint32_t* cp, bool on, uint32_t idx) {
+    return cp[on ? idx : 0u] & (on ? ~0u : 0u);
+}
+
+// Work-group of 256 lanes, persistent over 32-pair groups; each group's
+// blocks form one contiguous region of npw*nbytes bytes per side, at any
+// byte offset.  H: piece size h, L: Karatsuba levels (q = H * 2^L).  Three
+// work-groups per CU (at most 168 VGPRs per lane).
+template <uint32_t H, uint32_t L>
+__global__ void __launch_bounds__(kThreads, 3)
 bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
                 uint8_t* __restrict__ out, uint64_t n_pairs, ExtShape sh, BsGeom g) {
+    constexpr uint32_t kAcc = 2 * H - 1;
+    constexpr uint32_t kSub = pow3(L);
+    constexpr uint32_t kSubsets = kThreads / kSub;
     extern __shared__ __align__(16) uint32_t lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / 64u), lane = tid & 63u;
     const uint32_t q = sh.q, n_e = sh.n_e, nbytes = sh.nbytes;
-    const uint32_t qb = g.qb, qw = g.qw, jp = g.jp, xs = g.xs, ys = g.ys, ec = g.ec;
-    const uint32_t units = g.units;
-    uint32_t* raw = lds + g.raw;
+    const uint32_t qb = g.qb, es = g.es, ec = g.ec;
     uint32_t* xp = lds + g.xp;
     uint32_t* yp = lds + g.yp;
-    uint32_t* cp = lds + g.cp;
-    uint32_t* zp = lds + g.zp;
-    uint32_t* ot = lds + g.ot;
-
-    const uint64_t pair0 = (uint64_t)blockIdx.x * kBsPairs;
-    if (pair0 >= n_pairs) return;
-    const uint32_t npw = n_pairs - pair0 < kBsPairs ? (uint32_t)(n_pairs - pair0) : kBsPairs;
-    const uint8_t* xb = x + pair0 * nbytes;
-    const uint8_t* yb = y + pair0 * nbytes;
-    const uint32_t len = npw * nbytes;
-    const uint32_t lead_x = (uint32_t)((uintptr_t)xb & 15u);
-    const uint32_t lead_y = (uint32_t)((uintptr_t)yb & 15u);
-
-    for (uint32_t i = tid; i < 2 * jp + kTile; i += nt) cp[i] = 0u;
-    for (uint32_t i = tid; i < ec * (kYLo + kYHi); i += nt) {  // Y's zero margins
-        const uint32_t e = i / (kYLo + kYHi), r = i - e * (kYLo + kYHi);
-        yp[e * ys + bs_pad(r < kYLo ? r : jp + r)] = 0u;  // r >= kYLo: plane jp + (r - kYLo)
-    }
-
-    // ---- staging: unit k = (side, pair p, u) of chunk c is the 16-byte unit
-    // (lead + p*nbytes + c*ec*qb) / 16 + u of the side's raw region.  Units
-    // inside the region are loaded with 16-byte loads; units that straddle an
-    // end are read bytewise when stored; units outside it, and of pairs past
-    // npw, are zero.
-    const uint32_t n_units = 2 * kBsPairs * units;  // <= kStageRegs * nt
-    // slot r of this lane: unit k = tid + r*nt, packed as (lead + p*nbytes) << 4 | u
-    // (below 2^32: nbytes < 2^23), or ~0 for no unit (k >= n_units or p >= npw)
-    const uint32_t rcp_units = bs_recip(units);  // k < 2^11, units <= 16
-    uint32_t slot[kStageRegs];
-#pragma unroll
-    for (uint32_t r = 0; r < kStageRegs; ++r) {
-        const uint32_t k = tid + r * nt;
-        const uint32_t side = k >= kBsPairs * units ? 1u : 0u;
-        const uint32_t rem = k - side * (kBsPairs * units);
-        const uint32_t p = bs_div(rem, rcp_units), u = rem - p * units;
-        slot[r] = (k < n_units && p < npw) ? ((side ? lead_y : lead_x) + p * nbytes) << 4 | u : ~0u;
-    }
-    uint4 st[kStageRegs];
-    uint32_t edge = 0;  // bit r: slot r's unit straddles an end of the region
-    auto unit_index = [&](uint32_t r, uint32_t c) -> uint32_t {
-        return (((slot[r] >> 4) + c * ec * qb) >> 4) + (slot[r] & 15u);
-    };
-    auto load_chunk = [&](uint32_t c) {
-        edge = 0;
-#pragma unroll
-        for (uint32_t r = 0; r < kStageRegs; ++r) {
-            st[r] = make_uint4(0u, 0u, 0u, 0u);
-            if (slot[r] != ~0u) {
-                const uint32_t side = tid + r * nt >= kBsPairs * units ? 1u : 0u;
-                const uint32_t lead = side ? lead_y : lead_x;
-                const uint32_t uk = unit_index(r, c), first = 16u * uk;
-                if (first >= lead && first + 16u <= lead + len)
-                    st[r] = reinterpret_cast<const uint4*>((side ? yb : xb) - lead)[uk];
-                else if (first < lead + len && first + 16u > lead)
-                    edge |= 1u << r;
-            }
-        }
-    };
-    auto store_chunk = [&](uint32_t c) {
-#pragma unroll
-        for (uint32_t r = 0; r < kStageRegs; ++r) {
-            const uint32_t k = tid + r * nt;
-            if (k < n_units) {
-                uint4 v = st[r];
-                if (edge & (1u << r)) {
-                    const uint32_t side = k >= kBsPairs * units ? 1u : 0u;
-                    v = bs_edge_unit(side ? yb : xb, len, side ? lead_y : lead_x, unit_index(r, c));
-                }
-                reinterpret_cast<uint4*>(raw + (k >= kBsPairs * units ? kRawSkew : 0u))[k] = v;
-            }
-        }
-    };
-
-    // Lane (position (jb, dt), element subset): x planes j = 16 jb + jj, output
-    // planes t = 16 (jb + dt) + i.  Terms with j <= t (jj <= i) take y plane
-    // 16 da + (i - jj) and go to acc_lo (t-block jb + da); terms with j > t take
-    // y plane 16 db + (i - jj) and go to acc_hi (t-block jb + db).  A plain tile
-    // has da = db = dt; a folded diagonal tile has da = 0, db = q/16.
-    const uint32_t pos = tid % g.n_pos, sub = tid / g.n_pos;
-    const uint32_t jb = pos / g.reach, dt = pos - jb * g.reach;
-    const uint32_t da = dt, db = (g.fold && dt == 0) ? q / kTile : dt;
-    const bool active = sub < g.subsets && jb + dt < g.tb_n;
-    // y planes 16 da + m (m = 0 .. 15) at bs_pad(kYLo + 16 da + m) = 17 (da + 1) + m,
-    // and 16 db - 15 + m (m = 0 .. 14) at 17 db + 1 + m; all within
-    // [-kYLo, jp + kYHi) since 16 db <= q + 14 and jp >= q
-    const uint32_t xoff = jb * kPadBlock;
-    const uint32_t yoff_a = (da + 1) * kPadBlock, yoff_b = db * kPadBlock + 1;
-    // (not folded: da == db, both halves go to acc_lo and acc_hi stays unused)
-    uint32_t acc_lo[kTile], acc_hi[FOLD ? kTile : 1];
-#pragma unroll
-    for (uint32_t i = 0; i < kTile; ++i) acc_lo[i] = 0u;
-#pragma unroll
-    for (uint32_t i = 0; i < (FOLD ? kTile : 1); ++i) acc_hi[i] = 0u;
-
+    const uint32_t n_groups = (uint32_t)((n_pairs + kBsPairs - 1) / kBsPairs);
     const uint32_t n_chunks = (n_e + ec - 1) / ec;
-    load_chunk(0);
-    store_chunk(0);
-    __syncthreads();
-    for (uint32_t c = 0; c < n_chunks; ++c) {
-        const uint32_t e_cnt = (c + 1) * ec <= n_e ? ec : n_e - c * ec;
-        const uint32_t eoff = c * ec * qb;
-        // ---- transposes: item (side, word w, element le) gathers word w of
-        // element le of the 32 pairs (two LDS words and a funnel shift each;
-        // pairs past npw were staged as zero), transposes, and writes planes
-        // 32w .. 32w + 31.  Each side's items fill whole waves (padded to 64
-        // slots), so the side, and with it the pairs' byte offsets, are uniform
-        // across a wave; within a side the items run word-major
-        const uint32_t side_items = e_cnt * qw;
-        const uint32_t side_slots = (side_items + 63u) & ~63u;
-        const uint32_t rcp_e = bs_recip(e_cnt);  // side_items < 2^16
-        for (uint32_t it = tid; it < 2 * side_slots; it += nt) {
-            const uint32_t side = __builtin_amdgcn_readfirstlane(it >= side_slots ? 1u : 0u);
-            const uint32_t r = it - side * side_slots;
-            if (r >= side_items) continue;
-            const uint32_t w = bs_div(r, rcp_e);  // word-major within the side
-            const uint32_t le = r - w * e_cnt;
-            const uint32_t* rs = raw + side * (kBsPairs * 4 * units + kRawSkew);
-            const uint32_t lead = side ? lead_y : lead_x;
-            const uint32_t lt = le * qb + 4u * w;  // byte of the word in the pair's chunk
-            uint32_t a[32];
-            // both words are always read (the second may be the next pair's
-            // or a slack word) so that the 64 reads issue back to back
+
+    // Lane (rank, element subset): sub-product s = order[rank], whose operand
+    // is the XOR of the pieces p0 + (any subset of the lo+hi levels' bits);
+    // piece i covers planes i*H .. i*H + H - 1 (level 1 is the top bit).
+    const uint32_t rank = tid / kSubsets, sub = tid - rank * kSubsets;
+    const bool active = rank < kSub;
+    const uint32_t s = active ? g.order[rank] : 0u;
+    uint32_t p0 = 0, summask = 0, pieces = 1;
+    {
+        uint32_t rest = s;
 #pragma unroll
-            for (uint32_t h = 0; h < 32; h += 8) {
-#pragma unroll
-                for (uint32_t p = h; p < h + 8; ++p) {
-                    const uint32_t o = ((lead + p * nbytes + eoff) & 15u) + lt;
-                    const uint32_t* r2 = rs + p * 4 * units + (o >> 2);
-                    a[p] = bs_funnel(r2[1], r2[0], o * 8u);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (qb - 4u * w < 4u) {  // the element's last word: bytes past q/8 are the next one's
-                const uint32_t keep = (1u << (8u * (qb - 4u * w))) - 1u;
-#pragma unroll
-                for (uint32_t p = 0; p < 32; ++p) a[p] &= keep;
-            }
-            transpose32(a);
-            // plane j = 32w + i at bs_pad(j) (X) or bs_pad(kYLo + j) (Y); planes
-            // q .. jp - 1 are zero (masked bytes); 32w + 16 <= jp always
-            uint32_t* dst = side ? yp + le * ys + kPadBlock + 2 * kPadBlock * w
-                                 : xp + le * xs + 2 * kPadBlock * w;
-#pragma unroll
-            for (uint32_t i = 0; i < 16; ++i) dst[bs_pad(i)] = a[i];
-            if (32u * w + 32u <= jp) {
-#pragma unroll
-                for (uint32_t i = 16; i < 32; ++i) dst[bs_pad(i)] = a[i];
-            }
+        for (uint32_t b = 0; b < L; ++b, rest /= 3) {  // digit of level L - b: piece bit b
+            const uint32_t d = rest % 3;
+            if (d == 1) p0 |= 1u << b;
+            if (d == 2) summask |= 1u << b, pieces <<= 1;
         }
+    }
+    uint32_t acc[kAcc];
+#pragma unroll
+    for (uint32_t i = 0; i < kAcc; ++i) acc[i] = 0u;
+
+    // Persistent: the work-group takes groups blockIdx.x, + gridDim.x, ...,
+    // each chunk by chunk.  A task's items are loaded into registers while
+    // the task before it multiplies (and, after a group's last chunk, sums,
+    // reduces and stores), so that its transposes find them there.
+    uint32_t group = blockIdx.x, chunk = 0;
+    if (group >= n_groups) return;
+    uint32_t rows[kMaxIpl][16];
+    BsTask cur = bs_task(x, y, n_pairs, nbytes, q, ec, n_e, group, chunk);
+    bs_load_task<kMaxIpl>(cur, nbytes, wave, lane, rows);
+#pragma unroll 1
+    for (;;) {
+        bs_put_task<kMaxIpl>(cur, nbytes, wave, lane, rows, xp, yp, es, q, g.rcp_q);
         __syncthreads();
-        // ---- products: c[t] ^= x[j] & y[t - j] over the 16x16 tile
-        if (active) {
-            for (uint32_t le = sub; le < e_cnt; le += g.subsets) {
-                const uint32_t* xe = xp + le * xs + xoff;
-                const uint32_t* ya = yp + le * ys + yoff_a;
-                const uint32_t* yb2 = yp + le * ys + yoff_b;
-                // the two halves one after the other: 16 y planes live at a time
-                uint32_t xv[kTile], yv[kTile];
+        const bool last_chunk = chunk + 1 == n_chunks;
+        const uint32_t next_group = last_chunk ? group + gridDim.x : group;
+        const uint32_t next_chunk = last_chunk ? 0u : chunk + 1;
+        const bool more = next_group < n_groups;
+        BsTask nxt = cur;
+        if (more) {
+            nxt = bs_task(x, y, n_pairs, nbytes, q, ec, n_e, next_group, next_chunk);
+            bs_load_task<kMaxIpl>(nxt, nbytes, wave, lane, rows);
+        }
+        // ---- products: the lane's sub-product over its elements of the chunk
+        const uint32_t e_cnt = cur.bits / q;
+#pragma unroll 1
+        for (uint32_t le = active ? sub : e_cnt; le < e_cnt; le += kSubsets) {
+            const uint32_t* xe = xp + le * es;
+            const uint32_t* ye = yp + le * es;
+            uint32_t xv[H], yv[H];
+            const uint32_t off0 = p0 * H;
 #pragma unroll
-                for (uint32_t i = 0; i < kTile; ++i) xv[i] = xe[i];
+            for (uint32_t i = 0; i < H; ++i) xv[i] = xe[off0 + i];
 #pragma unroll
-                for (uint32_t m = 0; m < kTile; ++m) yv[m] = ya[m];
+            for (uint32_t i = 0; i < H; ++i) yv[i] = ye[off0 + i];
+            if constexpr (L > 0) {
+#pragma unroll 1
+                for (uint32_t pc = 1; pc < pieces; ++pc) {
+                    const uint32_t off = bs_piece_off<H, L>(p0, summask, pc);
 #pragma unroll
-                for (uint32_t i = 0; i < kTile; ++i)
+                    for (uint32_t i = 0; i < H; ++i) xv[i] ^= xe[off + i];
 #pragma unroll
-                    for (uint32_t jj = 0; jj <= i; ++jj)
-                        acc_lo[i] = bs_and_xor(xv[jj], yv[i - jj], acc_lo[i]);
+                    for (uint32_t i = 0; i < H; ++i) yv[i] ^= ye[off + i];
+                }
+            }
 #pragma unroll
-                for (uint32_t m = 0; m < kTile - 1; ++m) yv[m] = yb2[m];
+            for (uint32_t kk = 0; kk < H; ++kk)
 #pragma unroll
-                for (uint32_t i = 0; i < kTile; ++i)
+                for (uint32_t j = 0; j < H; ++j)
+                    acc[j + kk] = bs_and_xor(xv[j], yv[kk], acc[j + kk]);
+        }
+        __syncthreads();  // the planes are read before the next chunk or the sums overwrite them
+        if (last_chunk) {
+            const uint64_t pair0 = (uint64_t)group * kBsPairs;
+            const uint32_t npw =
+                n_pairs - pair0 < kBsPairs ? (uint32_t)(n_pairs - pair0) : kBsPairs;
+            // ---- sums: lane (rank, subset) stores its sums at row `subset`, column
+            // s*(2H - 1) of [subsets][ss] (ss odd: the subsets of a sub-product fall
+            // in different banks); then each (s, t) is the XOR over the subsets
+            if (active) {
+                uint32_t* dst = lds + sub * g.ss + s * kAcc;
 #pragma unroll
-                    for (uint32_t jj = i + 1; jj < kTile; ++jj) {
-                        if constexpr (FOLD)
-                            acc_hi[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_hi[i]);
-                        else
-                            acc_lo[i] = bs_and_xor(xv[jj], yv[i + kTile - 1 - jj], acc_lo[i]);
+                for (uint32_t t = 0; t < kAcc; ++t) dst[t] = acc[t];
+            }
+            __syncthreads();
+            uint32_t* src = lds + g.pa;
+            for (uint32_t i = tid; i < kSub * kAcc; i += nt) {
+                uint32_t v = 0;
+#pragma unroll
+                for (uint32_t k = 0; k < kSubsets; ++k) v ^= lds[k * g.ss + i];
+                src[i] = v;
+            }
+            __syncthreads();
+
+            // ---- recombination, innermost level first: the product of operands
+            // split as a + z^n b (pieces of n planes) is
+            //   ab = A (1 + z^n) + M z^n + B (z^n + z^2n)
+            // with A = a_lo b_lo, B = a_hi b_hi, M = (a_lo + a_hi)(b_lo + b_hi); the
+            // children of product s' are 3s' + {0: lo, 1: hi, 2: lo+hi}
+            {
+                uint32_t* dst = lds + g.pb;
+                uint32_t n = kSub, size = H;
+#pragma unroll
+                for (uint32_t l = 0; l < L; ++l) {
+                    const uint32_t in_w = 2 * size - 1, out_w = 4 * size - 1;
+                    n /= 3;
+                    for (uint32_t i = tid; i < n * out_w; i += nt) {
+                        const uint32_t sp = i / out_w, t = i - sp * out_w;
+                        const uint32_t* lo = src + 3 * sp * in_w;
+                        const uint32_t* hi = lo + in_w;
+                        const uint32_t* mid = hi + in_w;
+                        // every read in range (indices clamped), terms outside their
+                        // window masked off, so that the reads issue together
+                        const uint32_t t1 = t >= size ? t - size : 0u;
+                        const uint32_t t2 = t >= 2 * size ? t - 2 * size : 0u;
+                        const uint32_t m0 = t < in_w ? ~0u : 0u;
+                        const uint32_t m1 = t >= size && t1 < in_w ? ~0u : 0u;
+                        const uint32_t m2 = t >= 2 * size && t2 < in_w ? ~0u : 0u;
+                        const uint32_t c0 = t < in_w ? t : 0u, c1 = t1 < in_w ? t1 : 0u;
+                        const uint32_t c2 = t2 < in_w ? t2 : 0u;
+                        dst[i] = (lo[c0] & m0) ^ ((lo[c1] ^ hi[c1] ^ mid[c1]) & m1) ^ (hi[c2] & m2);
                     }
-            }
-        }
-        if (c + 1 < n_chunks) {  // the next chunk's bytes (raw is free after the transposes)
-            load_chunk(c + 1);
-            store_chunk(c + 1);
-        }
-        __syncthreads();
-    }
-    if (active) {  // t-blocks below tb_n + 1 (folded: jb + q/16 <= 2q/16 - 1)
-        uint32_t* ca = cp + (jb + da) * kTile;
-        uint32_t* cb = cp + (jb + db) * kTile;
-#pragma unroll
-        for (uint32_t i = 0; i < kTile; ++i) {
-            if constexpr (FOLD) {
-                if (da == db) {
-                    const uint32_t v = acc_lo[i] ^ acc_hi[i];
-                    if (v) atomicXor(ca + i, v);
-                } else {
-                    if (acc_lo[i]) atomicXor(ca + i, acc_lo[i]);
-                    if (acc_hi[i]) atomicXor(cb + i, acc_hi[i]);
+                    __syncthreads();
+                    uint32_t* tmp = src;
+                    src = dst;
+                    dst = tmp;
+                    size *= 2;
                 }
-            } else {
-                if (acc_lo[i]) atomicXor(ca + i, acc_lo[i]);
             }
-        }
-    }
-    __syncthreads();
+            const uint32_t* cp = src;  // the 2q - 1 product planes
+            uint32_t* zp = lds + g.zp;
 
-    // ---- reduction modulo P ------------------------------------------
-    // C = C_lo + t^q H with H[i] = c[q + i] (i <= q - 2) and t^q = 1 + sum_f t^f
-    // (every tap f <= q/2).  t^f H = (t^f H mod t^q) + t^q U_f with U_f[i] =
-    // H[i + q - f] = c[2q + i - f] for i <= f - 2; D = sum_f U_f; t^q D = D +
-    // sum_g t^g D needs no further reduction.  Output plane t < q:
-    //   z[t] = c[t] + H[t] + sum_f H[t - f] + D[t] + sum_g D[t - g].
-    for (uint32_t t = tid; t < q; t += nt) {
-        uint32_t z = cp[t] ^ (t + 1 < q ? cp[q + t] : 0u);
-        for (uint32_t k = 0; k < sh.n_taps; ++k) {
-            const uint32_t f = sh.taps[k];
-            if (t >= f) z ^= cp[q + t - f];                  // (t^f H)[t], t - f <= q - 2
-            if (t + 1 < f) z ^= cp[2 * q + t - f];           // U_f[t] in D[t]
-            for (uint32_t k2 = 0; k2 < sh.n_taps; ++k2) {    // U_f[t - g] in (t^g D)[t]
-                const uint32_t gg = sh.taps[k2];
-                if (t >= gg && t - gg + 1 < f) z ^= cp[2 * q + (t - gg) - f];
+            // ---- reduction modulo P ------------------------------------------
+            // C = C_lo + t^q H with H[i] = c[q + i] (i <= q - 2) and t^q = 1 + sum_f t^f
+            // (every tap f <= q/2).  t^f H = (t^f H mod t^q) + t^q U_f with U_f[i] =
+            // H[i + q - f] = c[2q + i - f] for i <= f - 2; D = sum_f U_f; t^q D = D +
+            // sum_g t^g D needs no further reduction.  Output plane t < q:
+            //   z[t] = c[t] + H[t] + sum_f H[t - f] + D[t] + sum_g D[t - g].
+            // Every read is in range (indices clamped into [0, 2q - 1)) and the
+            // terms outside their condition are masked off, so that a lane's reads
+            // issue together.  Planes q .. 32*qw - 1 of Z are zero.
+            for (uint32_t t = tid; t < 32 * g.qw; t += nt) {
+                if (t >= q) {
+                    zp[t] = 0u;
+                    continue;
+                }
+                uint32_t z = cp[t] ^ bs_term(cp, t + 1 < q, q + t);
+#pragma unroll
+                for (uint32_t k = 0; k < kMaxTaps; ++k) {
+                    const bool tk = k < sh.n_taps;
+                    const uint32_t f = tk ? sh.taps[k] : 0u;
+                    z ^= bs_term(cp, tk && t >= f, q + t - f);         // (t^f H)[t], t - f <= q - 2
+                    z ^= bs_term(cp, tk && t + 1 < f, 2 * q + t - f);   // U_f[t] in D[t]
+#pragma unroll
+                    for (uint32_t k2 = 0; k2 < kMaxTaps; ++k2) { // U_f[t - g] in (t^g D)[t]
+                        const bool tg = tk && k2 < sh.n_taps;
+                        const uint32_t gg = tg ? sh.taps[k2] : 0u;
+                        z ^= bs_term(cp, tg && t >= gg && t - gg + 1 < f, 2 * q + (t - gg) - f);
+                    }
+                }
+                zp[t] = z;
             }
-        }
-        zp[t] = z;
-    }
-    __syncthreads();
+            __syncthreads();
 
-    // ---- output: lane w transposes planes 32w .. 32w + 31 into word w of
-    // the 32 outputs; then the work-group stores its npw*qb bytes
-    for (uint32_t w = tid; w < qw; w += nt) {
-        uint32_t a[32];
+            // ---- output: lane (pair p, word w) gathers bit p of planes 32w ..
+            // 32w + 31 (the same planes for every pair: broadcast reads, all issued
+            // before the bits are assembled) and stores the word's bytes of pair p's
+            // q/8 output bytes
+            const uint32_t qw = g.qw;
+            for (uint32_t i = tid; i < kBsPairs * qw; i += nt) {
+                const uint32_t w = i / kBsPairs, p = i - w * kBsPairs;
+                uint32_t v = 0;
 #pragma unroll
-        for (uint32_t i = 0; i < 32; ++i) a[i] = 32u * w + i < q ? zp[32u * w + i] : 0u;
-        transpose32(a);  // a[p] = word w of pair p's output
+                for (uint32_t b = 0; b < 32; ++b) v |= ((zp[32u * w + b] >> p) & 1u) << b;
+                if (p >= npw) continue;
+                uint8_t* ob = out + (pair0 + p) * qb + 4u * w;
 #pragma unroll
-        for (uint32_t p = 0; p < 32; ++p) ot[p * qw + w] = a[p];
+                for (uint32_t k = 0; k < 4; ++k)
+                    if (4u * w + k < qb) ob[k] = (uint8_t)(v >> (8u * k));
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < kAcc; ++i) acc[i] = 0u;
+            __syncthreads();  // Z and the sums are read before the next planes overwrite them
+        }
+        if (!more) break;
+        group = next_group;
+        chunk = next_chunk;
+        cur = nxt;
     }
-    __syncthreads();
-    uint8_t* ob = out + pair0 * qb;
-    for (uint32_t i = tid; i < npw * qb; i += nt) {
-        const uint32_t p = i / qb, k = i - p * qb;
-        ob[i] = (uint8_t)(ot[p * qw + (k >> 2)] >> (8u * (k & 3u)));
+}
+
+// Launches one work-group per resident slot (CUs x work-groups per CU at
+// this LDS size, looked up once per device and size), or one per group when
+// there are fewer groups.
+template <uint32_t H, uint32_t L>
+hipError_t launch_one(const BsGeom& g, uint32_t groups, const uint8_t* x, const uint8_t* y,
+                      uint8_t* out, uint64_t n_pairs, const ExtShape& s, hipStream_t stream) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, uint32_t> resident;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint32_t lds = g.total * 4u;
+    const uint64_t key = (uint64_t)(uint32_t)dev << 32 | lds;
+    uint32_t slots = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = resident.find(key);
+        if (it != resident.end()) slots = it->second;
     }
+    if (slots == 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bitslice_kernel<H, L>, kThreads,
+                                                         lds);
+        if (e != hipSuccess) return e;
+        slots = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)(per_cu > 0 ? per_cu : 1);
+        std::lock_guard<std::mutex> lock(mu);
+        resident[key] = slots;
+    }
+    const uint32_t grid = groups < slots ? groups : slots;
+    hipLaunchKernelGGL((bitslice_kernel<H, L>), dim3(grid), dim3(kThreads), lds, stream, x, y, out,
+                       n_pairs, s, g);
+    return hipGetLastError();
+}
+
+// The instantiation for (h, levels), or an error if there is none: every q
+// that is a multiple of 8 up to 128 at each depth bs_search may pick
+// (8 <= h <= 22, except h = q itself below 8).
+hipError_t launch_for(const BsGeom& g, uint32_t groups, const uint8_t* x, const uint8_t* y,
+                      uint8_t* out, uint64_t n_pairs, const ExtShape& s, hipStream_t stream) {
+#define BS_CASE(HH, LL)                                                         \
+    if (g.h == HH && g.levels == LL)                                            \
+        return launch_one<HH, LL>(g, groups, x, y, out, n_pairs, s, stream);
+    BS_CASE(8, 0) BS_CASE(16, 0)
+    BS_CASE(8, 1) BS_CASE(12, 1) BS_CASE(16, 1) BS_CASE(20, 1)
+    BS_CASE(8, 2) BS_CASE(10, 2) BS_CASE(12, 2) BS_CASE(14, 2) BS_CASE(16, 2) BS_CASE(18, 2)
+    BS_CASE(20, 2) BS_CASE(22, 2)
+    BS_CASE(8, 3) BS_CASE(9, 3) BS_CASE(10, 3) BS_CASE(11, 3) BS_CASE(12, 3) BS_CASE(13, 3)
+    BS_CASE(14, 3) BS_CASE(15, 3) BS_CASE(16, 3)
+#undef BS_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* tile_positions,
-                       uint32_t* element_subsets, uint32_t* folded) {
-    const BsGeom g = bs_geom(s.q, s.n_e, kThreads);
+void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* levels,
+                       uint32_t* piece_planes, uint32_t* element_subsets) {
+    const BsGeom g = bs_geom(s.q, s.n_e);
     *chunk_elements = g.ec;
-    *tile_positions = g.n_pos;
+    *levels = g.levels;
+    *piece_planes = g.h;
     *element_subsets = g.subsets;
-    *folded = g.fold;
 }
 
 uint32_t bitslice_lds_words(const ExtShape& s) {
     if (s.q == 0 || s.q % 8 || s.q > kBitsliceMaxQ || s.n_e == 0) return 0xffffffffu;
-    return bs_geom(s.q, s.n_e, kThreads).total;
+    return bs_geom(s.q, s.n_e).total;
 }
 
 hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
@@ -468,20 +642,16 @@ hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y
     if (s.q == 0 || s.q > kBitsliceMaxQ || s.q % 8 || s.n_e == 0) return hipErrorInvalidValue;
     if ((uint64_t)s.nbytes * 8 != (uint64_t)s.q * s.n_e || s.nbytes >= (1u << 23))
         return hipErrorInvalidValue;
-    const BsGeom g = bs_geom(s.q, s.n_e, kThreads);
-    if (g.n_pos > (uint32_t)kThreads || 2 * kBsPairs * g.units > kStageRegs * (uint32_t)kThreads)
+    uint32_t max_tap = 0;
+    for (uint32_t k = 0; k < s.n_taps; ++k) max_tap = s.taps[k] > max_tap ? s.taps[k] : max_tap;
+    if (s.n_taps == 0 || s.n_taps > kMaxTaps || 2 * max_tap > s.q) return hipErrorInvalidValue;
+    const BsGeom g = bs_geom(s.q, s.n_e);
+    if (g.ec == 0 || g.n_sub * g.subsets > (uint32_t)kThreads || g.h << g.levels != s.q)
         return hipErrorInvalidValue;
     const uint64_t groups = (n_pairs + kBsPairs - 1) / kBsPairs;
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-    const uint32_t lds = g.total * 4u;
-    if (lds > 65536u) return hipErrorInvalidValue;
-    if (bs_fold(s.q))
-        hipLaunchKernelGGL(bitslice_kernel<true>, dim3((uint32_t)groups), dim3(kThreads), lds,
-                           stream, x, y, out, n_pairs, s, g);
-    else
-        hipLaunchKernelGGL(bitslice_kernel<false>, dim3((uint32_t)groups), dim3(kThreads), lds,
-                           stream, x, y, out, n_pairs, s, g);
-    return hipGetLastError();
+    if (g.total * 4u > 65536u) return hipErrorInvalidValue;
+    return launch_for(g, (uint32_t)groups, x, y, out, n_pairs, s, stream);
 }
 
 }  // namespace qext

@@ -166,10 +166,11 @@ constexpr uint32_t kProbeOpsPerIter = 16 * 9;  // 8 AND-XORs and 1 funnel shift,
 // is refused above 64 KiB).
 constexpr uint32_t kBitsliceMaxQ = 128;
 uint32_t bitslice_lds_words(const ExtShape& s);
-// Geometry of the bit-sliced kernel for s: elements per chunk, 16x16 tile
-// positions, element subsets, and whether diagonal tiles are folded.
-void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* tile_positions,
-                       uint32_t* element_subsets, uint32_t* folded);
+// Geometry of the bit-sliced kernel for s: elements per chunk, Karatsuba
+// levels over the bit planes, planes per piece (q / 2^levels), and element
+// subsets (lanes per sub-product).
+void bitslice_describe(const ExtShape& s, uint32_t* chunk_elements, uint32_t* levels,
+                       uint32_t* piece_planes, uint32_t* element_subsets);
 hipError_t launch_bitslice(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint8_t* out,
                            uint64_t n_pairs, hipStream_t stream);
 
