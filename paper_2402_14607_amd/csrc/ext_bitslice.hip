@@ -17,21 +17,20 @@
 // (q = 80, L = 2: 9 x 400 = 3600 instead of 6400).  Every lane owns one
 // sub-product and an element subset, keeps its 2h - 1 product planes in
 // registers across all elements (the inner product's sum commutes with the
-// Karatsuba recombination, which therefore runs once per 32 pairs), and
-// forms its operands from the element's planes in LDS (XOR of 1, 2, 4 or 8
-// pieces).  Lanes are ordered by the number of lo+hi digits, so that most
-// waves form their operands from the same number of pieces.
+// Karatsuba recombination, which therefore runs once per 32 pairs).  An
+// operand pass after the transposes writes, per element and side, every
+// operand that XORs two or more pieces next to the raw planes, so that the
+// product lanes only read their two h-plane operands.
 //
 // Transposes.  Item (side, half hp, word w) reads 32-bit word w of the
 // chunk's byte stream of the 16 pairs 16hp .. 16hp + 15 straight from memory
 // (buffer loads, bounds-checked against the work-group's region, so that
 // pairs past the last one read zero), transposes the 16 x 32 bit matrix
 // (both 16 x 16 halves at once) and writes its 16-bit halves of stream
-// planes 32w .. 32w + 31; a wave's 64 items are 64 consecutive words of one
-// side and one half, and the next item's loads are in flight while the
-// current one is transposed.  All elements of a block form one chunk when
-// their planes fit the LDS budget (the paper's point: 71 elements, 46 KB),
-// else the elements are taken in equal chunks.
+// planes 32w .. 32w + 31.  The elements are taken in chunks (the paper's
+// point: 28 elements, one per element subset, 40.5 KB of operand slots);
+// work-groups are persistent over 32-pair groups, and a chunk's rows are
+// loaded into registers while the chunk before it multiplies.
 //
 // After the last chunk the lanes store their sums in LDS, the element
 // subsets' sums are added per sub-product, the sub-products recombined level
@@ -111,24 +110,39 @@ __device__ __forceinline__ uint32_t bs_div(uint32_t n, uint32_t m) {
 }
 
 // Number of lo+hi digits of sub-product s (base-3 digits, 2 = lo+hi).
-__host__ __device__ inline uint32_t bs_sums(uint32_t s, uint32_t levels) {
+__host__ __device__ constexpr uint32_t bs_sums(uint32_t s, uint32_t levels) {
     uint32_t n = 0;
     for (uint32_t l = 0; l < levels; ++l, s /= 3) n += s % 3 == 2 ? 1u : 0u;
     return n;
 }
 
+// Operand slots of one element (one side) in LDS: the 2^L pieces in their
+// natural order (the element's q raw planes), then the 3^L - 2^L operands
+// that XOR two or more pieces, in the order of their sub-product index.
+// Slot of sub-product s, in units of h planes.
+__host__ __device__ constexpr uint32_t bs_slot(uint32_t s, uint32_t levels) {
+    uint32_t piece = 0, sum = 0, rest = s;
+    for (uint32_t b = 0; b < levels; ++b, rest /= 3) {  // digit of level L - b: piece bit b
+        if (rest % 3 == 1) piece |= 1u << b;
+        if (rest % 3 == 2) sum = 1;
+    }
+    if (!sum) return piece;
+    uint32_t k = 0;  // sums among the sub-products before s
+    for (uint32_t t = 0; t < s; ++t) k += bs_sums(t, levels) ? 1u : 0u;
+    return (1u << levels) + k;
+}
+
 // Geometry of a launch for (q, n_e), computed once on the host and passed
 // to the kernel by value.
 struct BsGeom {
-    uint32_t qb, qw, es;       // bytes, words per element; LDS words per element's planes
+    uint32_t qb, qw, es;       // bytes, words per element; LDS words per element's slots
     uint32_t levels, h, n_sub, subsets;
     uint32_t ec;               // elements per chunk (the last chunk may hold fewer)
-    uint32_t xp, yp;           // chunk phase: LDS word offsets of the X and Y planes
+    uint32_t xp, yp;           // chunk phase: LDS word offsets of the X and Y slots
     uint32_t ss;               // end phase: words per lane-sum row [n_sub][2h - 1] (odd)
     uint32_t pa, pb, zp;       // end phase: recombination buffers, Z
     uint32_t total;            // LDS words
     uint32_t rcp_q;            // bs_recip(q)
-    uint8_t order[kMaxSub];    // lane rank -> sub-product (fewest lo+hi digits first)
 };
 
 // The layout of (q, n_e) with L levels and chunks of ec elements.
@@ -136,15 +150,11 @@ BsGeom bs_layout(uint32_t q, uint32_t n_e, uint32_t levels, uint32_t ec) {
     BsGeom g{};
     g.qb = q / 8;
     g.qw = (q + 31) / 32;
-    g.es = q + 1;  // odd: consecutive elements' planes fall in different banks
     g.levels = levels;
     g.h = q >> levels;
     g.n_sub = pow3(levels);
     g.subsets = kThreads / g.n_sub;
-    uint32_t k = 0;
-    for (uint32_t c = 0; c <= levels; ++c)
-        for (uint32_t s = 0; s < g.n_sub; ++s)
-            if (bs_sums(s, levels) == c) g.order[k++] = (uint8_t)s;
+    g.es = (g.n_sub * g.h) | 1u;  // odd: consecutive elements fall in different banks
     g.ec = ec < n_e ? ec : n_e;
     g.xp = 0;
     g.yp = g.ec * g.es;
@@ -164,23 +174,22 @@ BsGeom bs_layout(uint32_t q, uint32_t n_e, uint32_t levels, uint32_t ec) {
 }
 
 // Estimated wave64 instructions issued per 32 pairs of a layout: the
-// product rounds (per active wave, h^2 AND-XORs plus the XORs and, at half
-// weight, the LDS reads forming the operands of the wave's most-pieced
-// lane), the transposes (one wave per 63 words of each side and half of a
-// chunk's stream), and the end phase.
+// product rounds (h^2 AND-XORs and, at half weight, the 2h operand reads of
+// every active wave), the operand pass (per element and side, the XORs of
+// the sum operands and, at half weight, the reads and writes), the
+// transposes (one wave per 63 words of each side and half of a chunk's
+// stream), and the end phase.
 double bs_cost(const BsGeom& g, uint32_t n_e) {
-    double round = 0.0;
     const uint32_t lanes = g.n_sub * g.subsets;
-    for (uint32_t w = 0; w * 64 < lanes; ++w) {
-        const uint32_t last = (w * 64 + 63 < lanes ? w * 64 + 63 : lanes - 1) / g.subsets;
-        const uint32_t pieces = 1u << bs_sums(g.order[last], g.levels);
-        round += g.h * g.h + 2.0 * g.h * (pieces - 1) + g.h * pieces + 16.0;
-    }
+    const double round = ((lanes + 63) / 64) * (g.h * g.h + g.h + 16.0);
     const uint32_t q = g.qb * 8;
+    uint32_t xors = 0;
+    for (uint32_t s = 0; s < g.n_sub; ++s) xors += (1u << bs_sums(s, g.levels)) - 1u;
+    const double per_elem = 2.0 * g.h * (xors + 0.5 * g.n_sub) / 64.0;  // reads + writes
     auto chunk = [&](uint32_t e) {
         const uint32_t words = (e * q + 31) / 32;
-        return ((e + g.subsets - 1) / g.subsets) * round + 4.0 * ((words + 62) / 63) * 240.0 +
-               200.0;
+        return ((e + g.subsets - 1) / g.subsets) * round + e * per_elem +
+               4.0 * ((words + 62) / 63) * 240.0 + 300.0;
     };
     const double end = 4.0 * (2.0 * g.h + 2.0 * g.subsets) + 2.0 * 200.0;
     return (n_e / g.ec) * chunk(g.ec) + (n_e % g.ec ? chunk(n_e % g.ec) : 0.0) + end;
@@ -197,15 +206,13 @@ BsGeom bs_search(uint32_t q, uint32_t n_e) {
     for (uint32_t levels = 0; levels <= kMaxLevels; ++levels) {
         if (q % (1u << levels) || (q >> levels) > kMaxPiece) continue;
         if (levels > 0 && (q >> levels) < 8) break;
-        uint32_t ec = n_e;
-        while (ec > 1 && (bs_layout(q, n_e, levels, ec).total * 4 > kLdsTarget ||
-                          (ec * q + 31) / 32 > 63 * kMaxIpl)) {
-            const uint32_t chunks = (n_e + ec - 1) / ec + 1;
-            ec = (n_e + chunks - 1) / chunks;
+        for (uint32_t ec = 1; ec <= n_e && ec <= 4096; ++ec) {
+            if ((ec * q + 31) / 32 > 63 * kMaxIpl) break;
+            const BsGeom g = bs_layout(q, n_e, levels, ec);
+            if (g.total * 4 > kLdsTarget) break;
+            const double cost = bs_cost(g, n_e);
+            if (!have || cost < best_cost) best = g, best_cost = cost, have = true;
         }
-        const BsGeom g = bs_layout(q, n_e, levels, ec);
-        const double cost = bs_cost(g, n_e);
-        if (!have || cost < best_cost) best = g, best_cost = cost, have = true;
     }
     return best;
 }
@@ -336,18 +343,33 @@ __device__ __forceinline__ void bs_put_task(const BsTask& t, uint32_t nbytes, ui
     }
 }
 
-// Piece offset (planes) of combination c of a sub-product whose lo+hi
-// levels are the set bits of summask: bit i of c selects the i-th of them.
+// The operand pass for one position (element, plane i) of one side: reads
+// the 2^L pieces' plane i and writes plane i of every operand that XORs two
+// or more of them (base points at plane i of the element's slots).  Piece p
+// belongs to sub-product s when each of s's lo/hi digits matches p's bit.
 template <uint32_t H, uint32_t L>
-__device__ __forceinline__ uint32_t bs_piece_off(uint32_t p0, uint32_t summask, uint32_t c) {
-    uint32_t p = p0;
+__device__ __forceinline__ void bs_form(uint32_t* base) {
+    constexpr uint32_t kPieces = 1u << L;
+    uint32_t pc[kPieces];
 #pragma unroll
-    for (uint32_t b = 0; b < L; ++b)
-        if (summask >> b & 1u) {
-            if (c & 1u) p |= 1u << b;
-            c >>= 1;
+    for (uint32_t p = 0; p < kPieces; ++p) pc[p] = base[p * H];
+#pragma unroll
+    for (uint32_t s = 0; s < pow3(L); ++s) {
+        if (bs_sums(s, L) == 0) continue;
+        uint32_t v = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kPieces; ++p) {
+            bool match = true;
+            uint32_t rest = s;
+#pragma unroll
+            for (uint32_t b = 0; b < L; ++b, rest /= 3) {
+                if (rest % 3 == 0 && (p >> b & 1u)) match = false;
+                if (rest % 3 == 1 && !(p >> b & 1u)) match = false;
+            }
+            if (match) v ^= pc[p];
         }
-    return p * H;
+        base[bs_slot(s, L) * H] = v;
+    }
 }
 
 // cp[idx] if on, else 0, reading cp[0] instead: the read is always in range.
@@ -376,22 +398,11 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     const uint32_t n_groups = (uint32_t)((n_pairs + kBsPairs - 1) / kBsPairs);
     const uint32_t n_chunks = (n_e + ec - 1) / ec;
 
-    // Lane (rank, element subset): sub-product s = order[rank], whose operand
-    // is the XOR of the pieces p0 + (any subset of the lo+hi levels' bits);
-    // piece i covers planes i*H .. i*H + H - 1 (level 1 is the top bit).
-    const uint32_t rank = tid / kSubsets, sub = tid - rank * kSubsets;
-    const bool active = rank < kSub;
-    const uint32_t s = active ? g.order[rank] : 0u;
-    uint32_t p0 = 0, summask = 0, pieces = 1;
-    {
-        uint32_t rest = s;
-#pragma unroll
-        for (uint32_t b = 0; b < L; ++b, rest /= 3) {  // digit of level L - b: piece bit b
-            const uint32_t d = rest % 3;
-            if (d == 1) p0 |= 1u << b;
-            if (d == 2) summask |= 1u << b, pieces <<= 1;
-        }
-    }
+    // Lane (sub-product s, element subset): its operands are slot bs_slot(s)
+    // of each element of X and Y
+    const uint32_t s = tid / kSubsets, sub = tid - s * kSubsets;
+    const bool active = s < kSub;
+    const uint32_t off0 = active ? bs_slot(s, L) * H : 0u;
     uint32_t acc[kAcc];
 #pragma unroll
     for (uint32_t i = 0; i < kAcc; ++i) acc[i] = 0u;
@@ -409,6 +420,16 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     for (;;) {
         bs_put_task<kMaxIpl>(cur, nbytes, wave, lane, rows, xp, yp, es, q, g.rcp_q);
         __syncthreads();
+        const uint32_t e_cnt = cur.bits / q;
+        if constexpr (L > 0) {
+            // ---- operand pass: the sum operands of every element and side
+            for (uint32_t pos = tid; pos < e_cnt * H; pos += nt) {
+                const uint32_t e = pos / H, i = pos - e * H;
+                bs_form<H, L>(xp + e * es + i);
+                bs_form<H, L>(yp + e * es + i);
+            }
+            __syncthreads();
+        }
         const bool last_chunk = chunk + 1 == n_chunks;
         const uint32_t next_group = last_chunk ? group + gridDim.x : group;
         const uint32_t next_chunk = last_chunk ? 0u : chunk + 1;
@@ -419,27 +440,15 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
             bs_load_task<kMaxIpl>(nxt, nbytes, wave, lane, rows);
         }
         // ---- products: the lane's sub-product over its elements of the chunk
-        const uint32_t e_cnt = cur.bits / q;
 #pragma unroll 1
         for (uint32_t le = active ? sub : e_cnt; le < e_cnt; le += kSubsets) {
-            const uint32_t* xe = xp + le * es;
-            const uint32_t* ye = yp + le * es;
+            const uint32_t* xe = xp + le * es + off0;
+            const uint32_t* ye = yp + le * es + off0;
             uint32_t xv[H], yv[H];
-            const uint32_t off0 = p0 * H;
 #pragma unroll
-            for (uint32_t i = 0; i < H; ++i) xv[i] = xe[off0 + i];
+            for (uint32_t i = 0; i < H; ++i) xv[i] = xe[i];
 #pragma unroll
-            for (uint32_t i = 0; i < H; ++i) yv[i] = ye[off0 + i];
-            if constexpr (L > 0) {
-#pragma unroll 1
-                for (uint32_t pc = 1; pc < pieces; ++pc) {
-                    const uint32_t off = bs_piece_off<H, L>(p0, summask, pc);
-#pragma unroll
-                    for (uint32_t i = 0; i < H; ++i) xv[i] ^= xe[off + i];
-#pragma unroll
-                    for (uint32_t i = 0; i < H; ++i) yv[i] ^= ye[off + i];
-                }
-            }
+            for (uint32_t i = 0; i < H; ++i) yv[i] = ye[i];
 #pragma unroll
             for (uint32_t kk = 0; kk < H; ++kk)
 #pragma unroll
