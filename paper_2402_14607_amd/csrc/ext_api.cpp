@@ -243,13 +243,21 @@ bool bitslice_applies(const ExtShape& s) {
 }
 
 // EXT_KERNEL_AUTO's choice without autotuning, among the shapes the
-// bit-sliced kernel applies to: fields of 16 to 128 bits that 16 divides
-// (whole 16x16 product tiles) with at least 30 elements per block.  Measured
-// on MI355X over 19 shapes from (80, 4) to (128, 100): in this region it is
-// 1.0x (q = 128 at 40 elements) to 3.2x faster than the word-level kernel;
-// outside it the word-level kernel was faster or within 2%.
+// bit-sliced kernel applies to: enough elements per block to amortize its
+// per-group end phase.  Measured on MI355X over q = 16 .. 128 (step 8) and
+// n_e in {2, 4, 8, 16, 30, 71, 150}: at the counts at or above these it was
+// 1.17-3.8x as fast as the word-level kernel, below them 0.15-1.14x; fields
+// that are whole 32-bit words (which the word-level kernel takes unpadded)
+// need the most elements.
 bool bitslice_preferred(const ExtShape& s) {
-    return s.q % 16 == 0 && s.q >= 16 && s.q <= 128 && s.n_e >= 30;
+    if (s.q < 16 || s.q > 128 || s.q % 8) return false;
+    uint32_t min_ne;
+    if (s.q == 32) min_ne = 100;
+    else if (s.q % 32 == 0) min_ne = 64;  // 64, 96, 128
+    else if (s.q < 40) min_ne = 40;   // 16, 24
+    else if (s.q < 64) min_ne = 24;   // 40, 48, 56
+    else min_ne = 16;                 // 72 .. 120 except 96
+    return s.n_e >= min_ne;
 }
 
 // The launch plan of (n_bits, m_bits, taps) for ext_params.kernel `kernel`

@@ -51,10 +51,10 @@ namespace {
 constexpr uint32_t kBsPairs = 32;      // pairs per work-group (bits of a plane)
 constexpr uint32_t kMaxLevels = 3;
 constexpr uint32_t kMaxSub = 27;       // 3^kMaxLevels
-constexpr uint32_t kMaxPiece = 22;     // largest piece size h (registers: 4h - 1 per lane)
+constexpr uint32_t kMaxPiece = 20;     // largest piece size h (registers: 4h - 1 per lane)
 constexpr uint32_t kLdsTarget = 53248;  // three work-groups on a CU's 160 KiB
 constexpr uint32_t kMaxTaps = 3;
-constexpr uint32_t kMaxIpl = 3;        // transpose items per lane per chunk (held in registers)
+constexpr uint32_t kMaxIpl = 2;        // transpose items per lane per chunk (held in registers)
 // third word of a buffer resource: 32-bit data format, no swizzle, stride 0
 constexpr int kBufferConfig = 0x00020000;
 
@@ -177,7 +177,7 @@ BsGeom bs_layout(uint32_t q, uint32_t n_e, uint32_t levels, uint32_t ec) {
 // product rounds (h^2 AND-XORs and, at half weight, the 2h operand reads of
 // every active wave), the operand pass (per element and side, the XORs of
 // the sum operands and, at half weight, the reads and writes), the
-// transposes (one wave per 63 words of each side and half of a chunk's
+// transposes (one wave per 64 words of each side and half of a chunk's
 // stream), and the end phase.
 double bs_cost(const BsGeom& g, uint32_t n_e) {
     const uint32_t lanes = g.n_sub * g.subsets;
@@ -189,7 +189,7 @@ double bs_cost(const BsGeom& g, uint32_t n_e) {
     auto chunk = [&](uint32_t e) {
         const uint32_t words = (e * q + 31) / 32;
         return ((e + g.subsets - 1) / g.subsets) * round + e * per_elem +
-               4.0 * ((words + 62) / 63) * 240.0 + 300.0;
+               4.0 * ((words + 63) / 64) * 200.0 + 300.0;
     };
     const double end = 4.0 * (2.0 * g.h + 2.0 * g.subsets) + 2.0 * 200.0;
     return (n_e / g.ec) * chunk(g.ec) + (n_e % g.ec ? chunk(n_e % g.ec) : 0.0) + end;
@@ -207,7 +207,7 @@ BsGeom bs_search(uint32_t q, uint32_t n_e) {
         if (q % (1u << levels) || (q >> levels) > kMaxPiece) continue;
         if (levels > 0 && (q >> levels) < 8) break;
         for (uint32_t ec = 1; ec <= n_e && ec <= 4096; ++ec) {
-            if ((ec * q + 31) / 32 > 63 * kMaxIpl) break;
+            if ((ec * q + 31) / 32 > 64 * kMaxIpl) break;
             const BsGeom g = bs_layout(q, n_e, levels, ec);
             if (g.total * 4 > kLdsTarget) break;
             const double cost = bs_cost(g, n_e);
@@ -230,11 +230,10 @@ BsGeom bs_geom(uint32_t q, uint32_t n_e) {
 
 // One task (a chunk of one 32-pair group) as the transposes see it.  The
 // chunk's byte stream of each side and half (pairs 16*half .. 16*half + 15)
-// is cut into waves of 63 words: lane l < 63 of item-wave (side, half, j)
-// transposes word w = 63j + l, lane 63 loads word 63j + 63 only to hand it
-// to lane 62.  Item-wave iw = wave + 4m (m < nw) of the work-group's four
-// waves has (side, half) = iw / nw and j = iw mod nw, so every lane holds nw
-// items, nw <= kMaxIpl.
+// is cut into waves of 64 words: lane l of item-wave (side, half, j)
+// transposes word w = 64j + l.  Item-wave iw = wave + 4m (m < nw) of the
+// work-group's four waves has (side, half) = iw / nw and j = iw mod nw, so
+// every lane holds nw items, nw <= kMaxIpl.
 struct BsTask {
     const uint8_t* base_x;  // dword holding the first byte of each side's region
     const uint8_t* base_y;
@@ -262,7 +261,7 @@ __device__ __forceinline__ BsTask bs_task(const uint8_t* x, const uint8_t* y, ui
     t.eoff = chunk * ec * (q / 8);
     t.bits = e_cnt * q;
     t.words = (t.bits + 31) / 32;
-    t.nw = (t.words + 62) / 63;
+    t.nw = (t.words + 63) / 64;
     return t;
 }
 
@@ -272,13 +271,16 @@ __device__ __forceinline__ uint32_t bs_row(const BsTask& t, uint32_t nbytes, boo
     return (side_y ? t.lead_y : t.lead_x) + (hf * 16u + p) * nbytes + t.eoff;
 }
 
-// Loads the task's items into r: for each row, the dword word w starts in,
-// from a buffer that starts at the row's first dword (the lanes' offsets
-// are just 4w).  The buffer is bounds-checked against the region's end, so
-// rows of pairs past the last read zero.
+// Loads the task's items: for each row, the two dwords that word w
+// straddles, one 8-byte load from a buffer that starts at the row's first
+// dword (the lanes' offsets are just 4w).  The buffer is bounds-checked per
+// dword against the region's end, so rows of pairs past the last read zero
+// and a pair of dwords whose second one lies past the end still returns the
+// first.
 template <uint32_t IPL>
 __device__ __forceinline__ void bs_load_task(const BsTask& t, uint32_t nbytes, uint32_t wave,
-                                             uint32_t lane, uint32_t (&r)[IPL][16]) {
+                                             uint32_t lane, uint32_t (&lo)[IPL][16],
+                                             uint32_t (&hi)[IPL][16]) {
 #pragma unroll
     for (uint32_t m = 0; m < IPL; ++m) {
         if (m >= t.nw) break;
@@ -287,7 +289,7 @@ __device__ __forceinline__ void bs_load_task(const BsTask& t, uint32_t nbytes, u
         const bool side_y = (sh2 >> 1) != 0;
         const uint8_t* base = side_y ? t.base_y : t.base_x;
         const uint32_t nrec = side_y ? t.nrec_y : t.nrec_x;
-        const uint32_t w = 63u * j + lane;
+        const uint32_t w = 64u * j + lane;
 #pragma unroll
         for (uint32_t p = 0; p < 16; ++p) {
             // row start and length as scalars (the resource must be uniform)
@@ -296,18 +298,20 @@ __device__ __forceinline__ void bs_load_task(const BsTask& t, uint32_t nbytes, u
             const uint32_t n = __builtin_amdgcn_readfirstlane(nrec > rs ? nrec - rs : 0u);
             const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(base + rs), (short)0, (int)n, kBufferConfig);
-            r[m][p] = __builtin_amdgcn_raw_buffer_load_b32(res, 4u * w, 0, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(res, 4u * w, 0, 0);
+            lo[m][p] = v[0];
+            hi[m][p] = v[1];
         }
     }
 }
 
 // Transposes the task's items and writes their 16-bit halves of stream
 // planes 32w .. 32w + 31 (plane b is bit b mod q of element b / q) in
-// groups of 8 (q is a multiple of 8).  A row's word straddles the lane's
-// dword and the next lane's (DPP wave shift: lane l reads lane l + 1).
+// groups of 8 (q is a multiple of 8).
 template <uint32_t IPL>
 __device__ __forceinline__ void bs_put_task(const BsTask& t, uint32_t nbytes, uint32_t wave,
-                                            uint32_t lane, const uint32_t (&r)[IPL][16],
+                                            uint32_t lane, const uint32_t (&lo)[IPL][16],
+                                            const uint32_t (&hi)[IPL][16],
                                             uint32_t* xp, uint32_t* yp, uint32_t es, uint32_t q,
                                             uint32_t rcp_q) {
 #pragma unroll
@@ -316,15 +320,14 @@ __device__ __forceinline__ void bs_put_task(const BsTask& t, uint32_t nbytes, ui
         const uint32_t iw = wave + 4u * m;
         const uint32_t sh2 = iw / t.nw, j = iw - sh2 * t.nw;
         const bool side_y = (sh2 >> 1) != 0;
-        const uint32_t w = 63u * j + lane;
+        const uint32_t w = 64u * j + lane;
         uint32_t a[16];
 #pragma unroll
         for (uint32_t p = 0; p < 16; ++p) {
-            const uint32_t next = __builtin_amdgcn_update_dpp(0u, r[m][p], 0x130, 0xf, 0xf, false);
             const uint32_t row = bs_row(t, nbytes, side_y, sh2 & 1u, p);
-            a[p] = __builtin_amdgcn_alignbit(next, r[m][p], (row & 3u) * 8u);
+            a[p] = __builtin_amdgcn_alignbit(hi[m][p], lo[m][p], (row & 3u) * 8u);
         }
-        if (lane == 63 || w >= t.words) continue;
+        if (w >= t.words) continue;
         transpose16(a);  // a[i]: plane i (low half), plane 16 + i (high half)
         uint16_t* planes = reinterpret_cast<uint16_t*>(side_y ? yp : xp) + (sh2 & 1u);
 #pragma unroll
@@ -413,12 +416,12 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     // reduces and stores), so that its transposes find them there.
     uint32_t group = blockIdx.x, chunk = 0;
     if (group >= n_groups) return;
-    uint32_t rows[kMaxIpl][16];
+    uint32_t rows_lo[kMaxIpl][16], rows_hi[kMaxIpl][16];
     BsTask cur = bs_task(x, y, n_pairs, nbytes, q, ec, n_e, group, chunk);
-    bs_load_task<kMaxIpl>(cur, nbytes, wave, lane, rows);
+    bs_load_task<kMaxIpl>(cur, nbytes, wave, lane, rows_lo, rows_hi);
 #pragma unroll 1
     for (;;) {
-        bs_put_task<kMaxIpl>(cur, nbytes, wave, lane, rows, xp, yp, es, q, g.rcp_q);
+        bs_put_task<kMaxIpl>(cur, nbytes, wave, lane, rows_lo, rows_hi, xp, yp, es, q, g.rcp_q);
         __syncthreads();
         const uint32_t e_cnt = cur.bits / q;
         if constexpr (L > 0) {
@@ -437,7 +440,7 @@ bitslice_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
         BsTask nxt = cur;
         if (more) {
             nxt = bs_task(x, y, n_pairs, nbytes, q, ec, n_e, next_group, next_chunk);
-            bs_load_task<kMaxIpl>(nxt, nbytes, wave, lane, rows);
+            bs_load_task<kMaxIpl>(nxt, nbytes, wave, lane, rows_lo, rows_hi);
         }
         // ---- products: the lane's sub-product over its elements of the chunk
 #pragma unroll 1
@@ -613,7 +616,7 @@ hipError_t launch_one(const BsGeom& g, uint32_t groups, const uint8_t* x, const 
 
 // The instantiation for (h, levels), or an error if there is none: every q
 // that is a multiple of 8 up to 128 at each depth bs_search may pick
-// (8 <= h <= 22, except h = q itself below 8).
+// (8 <= h <= 20, except h = q itself below 8).
 hipError_t launch_for(const BsGeom& g, uint32_t groups, const uint8_t* x, const uint8_t* y,
                       uint8_t* out, uint64_t n_pairs, const ExtShape& s, hipStream_t stream) {
 #define BS_CASE(HH, LL)                                                         \
@@ -622,7 +625,7 @@ hipError_t launch_for(const BsGeom& g, uint32_t groups, const uint8_t* x, const 
     BS_CASE(8, 0) BS_CASE(16, 0)
     BS_CASE(8, 1) BS_CASE(12, 1) BS_CASE(16, 1) BS_CASE(20, 1)
     BS_CASE(8, 2) BS_CASE(10, 2) BS_CASE(12, 2) BS_CASE(14, 2) BS_CASE(16, 2) BS_CASE(18, 2)
-    BS_CASE(20, 2) BS_CASE(22, 2)
+    BS_CASE(20, 2)
     BS_CASE(8, 3) BS_CASE(9, 3) BS_CASE(10, 3) BS_CASE(11, 3) BS_CASE(12, 3) BS_CASE(13, 3)
     BS_CASE(14, 3) BS_CASE(15, 3) BS_CASE(16, 3)
 #undef BS_CASE

@@ -216,9 +216,11 @@ def test_auto_choice(dev):
     gives the oracle's bytes."""
     import torch
 
-    for n_e, want in ((71, "bitslice"), (4, "word"), (40, "bitslice")):
-        with binding.Extractor(80 * n_e, 80) as ex:
-            assert json.loads(ex.describe())["kernel"] == want, n_e
+    for m, n_e, want in ((80, 71, "bitslice"), (80, 4, "word"), (80, 16, "bitslice"),
+                         (128, 40, "word"), (128, 64, "bitslice"), (24, 30, "word"),
+                         (24, 40, "bitslice"), (48, 24, "bitslice"), (48, 16, "word")):
+        with binding.Extractor(m * n_e, m) as ex:
+            assert json.loads(ex.describe())["kernel"] == want, (m, n_e)
     w = inputs.plain_workload(5680, 80, 45, 63, 64)
     with binding.Extractor(5680, 80, device_memory=True, autotune=True,
                            stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
