@@ -231,7 +231,9 @@ BsGeom bs_geom(uint32_t q, uint32_t n_e) {
 // One task (a chunk of one 32-pair group) as the transposes see it.  The
 // chunk's byte stream of each side and half (pairs 16*half .. 16*half + 15)
 // is cut into waves of 64 words: lane l of item-wave (side, half, j)
-// transposes word w = 64j + l.  Item-wave iw = wave + 4m (m < nw) of the
+// transposes word w = 64j + 2(l mod 32) + l / 32 (each half-wave takes every
+// other word, which spreads its 16-bit plane stores over about twice as many
+// LDS banks as consecutive words would).  Item-wave iw = wave + 4m (m < nw) of the
 // work-group's four waves has (side, half) = iw / nw and j = iw mod nw, so
 // every lane holds nw items, nw <= kMaxIpl.
 struct BsTask {
@@ -289,7 +291,7 @@ __device__ __forceinline__ void bs_load_task(const BsTask& t, uint32_t nbytes, u
         const bool side_y = (sh2 >> 1) != 0;
         const uint8_t* base = side_y ? t.base_y : t.base_x;
         const uint32_t nrec = side_y ? t.nrec_y : t.nrec_x;
-        const uint32_t w = 64u * j + lane;
+        const uint32_t w = 64u * j + 2u * (lane & 31u) + (lane >> 5);
 #pragma unroll
         for (uint32_t p = 0; p < 16; ++p) {
             // row start and length as scalars (the resource must be uniform)
@@ -320,7 +322,7 @@ __device__ __forceinline__ void bs_put_task(const BsTask& t, uint32_t nbytes, ui
         const uint32_t iw = wave + 4u * m;
         const uint32_t sh2 = iw / t.nw, j = iw - sh2 * t.nw;
         const bool side_y = (sh2 >> 1) != 0;
-        const uint32_t w = 64u * j + lane;
+        const uint32_t w = 64u * j + 2u * (lane & 31u) + (lane >> 5);
         uint32_t a[16];
 #pragma unroll
         for (uint32_t p = 0; p < 16; ++p) {
