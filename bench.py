@@ -478,21 +478,22 @@ def growing_online(dev, stream, k=320, chunk=1 << 18):
     out = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
     def feed(g):
         st = g.open_stream()
+        xa, ya, oa = x.data_ptr(), y.data_ptr(), out.data_ptr()  # device addresses
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pos, got = 0, 0
         while pos < n_bytes:
             c = min(chunk, n_bytes - pos)
-            rc = st.submit(x[pos:pos + c], c, y[pos:pos + c], c)
+            rc = st.submit(xa + pos, c, ya + pos, c)
             if rc == binding.EXT_EAGAIN:
-                n, _ = st.poll(out[got:], out_bytes - got, wait=True)
+                n, _ = st.poll(oa + got, out_bytes - got, wait=True)
                 got += n
                 continue
             pos += c
-            n, _ = st.poll(out[got:], out_bytes - got)
+            n, _ = st.poll(oa + got, out_bytes - got)
             got += n
         while got < out_bytes:
-            n, _ = st.poll(out[got:], out_bytes - got, wait=True)
+            n, _ = st.poll(oa + got, out_bytes - got, wait=True)
             assert n, "growing stream returned fewer bytes than m_k"
             got += n
         sec = time.perf_counter() - t0

@@ -221,10 +221,13 @@ int ext_growing_submit(ext_growing_stream *s, const void *x, size_t x_len, const
 /* Non-blocking: copy finished outputs into out (host or device memory per
  * mem_kind), whole blocks only, in block order, at most out_cap bytes;
  * *out_len: bytes written; *blocks_done (may be NULL): blocks returned so far
- * over the stream's life. */
+ * over the stream's life.  Device memory on the caller's HIP stream
+ * (use_hip_stream): the copies are queued on that stream and complete in its
+ * order; otherwise they are complete when the call returns. */
 int ext_growing_poll(ext_growing_stream *s, void *out, size_t out_cap, size_t *out_len,
                      uint64_t *blocks_done);
-/* As ext_growing_poll, but first waits for every launched block. */
+/* As ext_growing_poll, but first waits for every launched block, and
+ * returns after its copies are complete. */
 int ext_growing_drain(ext_growing_stream *s, void *out, size_t out_cap, size_t *out_len,
                       uint64_t *blocks_done);
 /* Algorithm 2's state: the next block l, its degree q_l, and the bytes per

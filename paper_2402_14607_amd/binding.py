@@ -265,7 +265,10 @@ def is_irreducible(m_bits: int, taps) -> bool:
 
 
 def _ptr(buf) -> int:
-    """Raw address of a torch tensor or numpy array."""
+    """Raw address of a torch tensor or numpy array (an int is taken as an
+    address already)."""
+    if isinstance(buf, int):
+        return buf
     if hasattr(buf, "data_ptr"):
         return buf.data_ptr()
     if isinstance(buf, np.ndarray):

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqrngext.so")
 SOURCES = ["ext_kernels.hip", "ext_api.cpp", "ext_batch.cpp", "ext_server.cpp", "serve_sim.cpp",
            "gf2_modulus.cpp", "ext_params.cpp", "ext_growing.cpp",
-           "ext_bitslice.hip", "ext_noalloc.hip"]
+           "ext_bitslice.hip", "ext_noalloc.hip", "ext_copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

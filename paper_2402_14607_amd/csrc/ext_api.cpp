@@ -32,12 +32,14 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
     const uint32_t target = knobs.base_words ? knobs.base_words : 8u;
     if (target > (uint32_t)kMaxBaseWords) return false;
     // Word-aligned elements are multiplied in place when their word count has
-    // an odd part the base products cover (<= 15).  Otherwise (q not a
+    // an odd part the base products cover (<= 15, or knobs.max_odd).  Otherwise (q not a
     // multiple of 32, or such a word count, or asked for) elements are
     // computed in zero-padded slots of qw words, the least count >= q/32
     // whose odd part is covered: the product of padded operands is the same
     // polynomial.
-    auto odd_ok = [](uint32_t w) { return (w >> __builtin_ctz(w)) <= 15u; };
+    const uint32_t max_odd = knobs.max_odd ? knobs.max_odd : 15u;
+    if (max_odd > 15u) return false;
+    auto odd_ok = [&](uint32_t w) { return (w >> __builtin_ctz(w)) <= max_odd; };
     uint32_t qw = (q + 31) / 32;
     const bool padded = (q % 32) != 0 || knobs.padded != 0 || !odd_ok(qw);
     while (!odd_ok(qw)) ++qw;

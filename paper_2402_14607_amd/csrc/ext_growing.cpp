@@ -149,7 +149,11 @@ int plan_for(ext_growing* g, uint32_t q, DegreePlan* out) {
     }
     std::vector<uint32_t> taps;
     if (!qext::default_modulus(q, &taps)) return EXT_ENOTSUP;
-    qext::PlanKnobs knobs{g->params.base_bits / 32, 0, 0, g->params.threads, 1};
+    // odd parts up to 7: base products of at most 8 words.  A block is one
+    // pair, so a call is bound by the longest lane's chain of AND-XORs; over
+    // q = 80 .. 5184 this padding rule also does slightly less work in total
+    // than odd parts up to 15 (deeper Karatsuba makes up for the padding).
+    qext::PlanKnobs knobs{g->params.base_bits / 32, 0, 0, g->params.threads, 1, 7};
     DegreePlan d;
     d.whole_ok = qext::plan_shape(q, g->n_e, taps.data(), (uint32_t)taps.size(), knobs, &d.whole);
     // slices: the degree's geometry for one element, then the block's n_e
@@ -437,22 +441,70 @@ int plan_blocks(ext_growing* g, uint64_t q0, uint64_t k, const uint8_t* xs, cons
     return EXT_OK;
 }
 
-// Queue a planned call on g->stream: its tables (read from host memory at
-// streams_src, tiles_src and jobs_src, which must stay untouched until the
-// copies have run) and zeroed queue heads into tab, then the launches on the
-// lanes, forked from and joined back into g->stream, then the combine step of
-// the sliced blocks on g->stream (their parts in g->d_part).  On a HIP error
-// the work queued so far is waited for and the handle's sticky error set.
+// Queue a planned call's launches on g->stream, its tables and zeroed queue
+// heads already queued into tab: the costliest launch on g->stream itself,
+// the others (one per further base size) on lanes forked from it at this
+// point, each on the least loaded one, joined back before the combine step
+// of the sliced blocks (their parts in g->d_part), which runs on g->stream.
+// A call with one launch needs no fork or join.  On a HIP error the work
+// queued so far is waited for and the handle's sticky error set.
+int device_error(ext_growing* g) {
+    for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
+    (void)hipStreamSynchronize(g->stream);
+    (void)hipGetLastError();
+    return g->sticky = EXT_EDEVICE;
+}
+
+int queue_launches(ext_growing* g, const Planned& p, const Tables& tab) {
+    std::vector<size_t> order(p.launches.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
+        return p.launches[a].cost > p.launches[c].cost;
+    });
+    if (order.size() > 1 && hipEventRecord(g->fork, g->stream) != hipSuccess)
+        return device_error(g);
+    // lane 0 is g->stream, lane l > 0 is g->lanes[l - 1]
+    uint64_t load[ext_growing::kLanes + 1] = {};
+    bool used[ext_growing::kLanes + 1] = {};
+    for (size_t i : order) {
+        const LaunchPlan& ln = p.launches[i];
+        int lane = 0;
+        for (int l = 1; l <= ext_growing::kLanes; ++l)
+            if (load[l] < load[lane]) lane = l;
+        hipStream_t st = lane ? g->lanes[lane - 1] : g->stream;
+        if (lane && !used[lane] && hipStreamWaitEvent(st, g->fork, 0) != hipSuccess)
+            return device_error(g);
+        used[lane] = true;
+        load[lane] += ln.cost + 1;
+        if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams, tab.tiles + ln.off,
+                                       ln.n, tab.heads + i, g->d_part, ln.grid, ln.lds,
+                                       st) != hipSuccess)
+            return device_error(g);
+    }
+    for (int l = 1; l <= ext_growing::kLanes; ++l) {
+        if (!used[l]) continue;
+        if (hipEventRecord(g->joins[l - 1], g->lanes[l - 1]) != hipSuccess ||
+            hipStreamWaitEvent(g->stream, g->joins[l - 1], 0) != hipSuccess)
+            return device_error(g);
+    }
+    if (!p.jobs.empty()) {
+        int cus = 1;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(p.jobs.size(), (uint64_t)cus * 4);
+        if (qext::launch_combine_padded(tab.streams, tab.jobs, (uint32_t)p.jobs.size(), g->d_part,
+                                        grid, p.combine_lds, g->stream) != hipSuccess)
+            return device_error(g);
+    }
+    return EXT_OK;
+}
+
+// Queue a planned call on g->stream: copies of its tables (read from host
+// memory at streams_src, tiles_src and jobs_src, which must stay untouched
+// until the copies have run) and of zeroed queue heads into tab, then its
+// launches (queue_launches).
 int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void* streams_src,
                  const void* tiles_src, const void* jobs_src) {
-    auto device_error = [&]() {
-        for (int i = 0; i < ext_growing::kLanes; ++i) (void)hipStreamSynchronize(g->lanes[i]);
-        (void)hipStreamSynchronize(g->stream);
-        (void)hipGetLastError();
-        return g->sticky = EXT_EDEVICE;
-    };
-    // the tables and the launches' zeroed queue heads, in stream order
-    // before the lanes fork (a copy, so that no launch needs a reset kernel)
+    // the queue heads are zeroed by a copy, so that no launch needs a reset kernel
     static const uint32_t kZeroHeads[kMaxGroups] = {};
     if (hipMemcpyAsync(tab.streams, streams_src, p.streams.size() * sizeof(BatchStream),
                        hipMemcpyHostToDevice, g->stream) ||
@@ -463,47 +515,8 @@ int queue_blocks(ext_growing* g, const Planned& p, const Tables& tab, const void
                         hipMemcpyHostToDevice, g->stream)) ||
         hipMemcpyAsync(tab.heads, kZeroHeads, p.launches.size() * sizeof(uint32_t),
                        hipMemcpyHostToDevice, g->stream))
-        return device_error();
-    // fork: the lanes start after the table copies (and the caller's work
-    // queued before this call); costliest launches first, each on the
-    // least loaded lane; join: the stream waits for every lane used
-    if (hipEventRecord(g->fork, g->stream) != hipSuccess) return device_error();
-    std::vector<size_t> order(p.launches.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
-        return p.launches[a].cost > p.launches[c].cost;
-    });
-    uint64_t load[ext_growing::kLanes] = {};
-    bool used[ext_growing::kLanes] = {};
-    for (size_t i : order) {
-        const LaunchPlan& ln = p.launches[i];
-        int lane = 0;
-        for (int l = 1; l < ext_growing::kLanes; ++l)
-            if (load[l] < load[lane]) lane = l;
-        if (!used[lane] && hipStreamWaitEvent(g->lanes[lane], g->fork, 0) != hipSuccess)
-            return device_error();
-        used[lane] = true;
-        load[lane] += ln.cost + 1;
-        if (qext::launch_batch_noreset(ln.bw, ln.threads, true, tab.streams, tab.tiles + ln.off,
-                                       ln.n, tab.heads + i, g->d_part, ln.grid, ln.lds,
-                                       g->lanes[lane]) != hipSuccess)
-            return device_error();
-    }
-    for (int l = 0; l < ext_growing::kLanes; ++l) {
-        if (!used[l]) continue;
-        if (hipEventRecord(g->joins[l], g->lanes[l]) != hipSuccess ||
-            hipStreamWaitEvent(g->stream, g->joins[l], 0) != hipSuccess)
-            return device_error();
-    }
-    if (!p.jobs.empty()) {
-        int cus = 1;
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(p.jobs.size(), (uint64_t)cus * 4);
-        if (qext::launch_combine_padded(tab.streams, tab.jobs, (uint32_t)p.jobs.size(), g->d_part,
-                                        grid, p.combine_lds, g->stream) != hipSuccess)
-            return device_error();
-    }
-    return EXT_OK;
+        return device_error(g);
+    return queue_launches(g, p, tab);
 }
 
 // Blocks 0 .. k-1 of x and y into out (ext_growing_extract); the launch
@@ -612,9 +625,11 @@ namespace {
 
 constexpr uint64_t kMaxLaunchBlocks = 1024;  // blocks per queued call
 constexpr uint64_t kMaxLaunchTiles = 16384;  // tiles per queued call (slices count each)
-constexpr size_t kTilesOff = qext::round256(kMaxLaunchBlocks * sizeof(BatchStream));
-constexpr size_t kJobsOff = kTilesOff + qext::round256(kMaxLaunchTiles * sizeof(BatchTile));
-constexpr size_t kTableBytes = kJobsOff + qext::round256(kMaxLaunchBlocks * sizeof(CombineJob));
+constexpr size_t round16(size_t v) { return (v + 15) / 16 * 16; }
+// the largest table set of one call, packed: streams, tiles, jobs
+constexpr size_t kTableBytes = round16(kMaxLaunchBlocks * sizeof(BatchStream)) +
+                               round16(kMaxLaunchTiles * sizeof(BatchTile)) +
+                               round16(kMaxLaunchBlocks * sizeof(CombineJob));
 
 // One queued call of the online form: k blocks from block0 (degree q0), their
 // outputs at monotonic ring position opos.
@@ -649,14 +664,18 @@ struct ext_growing_stream {
     // device launch tables (queued calls run in stream order, so one set)
     uint8_t* dtab = nullptr;
     uint32_t* dheads = nullptr;
-    // pinned copies of the tables, two sets, each reused once its copy ran
+    // the tables packed in pinned, coherent host memory, read by the staging
+    // kernel: two sets, each reused once the kernel that read it has run
     uint8_t* ptab = nullptr;
     hipEvent_t ptab_free[2] = {nullptr, nullptr};
     int ptab_next = 0;
-    // pinned staging of host submissions
+    // pinned, coherent staging of host submissions (read by the staging kernel)
     uint8_t* stage = nullptr;
     uint64_t stage_bytes = 0;
     hipEvent_t stage_free = nullptr;
+    // byte moves of the current submission (compaction, appended chunks),
+    // run by the next staging kernel
+    qext::CopySegs segs{};
     Planned plan;
 };
 
@@ -744,19 +763,20 @@ bool ring_fit(const ext_growing_stream* s, uint64_t q0, uint64_t k,
     return true;
 }
 
+void add_seg(ext_growing_stream* s, const uint8_t* src, uint8_t* dst, uint64_t len) {
+    if (len) s->segs.seg[s->segs.n++] = qext::CopySeg{src, dst, len};
+}
+
 // Room for len more bytes after tail on one side: compact the live bytes to
-// the front of the other buffer, or grow both buffers (after waiting for the
-// queued work that reads them).
+// the front of the other buffer (a move of the next staging kernel), or grow
+// both buffers (after waiting for the queued work that reads them).
 int make_room(ext_growing_stream* s, uint8_t** buf, int* cur, uint64_t* head, uint64_t* tail,
               uint64_t len) {
-    ext_growing* g = s->g;
     const uint64_t live = *tail - *head;
     if (*tail + len <= s->bcap) return EXT_OK;
     if (live + len <= s->bcap) {
         const int nxt = 1 - *cur;
-        if (live && hipMemcpyAsync(buf[nxt], buf[*cur] + *head, live, hipMemcpyDeviceToDevice,
-                                   g->stream) != hipSuccess)
-            return sfail(s);
+        add_seg(s, buf[*cur] + *head, buf[nxt], live);
         *cur = nxt;
         *head = 0;
         *tail = live;
@@ -810,16 +830,17 @@ int grow_pending(ext_growing_stream* s, uint64_t need) {
     return EXT_OK;
 }
 
-// Queue the copy of one submission to the tails of the pending buffers; host
-// data go through pinned staging, reused once the previous copies have run.
+// The moves of one submission to the tails of the pending buffers, run by
+// the next staging kernel: device data straight from the caller's memory,
+// host data through pinned staging (reused once the previous staging kernel
+// has run).
 int append(ext_growing_stream* s, const void* x, uint64_t x_len, const void* y, uint64_t y_len) {
     ext_growing* g = s->g;
     uint8_t* xdst = s->xbuf[s->xcur] + s->xtail;
     uint8_t* ydst = s->ybuf[s->ycur] + s->ytail;
     if (g->params.mem_kind == EXT_MEM_DEVICE) {
-        if ((x_len && hipMemcpyAsync(xdst, x, x_len, hipMemcpyDeviceToDevice, g->stream)) ||
-            (y_len && hipMemcpyAsync(ydst, y, y_len, hipMemcpyDeviceToDevice, g->stream)))
-            return sfail(s);
+        add_seg(s, (const uint8_t*)x, xdst, x_len);
+        add_seg(s, (const uint8_t*)y, ydst, y_len);
         return EXT_OK;
     }
     if (!x_len && !y_len) return EXT_OK;
@@ -829,7 +850,7 @@ int append(ext_growing_stream* s, const void* x, uint64_t x_len, const void* y, 
         if (s->stage) (void)hipHostFree(s->stage);
         s->stage = nullptr;
         s->stage_bytes = 0;
-        if (hipHostMalloc((void**)&s->stage, len, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&s->stage, len, hipHostMallocCoherent) != hipSuccess) {
             (void)hipGetLastError();
             return EXT_ENOMEM;
         }
@@ -837,11 +858,24 @@ int append(ext_growing_stream* s, const void* x, uint64_t x_len, const void* y, 
     }
     if (x_len) memcpy(s->stage, x, x_len);
     if (y_len) memcpy(s->stage + x_len, y, y_len);
-    if ((x_len && hipMemcpyAsync(xdst, s->stage, x_len, hipMemcpyHostToDevice, g->stream)) ||
-        (y_len &&
-         hipMemcpyAsync(ydst, s->stage + x_len, y_len, hipMemcpyHostToDevice, g->stream)) ||
-        hipEventRecord(s->stage_free, g->stream))
-        return sfail(s);
+    add_seg(s, s->stage, xdst, x_len);
+    add_seg(s, s->stage + x_len, ydst, y_len);
+    return EXT_OK;
+}
+
+// Queue the staging kernel on g->stream: the pending moves and, for a call,
+// its packed tables (meta_bytes at meta_src, pinned) into s->dtab and n_heads
+// cleared queue heads.  In host-memory mode the pinned staging is free again
+// once this kernel has run.
+int issue_stage(ext_growing_stream* s, const void* meta_src, uint32_t meta_bytes,
+                uint32_t n_heads) {
+    ext_growing* g = s->g;
+    const bool host_moves = s->segs.n && g->params.mem_kind == EXT_MEM_HOST;
+    const hipError_t e = qext::launch_copy_stage(s->segs, meta_src, s->dtab, meta_bytes,
+                                                 s->dheads, n_heads, g->stream);
+    s->segs.n = 0;
+    if (e != hipSuccess) return sfail(s);
+    if (host_moves && hipEventRecord(s->stage_free, g->stream) != hipSuccess) return sfail(s);
     return EXT_OK;
 }
 
@@ -867,26 +901,34 @@ int launch_ready(ext_growing_stream* s) {
         if (s->plan.tiles.size() > kMaxLaunchTiles) return EXT_ENOTSUP;
         rc = grow_part(g, s->plan.part_words);
         if (rc) return rc;
-        // the pinned table set of the call before last is free once its copy ran
+        // the pinned table set of the call before last is free once the
+        // staging kernel that read it has run
         const int slot = s->ptab_next;
         if (hipEventSynchronize(s->ptab_free[slot]) != hipSuccess) return sfail(s);
         uint8_t* pt = s->ptab + slot * kTableBytes;
-        memcpy(pt, s->plan.streams.data(), s->plan.streams.size() * sizeof(BatchStream));
-        memcpy(pt + kTilesOff, s->plan.tiles.data(), s->plan.tiles.size() * sizeof(BatchTile));
-        memcpy(pt + kJobsOff, s->plan.jobs.data(), s->plan.jobs.size() * sizeof(CombineJob));
-        const Tables tab{(BatchStream*)s->dtab, (BatchTile*)(s->dtab + kTilesOff),
-                         (CombineJob*)(s->dtab + kJobsOff), s->dheads};
-        rc = queue_blocks(g, s->plan, tab, pt, pt + kTilesOff, pt + kJobsOff);
+        const size_t sb = s->plan.streams.size() * sizeof(BatchStream);
+        const size_t tb = s->plan.tiles.size() * sizeof(BatchTile);
+        const size_t jb = s->plan.jobs.size() * sizeof(CombineJob);
+        const size_t to = round16(sb), jo = to + round16(tb), total = jo + round16(jb);
+        memcpy(pt, s->plan.streams.data(), sb);
+        memcpy(pt + to, s->plan.tiles.data(), tb);
+        memcpy(pt + jo, s->plan.jobs.data(), jb);
+        const Tables tab{(BatchStream*)s->dtab, (BatchTile*)(s->dtab + to),
+                         (CombineJob*)(s->dtab + jo), s->dheads};
+        // the submission's moves ride with the first call's tables
+        rc = issue_stage(s, pt, (uint32_t)total, (uint32_t)s->plan.launches.size());
+        if (rc) return rc;
+        if (hipEventRecord(s->ptab_free[slot], g->stream) != hipSuccess) return sfail(s);
+        s->ptab_next = 1 - slot;
+        rc = queue_launches(g, s->plan, tab);
         if (rc) return rc;
         GLaunch L{s->next_block, n, s->next_q, pos, bytes};
-        if (hipEventRecord(s->ptab_free[slot], g->stream) != hipSuccess ||
-            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
             return sfail(s);
         if (hipEventRecord(L.done, g->stream) != hipSuccess) {
             (void)hipEventDestroy(L.done);
             return sfail(s);
         }
-        s->ptab_next = 1 - slot;
         s->inflight.push_back(L);
         s->owrite = pos + bytes;
         uint64_t in = 0;
@@ -903,10 +945,28 @@ int launch_ready(ext_growing_stream* s) {
     return EXT_OK;
 }
 
+// Copy whole finished blocks into out, in block order: the ring ranges of
+// consecutive blocks are merged into as few copies as possible.  Device
+// memory on the caller's HIP stream: the copies are queued on it (later work
+// there, including this stream's next launches, comes after them); else they
+// run on g->copy and are waited for once before returning (drain always
+// waits).
 int copy_out(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
              uint64_t* blocks_done, bool wait) {
     ext_growing* g = s->g;
+    const bool device = g->params.mem_kind == EXT_MEM_DEVICE;
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const bool ordered = device && g->params.use_hip_stream;
+    hipStream_t cs = ordered ? g->stream : g->copy;
     size_t written = 0;
+    uint64_t run_src = 0, run_len = 0;  // the copy being merged: ring offset, bytes
+    size_t run_dst = 0;
+    auto flush = [&]() {
+        const bool ok = !run_len || hipMemcpyAsync((uint8_t*)out + run_dst, s->oring + run_src,
+                                                   run_len, kind, cs) == hipSuccess;
+        run_len = 0;
+        return ok;
+    };
     while (!s->inflight.empty()) {
         GLaunch& L = s->inflight.front();
         if (wait) {
@@ -925,13 +985,15 @@ int copy_out(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
             q += s->step;
         }
         if (n) {
-            const uint8_t* src = s->oring + (L.opos + L.taken_bytes) % s->ocap;
-            const hipMemcpyKind kind = g->params.mem_kind == EXT_MEM_DEVICE
-                                           ? hipMemcpyDeviceToDevice
-                                           : hipMemcpyDeviceToHost;
-            if (hipMemcpyAsync((uint8_t*)out + written, src, bytes, kind, g->copy) != hipSuccess ||
-                hipStreamSynchronize(g->copy) != hipSuccess)
-                return sfail(s);
+            const uint64_t src = (L.opos + L.taken_bytes) % s->ocap;
+            if (run_len && src == run_src + run_len) {
+                run_len += bytes;
+            } else {
+                if (!flush()) return sfail(s);
+                run_src = src;
+                run_dst = written;
+                run_len = bytes;
+            }
             written += bytes;
             L.taken += n;
             L.taken_bytes += bytes;
@@ -942,6 +1004,10 @@ int copy_out(ext_growing_stream* s, void* out, size_t out_cap, size_t* out_len,
         (void)hipEventDestroy(L.done);
         s->inflight.pop_front();
     }
+    // the ring ranges handed back may be overwritten by later launches only
+    // after these copies: stream order, or a wait before returning
+    if (!flush() || (written && (!ordered || wait) && hipStreamSynchronize(cs) != hipSuccess))
+        return sfail(s);
     if (out_len) *out_len = written;
     if (blocks_done) *blocks_done = s->returned;
     return EXT_OK;
@@ -984,7 +1050,7 @@ int ext_growing_open(ext_growing* g, ext_growing_stream** out) {
     ok = ok && hipMalloc((void**)&s->oring, s->ocap) == hipSuccess &&
          hipMalloc((void**)&s->dtab, kTableBytes) == hipSuccess &&
          hipMalloc((void**)&s->dheads, kMaxGroups * sizeof(uint32_t)) == hipSuccess &&
-         hipHostMalloc((void**)&s->ptab, 2 * kTableBytes, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&s->ptab, 2 * kTableBytes, hipHostMallocCoherent) == hipSuccess &&
          hipEventCreateWithFlags(&s->stage_free, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -1030,15 +1096,21 @@ int ext_growing_submit(ext_growing_stream* s, const void* x, size_t x_len, const
             rc = grow_pending(s, need);
             if (rc) return rc;
         }
+        // moves (compaction, the chunks), then the blocks completed; moves not
+        // carried by a call's staging kernel (none completed, or an error
+        // after a compaction switched buffers) go in one of their own
         rc = make_room(s, s->xbuf, &s->xcur, &s->xhead, &s->xtail, x_len);
-        if (rc) return rc;
-        rc = make_room(s, s->ybuf, &s->ycur, &s->yhead, &s->ytail, y_len);
-        if (rc) return rc;
-        rc = append(s, x, x_len, y, y_len);
-        if (rc) return rc;
-        s->xtail += x_len;
-        s->ytail += y_len;
-        rc = launch_ready(s);
+        if (!rc) rc = make_room(s, s->ybuf, &s->ycur, &s->yhead, &s->ytail, y_len);
+        if (!rc) rc = append(s, x, x_len, y, y_len);
+        if (!rc) {
+            s->xtail += x_len;
+            s->ytail += y_len;
+            rc = launch_ready(s);
+        }
+        if (s->segs.n) {
+            const int rc2 = issue_stage(s, nullptr, 0, 0);
+            if (!rc) rc = rc2;
+        }
         if (rc) return rc;
     } catch (const std::bad_alloc&) {
         return EXT_ENOMEM;

@@ -49,6 +49,8 @@ struct PlanKnobs {
     uint32_t threads;     // work-group size (256 or 1024)
     uint32_t padded;      // 1: use the padded layout even when q is a multiple of 32
                           // (byte-granular blocks and outputs)
+    uint32_t max_odd;     // largest odd part of the (padded) words per element, which
+                          // bounds the base product (0: 15)
 };
 
 // Fills *s for q, n_e and the taps; returns false if the shape is outside
@@ -131,6 +133,27 @@ struct ScatterDesc {
 hipError_t launch_stage(const uint8_t* src, const ScatterDesc* descs, uint32_t n_descs,
                         const void* meta_src, void* meta_dst, uint32_t meta_bytes, uint32_t* heads,
                         uint32_t n_heads, hipStream_t stream);
+
+// Up to kMaxCopySegs byte ranges to copy on the device (sources in device
+// memory or in pinned, coherent host memory; ranges neither overlap nor
+// alias another segment's destination), passed to the kernel by value.
+constexpr uint32_t kMaxCopySegs = 4;
+struct CopySeg {
+    const uint8_t* src;
+    uint8_t* dst;
+    uint64_t len;
+};
+struct CopySegs {
+    CopySeg seg[kMaxCopySegs];
+    uint32_t n;
+};
+
+// Queue one growing-stream staging kernel: copy every segment, copy
+// meta_bytes (a multiple of 16, may be 0) from meta_src (pinned, coherent
+// host memory) to meta_dst (device), and clear n_heads queue heads.
+hipError_t launch_copy_stage(const CopySegs& segs, const void* meta_src, void* meta_dst,
+                             uint32_t meta_bytes, uint32_t* heads, uint32_t n_heads,
+                             hipStream_t stream);
 
 // As launch_batch without the queue-head reset (the caller clears the head);
 // part (device) receives the partial sums of sliced tiles (may be null when

@@ -674,8 +674,17 @@ combine_padded_kernel(const BatchStream* __restrict__ streams, const CombineJob*
         const uint32_t cw = 2 * sh.qw;
         const uint32_t* src = part + job.part_word0;
         for (uint32_t i = threadIdx.x; i < cw; i += blockDim.x) {
-            uint32_t v = 0;
-            for (uint32_t k = 0; k < job.n_parts; ++k) v ^= src[(uint64_t)k * cw + i];
+            // eight parts' loads in flight before they are used (the parts
+            // were just written by other CUs: every load goes past this L2)
+            uint32_t v = 0, k = 0;
+            for (; k + 8 <= job.n_parts; k += 8) {
+                uint32_t a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = src[(uint64_t)(k + u) * cw + i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v ^= a[u];
+            }
+            for (; k < job.n_parts; ++k) v ^= src[(uint64_t)k * cw + i];
             lds[i] = v;
         }
         __syncthreads();

@@ -215,10 +215,16 @@ def test_growing_stream_random_chunks(dev, n_e, q1, delta_steps, b, k):
     want = oracle_blocks_parallel(x, y, n_e, q1, delta_steps, b, k)
     m_k = orc_params.output_bits(q1, delta_steps, b, k)
     assert want.size * 8 == m_k == binding.output_bits(q1, delta_steps, b, k)
-    for device_memory in (False, True):
-        say("  device_memory=%s" % device_memory)
+    import torch
+
+    # host memory; device memory on the handle's own stream (poll waits for
+    # its copies); device memory on torch's current stream (poll's copies are
+    # stream-ordered, and feed reads them on that stream)
+    for device_memory, on_current in ((False, False), (True, False), (True, True)):
+        say("  device_memory=%s, caller's stream=%s" % (device_memory, on_current))
+        stream = torch.cuda.current_stream(dev).cuda_stream if on_current else None
         with binding.Growing(n_e, q1, delta_steps, sample_bits=b,
-                             device_memory=device_memory) as g:
+                             device_memory=device_memory, stream=stream) as g:
             st = g.open_stream()
 
             def chunk_cap(s):
