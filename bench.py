@@ -600,7 +600,7 @@ def served_checks(chans, cap, dev, stream):
 def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
                modes=("served", "plain", "plain_at_1/16_load"), wg_per_cu: int = 0,
                max_inflight: int = 0, split_pairs: int = -1, producers: int = 4,
-               timing: int = 0, sweep=(96, 128, 192, 256, 384), sweep_s: float = 3.0,
+               timing: int = 0, sweep=(72, 80, 88, 96, 104, 112, 128), sweep_s: float = 3.0,
                capture_channels: int = 16):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
     1..64 blocks, 64 Gbps aggregate raw input; three quarters i.i.d. Gaussian
@@ -691,6 +691,9 @@ def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
             log("served leg: parity %s" % json.dumps(out[name]["parity"]))
             del cap
     if "served" in modes and sweep:
+        # the sweep's load generator runs at least 8 submitting threads: with 4,
+        # submission itself falls behind above about 90 Gbps (p99 submit lag)
+        sweep_producers = max(producers, 8)
         points = []
         best = 64.0 if ("served" in out and out["served"]["p99_latency_ms"] <= 1.0
                         and out["served"]["blocks_missing"] == 0) else None
@@ -699,9 +702,10 @@ def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
             res, _ = binding.simulate(chans, mode=binding.EXT_SIM_SERVED,
                                       raw_bytes_per_s=gbps * 1e9 / 8, warmup_s=0.5,
                                       duration_s=sweep_s, grace_s=2.0, max_lag_s=1.0, seed=5,
-                                      producer_threads=producers, config=config())
+                                      producer_threads=sweep_producers, config=config())
             pt = summary(res)
             pt["offered_raw_gbps"] = gbps
+            pt["producer_threads"] = sweep_producers
             points.append(pt)
             log("served leg: sweep %d Gbps: p99 %.3f ms, out %.2f Gbps, missing %d"
                 % (gbps, pt["p99_latency_ms"], pt["output_gbps"], pt["blocks_missing"]))
@@ -765,7 +769,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="served-leg measurement window, after 1 s of warm-up")
-    ap.add_argument("--serve-sweep", default="96,128,192,256,384",
+    ap.add_argument("--serve-sweep", default="72,80,88,96,104,112,128",
                     help="offered raw Gbps of the saturation sweep (empty: none)")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-workload leg")
     ap.add_argument("--no-stress", action="store_true",
