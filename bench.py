@@ -599,7 +599,7 @@ def served_checks(chans, cap, dev, stream):
 
 def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
                modes=("served", "plain", "plain_at_1/16_load"), wg_per_cu: int = 0,
-               max_inflight: int = 0, split_pairs: int = -1, producers: int = 4,
+               max_inflight: int = 0, split_pairs: int = -1, producers: int = 8,
                timing: int = 0, sweep=(72, 80, 88, 96, 104, 112, 128), sweep_s: float = 3.0,
                capture_channels: int = 16):
     """The served workload: 256 channel pairs with Poisson chunk arrivals of
@@ -692,7 +692,7 @@ def served_leg(w, dev, stream, duration_s: float, warmup_s: float,
             del cap
     if "served" in modes and sweep:
         # the sweep's load generator runs at least 8 submitting threads: with 4,
-        # submission itself falls behind above about 90 Gbps (p99 submit lag)
+        # submission itself falls behind at the higher rates (p99 submit lag)
         sweep_producers = max(producers, 8)
         points = []
         best = 64.0 if ("served" in out and out["served"]["p99_latency_ms"] <= 1.0
@@ -781,7 +781,7 @@ def main():
     ap.add_argument("--serve-split", type=int, default=-1,
                     help="server split_pairs (1: slice large pairs over work-groups, 0: whole "
                          "pairs; -1 = library default)")
-    ap.add_argument("--serve-producers", type=int, default=4,
+    ap.add_argument("--serve-producers", type=int, default=8,
                     help="load generator threads submitting chunks")
     ap.add_argument("--serve-timing", type=int, default=0,
                     help="1: time every server cycle's phases with GPU events (diagnostic)")
