@@ -55,12 +55,13 @@ struct ext_growing {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::map<uint32_t, DegreePlan> plans;  // plan per degree
-    // device scratch of the prefix call, grown on demand
-    BatchStream* d_streams = nullptr;
-    BatchTile* d_tiles = nullptr;
-    CombineJob* d_jobs = nullptr;
+    // launch tables of the prefix call, packed (streams, tiles, jobs), in
+    // device memory and in pinned, coherent host memory that the staging
+    // kernel reads; grown on demand
+    uint8_t* d_tab = nullptr;
+    uint8_t* h_tab = nullptr;
+    uint64_t cap_tab = 0;
     uint32_t* d_heads = nullptr;
-    uint64_t cap_blocks = 0, cap_tiles = 0, cap_jobs = 0;
     // partial sums of sliced blocks (every call of the handle, in stream order)
     uint32_t* d_part = nullptr;
     uint64_t cap_part = 0;
@@ -99,21 +100,19 @@ void release_lanes(ext_growing* g) {
 }
 
 void free_scratch(ext_growing* g) {
-    (void)hipFree(g->d_streams);
-    (void)hipFree(g->d_tiles);
-    (void)hipFree(g->d_jobs);
+    (void)hipFree(g->d_tab);
+    if (g->h_tab) (void)hipHostFree(g->h_tab);
     (void)hipFree(g->d_heads);
     (void)hipFree(g->d_part);
     (void)hipFree(g->dx);
     (void)hipFree(g->dy);
     (void)hipFree(g->dout);
-    g->d_streams = nullptr;
-    g->d_tiles = nullptr;
-    g->d_jobs = nullptr;
+    g->d_tab = nullptr;
+    g->h_tab = nullptr;
     g->d_heads = nullptr;
     g->d_part = nullptr;
     g->dx = g->dy = g->dout = nullptr;
-    g->cap_blocks = g->cap_tiles = g->cap_jobs = g->cap_part = 0;
+    g->cap_tab = g->cap_part = 0;
     g->cap_in = g->cap_out = 0;
 }
 
@@ -191,26 +190,19 @@ bool use_slices(const DegreePlan& d, bool allow) {
     return (uint64_t)d.whole.np * d.whole.n_e > 2ull * d.whole.threads;
 }
 
-// Device tables of the prefix call, grown to at least the given counts.
-int grow_tables(ext_growing* g, uint64_t streams, uint64_t tiles, uint64_t jobs) {
+// Table buffers of the prefix call, grown to at least `bytes` each (every
+// prefix call waits for its work before returning, so none is in use).
+int grow_tables(ext_growing* g, uint64_t bytes) {
     bool ok = true;
-    if (streams > g->cap_blocks) {
-        (void)hipFree(g->d_streams);
-        g->d_streams = nullptr;
-        ok = hipMalloc((void**)&g->d_streams, streams * sizeof(BatchStream)) == hipSuccess;
-        g->cap_blocks = ok ? streams : 0;
-    }
-    if (ok && tiles > g->cap_tiles) {
-        (void)hipFree(g->d_tiles);
-        g->d_tiles = nullptr;
-        ok = hipMalloc((void**)&g->d_tiles, tiles * sizeof(BatchTile)) == hipSuccess;
-        g->cap_tiles = ok ? tiles : 0;
-    }
-    if (ok && jobs > g->cap_jobs) {
-        (void)hipFree(g->d_jobs);
-        g->d_jobs = nullptr;
-        ok = hipMalloc((void**)&g->d_jobs, jobs * sizeof(CombineJob)) == hipSuccess;
-        g->cap_jobs = ok ? jobs : 0;
+    if (bytes > g->cap_tab) {
+        (void)hipFree(g->d_tab);
+        if (g->h_tab) (void)hipHostFree(g->h_tab);
+        g->d_tab = nullptr;
+        g->h_tab = nullptr;
+        g->cap_tab = 0;
+        ok = hipMalloc((void**)&g->d_tab, bytes) == hipSuccess &&
+             hipHostMalloc((void**)&g->h_tab, bytes, hipHostMallocCoherent) == hipSuccess;
+        if (ok) g->cap_tab = bytes;
     }
     if (ok && !g->d_heads)
         ok = hipMalloc((void**)&g->d_heads, kMaxGroups * sizeof(uint32_t)) == hipSuccess;
@@ -344,6 +336,8 @@ struct Tables {
     CombineJob* jobs;
     uint32_t* heads;
 };
+
+constexpr size_t round16(size_t v) { return (v + 15) / 16 * 16; }
 
 // One persistent launch of a planned call: the tiles [off, off + n) of one
 // (base size, work-group size) class.
@@ -545,15 +539,28 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
         Planned p;
         int rc = plan_blocks(g, g->q1, r.k, xs, ys, os, !fixed, &p);
         if (rc) return rc;
+        // the tables: copied into the static scratch (allocation-free call), or
+        // packed into the handle's pinned buffer for the staging kernel
         Tables tab;
+        size_t tab_bytes = 0;
         if (fixed) {
             tab = *fixed;
         } else {
-            rc = grow_tables(g, p.streams.size(), p.tiles.size(), p.jobs.size());
+            const size_t sb = p.streams.size() * sizeof(BatchStream);
+            const size_t tb = p.tiles.size() * sizeof(BatchTile);
+            const size_t jb = p.jobs.size() * sizeof(CombineJob);
+            const size_t to = round16(sb), jo = to + round16(tb);
+            tab_bytes = jo + round16(jb);
+            if (tab_bytes > 0xffffffffull) return EXT_ENOTSUP;
+            rc = grow_tables(g, tab_bytes);
             if (rc) return rc;
             rc = grow_part(g, p.part_words);
             if (rc) return rc;
-            tab = Tables{g->d_streams, g->d_tiles, g->d_jobs, g->d_heads};
+            memcpy(g->h_tab, p.streams.data(), sb);
+            memcpy(g->h_tab + to, p.tiles.data(), tb);
+            memcpy(g->h_tab + jo, p.jobs.data(), jb);
+            tab = Tables{(BatchStream*)g->d_tab, (BatchTile*)(g->d_tab + to),
+                         (CombineJob*)(g->d_tab + jo), g->d_heads};
         }
         // from here on work is queued: every exit waits for the stream first,
         // so no copy still reads the caller's or these host buffers
@@ -565,7 +572,16 @@ int extract_blocks(ext_growing* g, const void* x, const void* y, uint64_t n_byte
                 return g->sticky = EXT_EDEVICE;
             }
         }
-        rc = queue_blocks(g, p, tab, p.streams.data(), p.tiles.data(), p.jobs.data());
+        if (fixed) {
+            rc = queue_blocks(g, p, tab, p.streams.data(), p.tiles.data(), p.jobs.data());
+        } else {
+            // one staging kernel uploads the tables and clears the queue heads
+            if (qext::launch_copy_stage(qext::CopySegs{}, g->h_tab, g->d_tab, (uint32_t)tab_bytes,
+                                        g->d_heads, (uint32_t)p.launches.size(),
+                                        g->stream) != hipSuccess)
+                return device_error(g);
+            rc = queue_launches(g, p, tab);
+        }
         if (rc) return rc;
         if (host && hipMemcpyAsync(out, g->dout, r.out_bytes, hipMemcpyDeviceToHost, g->stream)) {
             (void)hipStreamSynchronize(g->stream);
@@ -625,7 +641,6 @@ namespace {
 
 constexpr uint64_t kMaxLaunchBlocks = 1024;  // blocks per queued call
 constexpr uint64_t kMaxLaunchTiles = 16384;  // tiles per queued call (slices count each)
-constexpr size_t round16(size_t v) { return (v + 15) / 16 * 16; }
 // the largest table set of one call, packed: streams, tiles, jobs
 constexpr size_t kTableBytes = round16(kMaxLaunchBlocks * sizeof(BatchStream)) +
                                round16(kMaxLaunchTiles * sizeof(BatchTile)) +
