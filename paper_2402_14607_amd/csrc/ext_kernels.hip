@@ -122,17 +122,69 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
     }
 }
 
-// Karatsuba path of sub-product p: one base-3 digit per level, 0 = low
-// halves, 1 = high halves, 2 = sum of halves.  Bit l of a mask describes the
-// level whose halves are B * 2^l bits (l = 0 is the lowest level).
+// Binomial coefficients C(n, k) for n, k <= kMaxPathLevels (the most
+// Karatsuba levels a shape has).
+constexpr uint32_t kMaxPathLevels = 10;
+struct ChooseTable {
+    uint32_t v[kMaxPathLevels + 1][kMaxPathLevels + 1];
+};
+constexpr ChooseTable make_choose() {
+    ChooseTable t{};
+    for (uint32_t n = 0; n <= kMaxPathLevels; ++n) {
+        t.v[n][0] = 1;
+        for (uint32_t k = 1; k <= n; ++k) t.v[n][k] = t.v[n - 1][k - 1] + (k < n ? t.v[n - 1][k] : 0);
+    }
+    return t;
+}
+__constant__ ChooseTable kChoose = make_choose();
+
+// Karatsuba path of the sub-product of rank p: at each level it takes the low
+// halves, the high halves or the sum of halves.  Bit l of a mask describes
+// the level whose halves are B * 2^l bits (l = 0 is the lowest level).  The
+// 3^L paths are ranked by their number c of sum-of-halves levels, which sets
+// the work of a lane outside its base product (2^c pieces per operand,
+// 2^(L - c) scatter offsets): lanes of a wave, which take consecutive ranks,
+// then loop about equally often.  Within class c (C(L, c) 2^(L-c) paths) the
+// rank is comb * 2^(L-c) + bits: comb picks the sum-of-halves levels (the
+// combinatorial number system), bits the low/high choice of the other levels,
+// highest level first.  Table reads are at uniform indices (scalar loads).
 __device__ __forceinline__ void path_masks(uint32_t p, uint32_t levels, uint32_t& hi_mask,
                                            uint32_t& mid_mask) {
-    uint32_t hm = 0, mm = 0, v = p;
-    for (uint32_t l = 0; l < levels; ++l) {
-        const uint32_t d = v % 3u;
-        v /= 3u;
-        hm |= (uint32_t)(d == 1u) << l;
-        mm |= (uint32_t)(d == 2u) << l;
+    uint32_t r = p, c = 0;
+    bool found = false;
+#pragma unroll
+    for (uint32_t cc = 0; cc <= kMaxPathLevels; ++cc) {
+        if (cc > levels) break;
+        const uint32_t cnt = kChoose.v[levels][cc] << (levels - cc);
+        if (!found) {
+            if (r < cnt) {
+                c = cc;
+                found = true;
+            } else {
+                r -= cnt;
+            }
+        }
+    }
+    const uint32_t free_levels = levels - c;
+    uint32_t bits = r & ((1u << free_levels) - 1u);
+    uint32_t comb = r >> free_levels;
+    uint32_t hm = 0, mm = 0, k = c;
+#pragma unroll
+    for (int pos = (int)kMaxPathLevels - 1; pos >= 0; --pos) {
+        if ((uint32_t)pos >= levels) continue;
+        // C(pos, k): k-subsets of the levels below pos
+        uint32_t below = 0;
+#pragma unroll
+        for (uint32_t kk = 0; kk <= kMaxPathLevels; ++kk)
+            below = k == kk ? kChoose.v[pos][kk] : below;
+        if (k > 0 && comb >= below) {
+            mm |= 1u << pos;
+            comb -= below;
+            --k;
+        } else {
+            hm |= (bits & 1u) << pos;
+            bits >>= 1;
+        }
     }
     hi_mask = hm;
     mid_mask = mm;
