@@ -642,6 +642,11 @@ ext_ip_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
                                  out + pair0 * sh.qbytes, npw, lds);
 }
 
+// Whether the batched kernel of base size BW ranks its sub-products: only
+// bases of at most 8 words reach five or more levels in practice.
+template <int BW>
+constexpr bool kBatchRank = BW <= 8;
+
 // Batched form: a persistent grid drains a device work queue of tiles
 // (stream, first pair, pair count; or one slice of one pair) shared by many
 // streams of different shapes.  Each work-group takes the next tile with one atomic add on the
@@ -666,14 +671,14 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
         const uint8_t* yb = st.y + tile.in_pair0 * sh.nbytes;
         if (tile.n_items) {  // one slice of one pair; out_off is its part's word offset
             if constexpr (PAD)  // elements [item0, item0 + n_items)
-                extract_slice_padded<BW, false>(sh, xb, yb, part + tile.out_off, tile.item0,
-                                                tile.n_items, lds);
+                extract_slice_padded<BW, kBatchRank<BW>>(sh, xb, yb, part + tile.out_off,
+                                                         tile.item0, tile.n_items, lds);
             else  // items [item0, item0 + n_items)
-                extract_slice<BW, false>(sh, reinterpret_cast<const uint32_t*>(xb),
+                extract_slice<BW, kBatchRank<BW>>(sh, reinterpret_cast<const uint32_t*>(xb),
                                   reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
                                   tile.item0, tile.n_items, lds);
         } else
-            extract_group<BW, PAD, false>(sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
+            extract_group<BW, PAD, kBatchRank<BW>>(sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
 }
