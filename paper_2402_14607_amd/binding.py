@@ -345,8 +345,8 @@ class Extractor:
         return tuple(int(exps[i]) for i in range(n.value))
 
     def describe(self) -> str:
-        buf = ctypes.create_string_buffer(512)
-        _check(self.lib.ext_describe(self.handle, buf, 512), "ext_describe")
+        buf = ctypes.create_string_buffer(1024)
+        _check(self.lib.ext_describe(self.handle, buf, 1024), "ext_describe")
         return buf.value.decode()
 
     def extract(self, x, y, out, n_pairs: int) -> None:

@@ -139,6 +139,12 @@ struct ext_ctx {
     uint32_t b = 8;
     std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
     ExtShape shape{};
+    // latency plan for launches that would leave CUs idle: one element per
+    // lane item and one more Karatsuba level, so a lane's chain is one short
+    // base product (word-level kernel only; same outputs)
+    ExtShape small{};
+    bool has_small = false;
+    uint32_t cus = 0;
     bool bitslice = false;  // plain/streaming launches take the bit-sliced kernel
     uint32_t kernel = EXT_KERNEL_AUTO;  // ext_params.kernel, for streams of other shapes
     uint32_t mem_kind = EXT_MEM_HOST;
@@ -232,6 +238,14 @@ int launch(ext_ctx* c, const ExtShape& shape, bool bitslice, const void* x, cons
 }
 
 int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
+    if (!c->bitslice && c->has_small) {
+        // fewer work-groups than CUs: the latency plan spreads the same pairs
+        // over more of them, each lane one base product
+        const uint64_t wgs = (n_pairs + c->shape.ppw - 1) / c->shape.ppw;
+        const uint64_t wgs_small = (n_pairs + c->small.ppw - 1) / c->small.ppw;
+        if (wgs < c->cus && wgs_small > wgs)
+            return launch(c, c->small, false, x, y, out, n_pairs);
+    }
     return launch(c, c->shape, c->bitslice, x, y, out, n_pairs);
 }
 
@@ -449,6 +463,23 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         }
         c->shape = ts;
     }
+    // the latency plan (when the caller fixed no plan knob): every element
+    // its own lane item, base half the default's (one more Karatsuba level)
+    if (!c->bitslice && !p->base_bits && !p->groups && !p->pairs_per_group) {
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const ExtShape& d = c->shape;
+        qext::PlanKnobs sk{d.bw > 1 ? d.bw / 2 : 1, d.n_e, 0, d.threads, d.padded};
+        ExtShape ss;
+        if (cus > 0 && qext::plan_shape(m_bits, d.n_e, taps.data(), (uint32_t)taps.size(), sk, &ss) &&
+            ss.padded == d.padded && ss.qw == d.qw && d.align % ss.align == 0) {
+            // (inputs are checked against the default plan's alignment, which
+            // the latency plan's divides)
+            c->small = ss;
+            c->has_small = true;
+            c->cus = (uint32_t)cus;
+        }
+    }
     *out = c;
     return EXT_OK;
 }
@@ -479,13 +510,19 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
                  qext::kThreads, qext::bitslice_lds_words(s) * 4, ec, levels, piece, subs);
         return EXT_OK;
     }
+    char small[160] = "";
+    if (c->has_small)
+        snprintf(small, sizeof small,
+                 ", \"small_launch\": {\"below_workgroups\": %u, \"base_bits\": %u, "
+                 "\"karatsuba_levels\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u}",
+                 c->cus, c->small.bw * 32, c->small.levels, c->small.ppw, c->small.groups);
     snprintf(buf, cap,
              "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"base_bits\": %u, \"karatsuba_levels\": %u, "
              "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
              "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d, \"padded\": %u, "
-             "\"slot_words\": %u, \"kernel\": \"%s\"}",
+             "\"slot_words\": %u, \"kernel\": \"%s\"%s}",
              (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
-             s.groups, s.stage, s.lds_words * 4, s.threads, s.padded, s.qw, "word");
+             s.groups, s.stage, s.lds_words * 4, s.threads, s.padded, s.qw, "word", small);
     return EXT_OK;
 }
 
