@@ -163,6 +163,67 @@ def test_shapes_full(dev, m, n_e):
     assert np.array_equal(got, oracle.ext_blocks(x, y, n, m))
 
 
+# deep Karatsuba trees reached with small fixed bases: 5 to 7 levels take the
+# sub-products in the ranked order (by number of sum-of-halves levels), 4 and
+# 8 in base-3 digit order; a fixed base also keeps the default plan (no
+# latency plan) whatever the pair count
+RANKED_SHAPES = [(1024, 2, 32), (2048, 2, 64), (2048, 1, 32), (4096, 2, 32), (8192, 1, 32),
+                 (1024, 3, 64)]
+
+
+@pytest.mark.parametrize("m,n_e,base", RANKED_SHAPES, ids=lambda v: str(v))
+def test_deep_karatsuba_levels(dev, m, n_e, base):
+    import json
+
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(5000 + m + n_e + base))
+    n = m * n_e
+    pairs = 3
+    x = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    y = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    with binding.Extractor(n, m, device_memory=True, base_bits=base,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        plan = json.loads(ex.describe())
+        say("m=%d n_e=%d base %d bits: %d levels, %s" % (m, n_e, base, plan["karatsuba_levels"],
+                                                      ex.describe()))
+        assert plan["base_bits"] == base and "small_launch" not in plan
+        got = gpu_extract(dev, x, y, n, m, ex=ex)
+    assert np.array_equal(got, oracle.ext_blocks(x, y, n, m))
+
+
+@pytest.mark.parametrize("m,n_e", [(256, 4), (2048, 4), (1024, 1), (512, 8)],
+                         ids=lambda v: str(v))
+def test_latency_plan_equals_default_plan(dev, m, n_e):
+    """A launch with fewer work-groups than CUs takes the context's latency
+    plan (ext_describe's small_launch); its bytes equal the default plan's
+    (a context with the base fixed at its default size has no latency plan)
+    and the oracle's."""
+    import json
+
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(6000 + m + n_e))
+    n = m * n_e
+    pairs = 37
+    x = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    y = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    with binding.Extractor(n, m, device_memory=True, stream=st) as ex:
+        plan = json.loads(ex.describe())
+        say("m=%d n_e=%d: %s" % (m, n_e, ex.describe()))
+        assert "small_launch" in plan
+        assert (pairs + plan["pairs_per_workgroup"] - 1) // plan["pairs_per_workgroup"] < \
+            plan["small_launch"]["below_workgroups"]
+        small = gpu_extract(dev, x, y, n, m, ex=ex)
+        base = plan["base_bits"]
+    with binding.Extractor(n, m, device_memory=True, stream=st, base_bits=base) as ex:
+        assert "small_launch" not in json.loads(ex.describe())
+        default = gpu_extract(dev, x, y, n, m, ex=ex)
+    assert np.array_equal(small, default)
+    assert np.array_equal(small, oracle.ext_blocks(x, y, n, m))
+
+
 # degrees that are not multiples of 32: elements sit at byte (not word)
 # offsets, are re-laid out in zero-padded 32-bit slots, and outputs are
 # q/8 bytes per pair at byte offsets; and multiples of 32 whose word count
