@@ -133,13 +133,17 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
 // operand, 2^(L - c) scatter offsets): lanes of a wave, which take
 // consecutive p, then loop about equally often instead of as often as the
 // wave's worst path.  The ranked masks come from a table built at compile
-// time.  The plain kernel ranks (RANK); the batched kernel keeps the digits,
-// since the ranked variant, though it changed none of the loops' instruction
-// counts there, measured 2-5 % slower on its launches.  At three levels a wave spans every path either way and the plain
+// time.  MINL sets from how many levels a kernel ranks: the plain kernel of
+// unpadded shapes takes its items rank-major (extract_group) and ranks from
+// two levels on, padded shapes and the batched kernel (items pair-major) from
+// five, and the batched kernel only for bases of at most 8 words: at 16 words,
+// where no shape reaches five levels, the variant that carried the ranking
+// changed none of the loops' instruction counts and still measured 2-5 %
+// slower on its launches.  At three levels a wave spans every path either way and the plain
 // digits measured faster; at six the ranking cut the forward-block-stress
 // launch by 14 %.
-constexpr uint32_t kRankMin = 5, kRankMax = 7;
-constexpr uint32_t kRankedCount = 243 + 729 + 2187;  // 3^5 + 3^6 + 3^7
+constexpr uint32_t kRankMin = 2, kRankMax = 7;
+constexpr uint32_t kRankedCount = 9 + 27 + 81 + 243 + 729 + 2187;  // 3^2 .. 3^7
 struct RankedPaths {
     uint32_t v[kRankedCount];  // mid_mask << 16 | hi_mask
 };
@@ -191,12 +195,14 @@ constexpr RankedPaths make_ranked() {
 }
 __constant__ RankedPaths kRanked = make_ranked();
 
-template <bool RANK>
+template <uint32_t MINL>
 __device__ __forceinline__ void path_masks(uint32_t p, uint32_t levels, uint32_t& hi_mask,
                                            uint32_t& mid_mask) {
-    if (RANK && levels >= kRankMin && levels <= kRankMax) {
-        const uint32_t off = levels == kRankMin ? 0u : (levels == kRankMin + 1 ? 243u : 972u);
-        const uint32_t v = kRanked.v[off + p];
+    if (levels >= MINL && levels >= kRankMin && levels <= kRankMax) {
+        // table offset of L levels: 3^2 + ... + 3^(L-1) = (3^L - 9) / 2
+        uint32_t p3 = 1;
+        for (uint32_t l = 0; l < levels; ++l) p3 *= 3u;
+        const uint32_t v = kRanked.v[(p3 - 9u) / 2u + p];
         hi_mask = v & 0xffffu;
         mid_mask = v >> 16;
         return;
@@ -235,7 +241,8 @@ __device__ __forceinline__ void scatter_acc(const uint32_t (&acc)[2 * BW], uint3
 // to the whole work-group) modulo P and store the q-bit results at out
 // (qw words per pair); ds holds npw * dn words of scratch.  Ends after the
 // last global store, without a barrier.
-__device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t* cs, uint32_t* ds,
+__device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t* cs,
+                                             uint32_t cstride, uint32_t* ds,
                                              uint32_t* __restrict__ out, uint32_t npw) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nt = blockDim.x;
@@ -247,7 +254,7 @@ __device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t*
     const uint32_t dn = sh.dn;
     for (uint32_t i = tid; i < npw * dn; i += nt) {
         const uint32_t j = i / dn, k = i - j * dn;
-        const uint32_t* hi = cs + j * cw + qw;
+        const uint32_t* hi = cs + j * cstride + qw;
         uint32_t d = 0;
         for (uint32_t t = 0; t < sh.n_taps; ++t) {
             const uint32_t r = sh.q - sh.taps[t];
@@ -263,7 +270,7 @@ __device__ __forceinline__ void reduce_store(const ExtShape& sh, const uint32_t*
 
     for (uint32_t i = tid; i < npw * qw; i += nt) {
         const uint32_t j = i / qw, w = i - j * qw;
-        const uint32_t* c = cs + j * cw;
+        const uint32_t* c = cs + j * cstride;
         const uint32_t* hi = c + qw;
         const uint32_t* dd = ds + j * dn;
         uint32_t z = c[w] ^ hi[w] ^ (w < dn ? dd[w] : 0u);
@@ -458,48 +465,75 @@ __device__ __forceinline__ void reduce_store_padded(const ExtShape& sh, const ui
 // One work-group's share: npw consecutive block pairs of one stream with
 // shape sh (npw <= sh.ppw); xb, yb point at the first pair's blocks and outb
 // at its output (bytes; 4-byte aligned unless the shape is padded).  lds
-// holds sh.lds_words words.  Ends after the last global store, without a
-// barrier.
-template <int BW, bool PAD, bool RANK>
+// holds sh.lds_words words, plus group_pad_words(sh) with RMAJOR.  Ends after
+// the last global store, without a barrier.
+//
+// Items are (pair, sub-product, element group).  RMAJOR takes them rank-major
+// (lanes next to each other hold the same sub-product of different pairs), so
+// that with the ranked order the lanes of a wave share their number of
+// sum-of-halves levels and loop equally often; the staged blocks and the sums
+// then sit at padded per-pair strides (blocks + 4 words, sums + 1) so that the
+// pairs' words fall in different LDS banks.  Otherwise items are pair-major.
+template <int BW, bool PAD, uint32_t MINL, bool RMAJOR>
 __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint8_t* __restrict__ xb,
                                               const uint8_t* __restrict__ yb,
                                               uint8_t* __restrict__ outb, uint32_t npw,
                                               uint32_t* lds) {
+    static_assert(!(PAD && RMAJOR), "padded shapes keep their own staging layout");
     const uint32_t tid = threadIdx.x;
     const uint32_t nt = blockDim.x;  // sh.threads lanes
     const uint32_t nw = sh.nw, qw = sh.qw, cw = 2 * qw;
+    const uint32_t nws = RMAJOR ? nw + 4u : nw;  // staged words per pair
+    const uint32_t cws = RMAJOR ? cw + 1u : cw;  // sum words per pair
     const uint32_t* xg = reinterpret_cast<const uint32_t*>(xb);
     const uint32_t* yg = reinterpret_cast<const uint32_t*>(yb);
     // padded shapes: kPadSlack words after each staged area (raw copies)
-    const uint32_t area = (sh.stage ? sh.ppw * nw : 0) + (PAD ? kPadSlack : 0);
-    uint32_t* xs = lds;                               // [ppw][nw]   (staged X)
-    uint32_t* ys = xs + area;                         // [ppw][nw]   (staged Y)
-    uint32_t* cs = ys + area;                         // [ppw][2qw]  unreduced sums
-    uint32_t* ds = cs + sh.ppw * cw;                  // [ppw][dn]   second-pass words
+    const uint32_t area = (sh.stage ? sh.ppw * nws : 0) + (PAD ? kPadSlack : 0);
+    uint32_t* xs = lds;                               // [ppw][nws]  (staged X)
+    uint32_t* ys = xs + area;                         // [ppw][nws]  (staged Y)
+    uint32_t* cs = ys + area;                         // [ppw][cws]  unreduced sums
+    uint32_t* ds = cs + sh.ppw * cws;                 // [ppw][dn]   second-pass words
     uint32_t* hs = ds + sh.ppw * sh.dn;               // [ppw][qw]   C >> q (padded shapes)
 
-    for (uint32_t i = tid; i < npw * cw; i += nt) cs[i] = 0;
+    for (uint32_t i = tid; i < npw * cws; i += nt) cs[i] = 0;
     if constexpr (PAD) {
         stage_padded(sh, xb, yb, xs, ys, npw);  // padded shapes are always staged
     } else if (sh.stage) {
-        for (uint32_t i = tid; i < npw * nw; i += nt) {
-            xs[i] = xg[i];
-            ys[i] = yg[i];
+        if constexpr (RMAJOR) {
+            for (uint32_t j = 0; j < npw; ++j)
+                for (uint32_t k = tid; k < nw; k += nt) {
+                    xs[j * nws + k] = xg[j * nw + k];
+                    ys[j * nws + k] = yg[j * nw + k];
+                }
+        } else {
+            for (uint32_t i = tid; i < npw * nw; i += nt) {
+                xs[i] = xg[i];
+                ys[i] = yg[i];
+            }
         }
     }
     __syncthreads();
 
     // ---- sub-products ---------------------------------------------------
     const uint32_t per_pair = sh.np * sh.groups;
+    const uint32_t per_rank = npw * sh.groups;
     const uint32_t items = npw * per_pair;
     const uint32_t lmask = (1u << sh.levels) - 1u;
     for (uint32_t it = tid; it < items; it += nt) {
-        const uint32_t j = it / per_pair;
-        const uint32_t rem = it - j * per_pair;
-        const uint32_t p = rem / sh.groups;
-        const uint32_t g = rem - p * sh.groups;
+        uint32_t j, p, g;
+        if constexpr (RMAJOR) {
+            p = it / per_rank;
+            const uint32_t rem = it - p * per_rank;
+            j = rem / sh.groups;
+            g = rem - j * sh.groups;
+        } else {
+            j = it / per_pair;
+            const uint32_t rem = it - j * per_pair;
+            p = rem / sh.groups;
+            g = rem - p * sh.groups;
+        }
         uint32_t hi_mask, mid_mask;
-        path_masks<RANK>(p, sh.levels, hi_mask, mid_mask);
+        path_masks<MINL>(p, sh.levels, hi_mask, mid_mask);
         uint32_t acc[2 * BW];
 #pragma unroll
         for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
@@ -509,8 +543,8 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint8_t*
         for (uint32_t e = g * sh.epg; e < e_end; ++e) {
             uint32_t xo[BW], yo[BW];
             if (sh.stage) {  // operands from the LDS copy
-                form_operand<BW>(xo, xs + j * nw + e * qw, hi_mask, mid_mask);
-                form_operand<BW>(yo, ys + j * nw + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(xo, xs + j * nws + e * qw, hi_mask, mid_mask);
+                form_operand<BW>(yo, ys + j * nws + e * qw, hi_mask, mid_mask);
             } else {         // straight from HBM (one sub-product per element)
                 form_operand<BW>(xo, xg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
                 form_operand<BW>(yo, yg + (uint64_t)j * nw + e * qw, hi_mask, mid_mask);
@@ -518,13 +552,13 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint8_t*
             clmul_acc<BW>(xo, yo, acc);
         }
 
-        scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs + j * cw);
+        scatter_acc<BW>(acc, hi_mask, mid_mask, lmask, cs + j * cws);
     }
     __syncthreads();
     if constexpr (PAD)
         reduce_store_padded(sh, cs, hs, ds, outb, npw);
     else
-        reduce_store(sh, cs, ds, reinterpret_cast<uint32_t*>(outb), npw);
+        reduce_store(sh, cs, cws, ds, reinterpret_cast<uint32_t*>(outb), npw);
 }
 
 // One slice of one block pair, for pairs with more sub-products than a
@@ -534,7 +568,7 @@ __device__ __forceinline__ void extract_group(const ExtShape& sh, const uint8_t*
 // slices' parts XOR to the rest) is stored at part; combine_kernel adds the
 // parts and reduces.  Only the elements the slice touches are staged.  Ends
 // after the last global store, without a barrier.
-template <int BW, bool RANK>
+template <int BW, uint32_t MINL>
 __device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t* __restrict__ xg,
                                               const uint32_t* __restrict__ yg,
                                               uint32_t* __restrict__ part, uint32_t item0,
@@ -563,7 +597,7 @@ __device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t
         const uint32_t e = gi / sh.np;
         const uint32_t p = gi - e * sh.np;
         uint32_t hi_mask, mid_mask;
-        path_masks<RANK>(p, sh.levels, hi_mask, mid_mask);
+        path_masks<MINL>(p, sh.levels, hi_mask, mid_mask);
         uint32_t acc[2 * BW];
 #pragma unroll
         for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
@@ -589,7 +623,7 @@ __device__ __forceinline__ void extract_slice(const ExtShape& sh, const uint32_t
 // unreduced sum (2qw words, the other slices' parts XOR to the rest) is
 // stored at part, and combine_padded_kernel adds the parts, reduces and
 // stores the pair.  Ends after the last global store, without a barrier.
-template <int BW, bool RANK>
+template <int BW, uint32_t MINL>
 __device__ __forceinline__ void extract_slice_padded(const ExtShape& sh,
                                                      const uint8_t* __restrict__ xb,
                                                      const uint8_t* __restrict__ yb,
@@ -613,7 +647,7 @@ __device__ __forceinline__ void extract_slice_padded(const ExtShape& sh,
         const uint32_t e = it / sh.np;
         const uint32_t p = it - e * sh.np;
         uint32_t hi_mask, mid_mask;
-        path_masks<RANK>(p, sh.levels, hi_mask, mid_mask);
+        path_masks<MINL>(p, sh.levels, hi_mask, mid_mask);
         uint32_t acc[2 * BW];
 #pragma unroll
         for (int w = 0; w < 2 * BW; ++w) acc[w] = 0;
@@ -638,14 +672,15 @@ ext_ip_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
     if (pair0 >= n_pairs) return;
     const uint64_t left = n_pairs - pair0;
     const uint32_t npw = left < sh.ppw ? (uint32_t)left : sh.ppw;
-    extract_group<BW, PAD, true>(sh, x + pair0 * sh.nbytes, y + pair0 * sh.nbytes,
-                                 out + pair0 * sh.qbytes, npw, lds);
+    extract_group<BW, PAD, PAD ? 5u : 2u, !PAD>(sh, x + pair0 * sh.nbytes, y + pair0 * sh.nbytes,
+                                                out + pair0 * sh.qbytes, npw, lds);
 }
 
-// Whether the batched kernel of base size BW ranks its sub-products: only
-// bases of at most 8 words reach five or more levels in practice.
+// From how many levels the batched kernel of base size BW ranks its
+// sub-products (items pair-major): only bases of at most 8 words reach five
+// or more levels in practice.
 template <int BW>
-constexpr bool kBatchRank = BW <= 8;
+constexpr uint32_t kBatchRank = BW <= 8 ? 5u : 100u;
 
 // Batched form: a persistent grid drains a device work queue of tiles
 // (stream, first pair, pair count; or one slice of one pair) shared by many
@@ -678,7 +713,8 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
                                   reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
                                   tile.item0, tile.n_items, lds);
         } else
-            extract_group<BW, PAD, kBatchRank<BW>>(sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
+            extract_group<BW, PAD, kBatchRank<BW>, false>(sh, xb, yb, st.out + tile.out_off,
+                                                          tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
 }
@@ -734,7 +770,7 @@ combine_kernel(const BatchStream* __restrict__ streams, const CombineJob* __rest
             }
         }
         __syncthreads();
-        reduce_store(sh, lds, lds + cw, reinterpret_cast<uint32_t*>(st.out + job.out_byte0), 1);
+        reduce_store(sh, lds, cw, lds + cw, reinterpret_cast<uint32_t*>(st.out + job.out_byte0), 1);
         __syncthreads();  // lds is reused by the next job
     }
 }
@@ -853,12 +889,16 @@ hipError_t launch_bw(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint
                      uint64_t n_pairs, hipStream_t stream) {
     const uint64_t groups = (n_pairs + s.ppw - 1) / s.ppw;
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-    if (s.padded)
+    if (s.padded) {
         hipLaunchKernelGGL((ext_ip_kernel<BW, true>), dim3((uint32_t)groups), dim3(s.threads),
                            s.lds_words * 4u, stream, x, y, out, n_pairs, s);
-    else
+    } else {
+        // the rank-major layout's padded strides: 4 words per staged block and
+        // side, 1 per sum
+        const uint32_t pad = s.ppw * (1u + (s.stage ? 8u : 0u));
         hipLaunchKernelGGL((ext_ip_kernel<BW, false>), dim3((uint32_t)groups), dim3(s.threads),
-                           s.lds_words * 4u, stream, x, y, out, n_pairs, s);
+                           (s.lds_words + pad) * 4u, stream, x, y, out, n_pairs, s);
+    }
     return hipGetLastError();
 }
 
