@@ -104,7 +104,9 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
                 return !padded || (uint64_t)pp * r.nw <= (uint64_t)kPadRegs * threads;
             };
             while (ppw > 1 && (lds_words(ppw) * 4 > kMaxLdsBytes || !regs_ok(ppw))) --ppw;
-            if (lds_words(ppw) * 4 > 65536 || !regs_ok(ppw)) continue;
+            // (unpadded shapes add their rank-major padding, see group_lds_bytes)
+            const uint32_t pad = padded ? 0u : ppw * (1u + (stage_try ? 8u : 0u));
+            if ((lds_words(ppw) + pad) * 4 > 65536 || !regs_ok(ppw)) continue;
             const uint64_t items = (uint64_t)ppw * per_pair;
             const uint64_t rounds = (items + threads - 1) / threads;
             const double util = (double)items / (double)(rounds * threads);
@@ -522,7 +524,7 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
              "\"staged\": %u, \"lds_bytes\": %u, \"threads\": %d, \"padded\": %u, "
              "\"slot_words\": %u, \"kernel\": \"%s\"%s}",
              (unsigned long long)c->n_bits, c->m_bits, s.n_e, s.bw * 32, s.levels, s.np, s.ppw,
-             s.groups, s.stage, s.lds_words * 4, s.threads, s.padded, s.qw, "word", small);
+             s.groups, s.stage, qext::group_lds_bytes(s), s.threads, s.padded, s.qw, "word", small);
     return EXT_OK;
 }
 

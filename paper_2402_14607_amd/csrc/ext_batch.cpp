@@ -565,7 +565,7 @@ int ext_batch_create(const ext_batch_item* items, uint32_t n_items, const ext_pa
                 std::vector<std::pair<double, BatchTile>> tl;
                 for (uint32_t si : kv.second) {
                     const BatchStream& st = b->streams[si];
-                    g.lds_bytes = std::max(g.lds_bytes, st.shape.lds_words * 4);
+                    g.lds_bytes = std::max(g.lds_bytes, qext::group_lds_bytes(st.shape));
                     // cost of one tile ~ base products per lane-slot it occupies
                     const double per_pair = (double)st.shape.np * st.shape.n_e;
                     for (uint64_t p0 = 0; p0 < st.n_pairs; p0 += st.shape.ppw) {

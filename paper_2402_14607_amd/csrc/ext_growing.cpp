@@ -391,7 +391,7 @@ int plan_blocks(ext_growing* g, uint64_t q0, uint64_t k, const uint8_t* xs, cons
         if (!sliced) {
             const uint64_t cost = ((uint64_t)s.np * s.groups + s.threads - 1) / s.threads * s.epg;
             gr.tiles.push_back({cost, BatchTile{(uint32_t)l, 1, 0, 0, 0, 0}});
-            gr.lds = std::max(gr.lds, s.lds_words * 4);
+            gr.lds = std::max(gr.lds, qext::group_lds_bytes(s));
         } else {
             const uint32_t es = d.slice_elems, cw = 2 * s.qw;
             const uint32_t n_parts = (s.n_e + es - 1) / es;

@@ -53,6 +53,15 @@ struct PlanKnobs {
                           // bounds the base product (0: 15)
 };
 
+// LDS bytes one work-group of shape s takes in the plain and batched kernels:
+// lds_words, plus, for unpadded shapes (whose pairs the kernels lay out
+// rank-major at padded strides), 4 words per staged block and side and 1 per
+// sum, for each pair.
+inline uint32_t group_lds_bytes(const ExtShape& s) {
+    const uint32_t pad = s.padded ? 0u : s.ppw * (1u + (s.stage ? 8u : 0u));
+    return (s.lds_words + pad) * 4u;
+}
+
 // Fills *s for q, n_e and the taps; returns false if the shape is outside
 // what the kernel supports.
 bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,

@@ -133,10 +133,10 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
 // operand, 2^(L - c) scatter offsets): lanes of a wave, which take
 // consecutive p, then loop about equally often instead of as often as the
 // wave's worst path.  The ranked masks come from a table built at compile
-// time.  MINL sets from how many levels a kernel ranks: the plain kernel of
-// unpadded shapes takes its items rank-major (extract_group) and ranks from
-// two levels on, padded shapes and the batched kernel (items pair-major) from
-// five, and the batched kernel only for bases of at most 8 words: at 16 words,
+// time.  MINL sets from how many levels a kernel ranks: unpadded shapes'
+// whole-pair work-groups take their items rank-major (extract_group) and rank
+// from two levels on; padded shapes and slices (items pair-major) from five,
+// and in the batched kernel only for bases of at most 8 words: at 16 words,
 // where no shape reaches five levels, the variant that carried the ranking
 // changed none of the loops' instruction counts and still measured 2-5 %
 // slower on its launches.  At three levels a wave spans every path either way and the plain
@@ -676,9 +676,10 @@ ext_ip_kernel(const uint8_t* __restrict__ x, const uint8_t* __restrict__ y,
                                                 out + pair0 * sh.qbytes, npw, lds);
 }
 
-// From how many levels the batched kernel of base size BW ranks its
-// sub-products (items pair-major): only bases of at most 8 words reach five
-// or more levels in practice.
+// From how many levels the batched kernel of base size BW ranks the
+// sub-products of its slices and padded tiles (items pair-major): only bases
+// of at most 8 words reach five or more levels in practice.  Unpadded whole
+// tiles go rank-major, as in the plain kernel.
 template <int BW>
 constexpr uint32_t kBatchRank = BW <= 8 ? 5u : 100u;
 
@@ -713,8 +714,8 @@ ext_batch_kernel(const BatchStream* __restrict__ streams, const BatchTile* __res
                                   reinterpret_cast<const uint32_t*>(yb), part + tile.out_off,
                                   tile.item0, tile.n_items, lds);
         } else
-            extract_group<BW, PAD, kBatchRank<BW>, false>(sh, xb, yb, st.out + tile.out_off,
-                                                          tile.npw, lds);
+            extract_group<BW, PAD, PAD ? kBatchRank<BW> : 2u, !PAD>(
+                sh, xb, yb, st.out + tile.out_off, tile.npw, lds);
         __syncthreads();  // LDS and `next` are reused by the next tile
     }
 }
@@ -889,16 +890,12 @@ hipError_t launch_bw(const ExtShape& s, const uint8_t* x, const uint8_t* y, uint
                      uint64_t n_pairs, hipStream_t stream) {
     const uint64_t groups = (n_pairs + s.ppw - 1) / s.ppw;
     if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-    if (s.padded) {
+    if (s.padded)
         hipLaunchKernelGGL((ext_ip_kernel<BW, true>), dim3((uint32_t)groups), dim3(s.threads),
-                           s.lds_words * 4u, stream, x, y, out, n_pairs, s);
-    } else {
-        // the rank-major layout's padded strides: 4 words per staged block and
-        // side, 1 per sum
-        const uint32_t pad = s.ppw * (1u + (s.stage ? 8u : 0u));
+                           group_lds_bytes(s), stream, x, y, out, n_pairs, s);
+    else
         hipLaunchKernelGGL((ext_ip_kernel<BW, false>), dim3((uint32_t)groups), dim3(s.threads),
-                           (s.lds_words + pad) * 4u, stream, x, y, out, n_pairs, s);
-    }
+                           group_lds_bytes(s), stream, x, y, out, n_pairs, s);
     return hipGetLastError();
 }
 

@@ -351,7 +351,7 @@ int launch_cycle(ext_server* s, std::unique_lock<std::mutex>& lk) {
             g = &gb.back();
         }
         if (g->tiles.empty()) g->lds = 0;
-        g->lds = std::max(g->lds, sh.lds_words * 4);
+        g->lds = std::max(g->lds, qext::group_lds_bytes(sh));
         const uint64_t slot0 = r.first_pair % c.R;
         if (c.slices > 1) {
             const uint32_t items = sh.np * sh.n_e;
