@@ -130,18 +130,18 @@ __device__ __forceinline__ void form_operand(uint32_t (&r)[BW], const uint32_t* 
 // level (0 = low halves, 1 = high halves, 2 = sum of halves).  Within that
 // range the 3^L paths are ranked by their number c of sum-of-halves levels,
 // which sets the work of a lane outside its base product (2^c pieces per
-// operand, 2^(L - c) scatter offsets): lanes of a wave, which take
-// consecutive p, then loop about equally often instead of as often as the
-// wave's worst path.  The ranked masks come from a table built at compile
-// time.  MINL sets from how many levels a kernel ranks: unpadded shapes'
-// whole-pair work-groups take their items rank-major (extract_group) and rank
-// from two levels on; padded shapes and slices (items pair-major) from five,
-// and in the batched kernel only for bases of at most 8 words: at 16 words,
-// where no shape reaches five levels, the variant that carried the ranking
-// changed none of the loops' instruction counts and still measured 2-5 %
-// slower on its launches.  At three levels a wave spans every path either way and the plain
-// digits measured faster; at six the ranking cut the forward-block-stress
-// launch by 14 %.
+// operand, 2^(L - c) scatter offsets): lanes of a wave holding neighbouring
+// ranks then loop about equally often instead of as often as the wave's
+// worst path.  The ranked masks come from a table built at compile time.
+// MINL sets from how many levels a kernel ranks.  Unpadded shapes' whole-pair
+// work-groups take their items rank-major (extract_group), so a wave holds a
+// few neighbouring ranks, and rank from two levels on (paper block, three
+// levels: 0.500 -> 0.463 ms per launch).  Padded shapes and slices take their
+// items pair-major, so a wave spans every path of a pair unless L is large,
+// and rank from five levels on (forward-block stress, six levels: -14 %); in
+// the batched kernel only with bases of at most 8 words: at 16 words, where no
+// shape reaches five levels, the variant that carried the ranking changed
+// none of the loops' instruction counts and still measured 2-5 % slower.
 constexpr uint32_t kRankMin = 2, kRankMax = 7;
 constexpr uint32_t kRankedCount = 9 + 27 + 81 + 243 + 729 + 2187;  // 3^2 .. 3^7
 struct RankedPaths {
