@@ -163,10 +163,10 @@ def test_shapes_full(dev, m, n_e):
     assert np.array_equal(got, oracle.ext_blocks(x, y, n, m))
 
 
-# deep Karatsuba trees reached with small fixed bases: 5 to 7 levels take the
-# sub-products in the ranked order (by number of sum-of-halves levels), 4 and
-# 8 in base-3 digit order; a fixed base also keeps the default plan (no
-# latency plan) whatever the pair count
+# deep Karatsuba trees reached with small fixed bases: up to 7 levels take the
+# sub-products in the ranked order (by number of sum-of-halves levels), 8 in
+# base-3 digit order; a fixed base also keeps the default plan (no latency
+# plan) whatever the pair count
 RANKED_SHAPES = [(1024, 2, 32), (2048, 2, 64), (2048, 1, 32), (4096, 2, 32), (8192, 1, 32),
                  (1024, 3, 64)]
 
