@@ -103,7 +103,9 @@ bool plan_shape(uint32_t q, uint32_t n_e, const uint32_t* taps, uint32_t n_taps,
             auto regs_ok = [&](uint32_t pp) {
                 return !padded || (uint64_t)pp * r.nw <= (uint64_t)kPadRegs * threads;
             };
-            while (ppw > 1 && (lds_words(ppw) * 4 > kMaxLdsBytes || !regs_ok(ppw))) --ppw;
+            // (a pair count fixed by the knobs may use up to the 64 KiB limit)
+            const uint64_t lds_cap = knobs.ppw ? 65536u : kMaxLdsBytes;
+            while (ppw > 1 && ((uint64_t)lds_words(ppw) * 4 > lds_cap || !regs_ok(ppw))) --ppw;
             // (unpadded shapes add their rank-major padding, see group_lds_bytes)
             const uint32_t pad = padded ? 0u : ppw * (1u + (stage_try ? 8u : 0u));
             if ((lds_words(ppw) + pad) * 4 > 65536 || !regs_ok(ppw)) continue;

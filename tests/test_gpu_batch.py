@@ -159,6 +159,29 @@ def test_autotuned_plan_is_bit_identical(dev):
         assert np.array_equal(o, want)
 
 
+@pytest.mark.parametrize("threads,ppw", [(384, 14), (448, 16), (576, 21), (640, 23)])
+def test_fixed_pairs_per_workgroup_beyond_default_lds(dev, threads, ppw):
+    """A pair count fixed by the plan knobs is kept up to the 64 KiB LDS
+    limit (36-60 KiB here, above the default plan's 32 KiB target), on work
+    groups of 6, 7, 9 and 10 waves: 300 pairs (a ragged last group) equal the
+    oracle's bytes."""
+    import torch
+
+    w = inputs.plain_workload(8192, 2048, 300, 63, 64)
+    x, y = to_dev(dev, w.x), to_dev(dev, w.y)
+    out = torch.zeros(300 * 256, dtype=torch.uint8, device=dev)
+    with binding.Extractor(8192, 2048, device_memory=True, base_bits=256, threads=threads,
+                           pairs_per_group=ppw,
+                           stream=torch.cuda.current_stream(dev).cuda_stream) as ex:
+        plan = json.loads(ex.describe())
+        say("plan %s" % plan)
+        assert (plan["threads"], plan["pairs_per_workgroup"]) == (threads, ppw)
+        assert 32768 < plan["lds_bytes"] <= 65536
+        ex.extract(x, y, out, 300)
+        ex.sync()
+    assert np.array_equal(out.cpu().numpy(), oracle.ext_blocks(w.x, w.y, 8192, 2048))
+
+
 def test_wide_workgroups_large_field(dev):
     """1024-lane work-groups (one round for the 729 items of an m = 16384
     pair) give the oracle's bytes in the plain form (the served-form tests
