@@ -5,9 +5,11 @@ per source, seeds 11 and 12).
 
 One step = one pass of the whole hot path (one ext_extract over all 65536
 block pairs, inputs resident in HBM, outputs written to HBM).  Prints one
-JSON line.
+JSON line.  The warmup runs at least W steps and keeps going until the GPU has
+been busy for --warm-seconds (0.3 s by default), so that the K timed steps run
+at settled clocks.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--warm-seconds S]
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ sys.path.insert(0, ROOT)
 N_BITS = 8192
 M_BITS = 2048
 N_PAIRS = 65536
+WARM_S = 0.3  # default least time the headline's warmup keeps the GPU busy
 # 256 CUs x 64 lanes x 2.4 GHz x 32 bit-MACs per v_bitop3_b32 lane-op
 PEAK_BITMAC_T = 256 * 64 * 2.4e9 * 32 / 1e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_14607_amd", "csrc", "ext_kernels.hip")
@@ -762,6 +765,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warm-seconds", type=float, default=WARM_S,
+                    help="least GPU-busy time of the headline warmup (its steps continue "
+                         "past --warmup until then)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-point", action="store_true")
     ap.add_argument("--no-growing", action="store_true", help="skip the Algorithm 2 leg")
@@ -835,10 +841,25 @@ def main():
     plan = json.loads(ex.describe())
     log("plan: %s" % json.dumps(plan))
 
+    # at least W warmup steps, continued in rounds of 20 until they have kept
+    # the GPU busy for --warm-seconds (counter passes, which need no settled
+    # clocks, pass 0): the GPU is first used here (after the
+    # CPU baseline), and coming out of idle it takes tens of milliseconds to
+    # raise its clocks, so that a few steps alone leave the timed ones on the
+    # ramp rather than at the steady rate a continuously running extractor has
+    warm_steps, t_warm = 0, time.perf_counter()
     for _ in range(args.warmup):
         ex.extract(x, y, out, N_PAIRS)
+        warm_steps += 1
     torch.cuda.synchronize()
-    log("warmup done (%d steps)" % args.warmup)
+    while time.perf_counter() - t_warm < args.warm_seconds:
+        for _ in range(20):
+            ex.extract(x, y, out, N_PAIRS)
+        warm_steps += 20
+        torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t_warm
+    log("warmup done (%d steps, %.3f s; at least %d steps and %.2f s)"
+        % (warm_steps, warm_s, args.warmup, args.warm_seconds))
 
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -935,6 +956,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_run": {"steps": warm_steps, "seconds": round(warm_s, 3),
+                       "min_seconds": args.warm_seconds},
         "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
