@@ -560,8 +560,10 @@ int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t 
  * product size, Karatsuba levels, work-group shape) into buf (1024 bytes
  * suffice).  A word-level context planned without fixed knobs also has a
  * latency plan ("small_launch": one element per lane item, half the base
- * size) that plain and streaming launches take when the default plan would
- * give fewer work-groups than the GPU has compute units. */
+ * size, or smaller while a pair's n_e * 3^levels items fit in one
+ * work-group's lanes) that plain and streaming launches take when the
+ * default plan would give fewer work-groups than the GPU has compute
+ * units. */
 int ext_describe(const ext_ctx *c, char *buf, size_t cap);
 
 /* Diagnostic: the device's measured issue rate of the extraction kernel's

@@ -468,17 +468,33 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         c->shape = ts;
     }
     // the latency plan (when the caller fixed no plan knob): every element
-    // its own lane item, base half the default's (one more Karatsuba level)
+    // its own lane item, base half the default's (one more Karatsuba level),
+    // halved again while a pair's items (n_e * 3^levels) still fit in one
+    // round of the group's lanes, so that each lane's chain is one shorter
+    // base product; a base whose items need a second round is not taken
     if (!c->bitslice && !p->base_bits && !p->groups && !p->pairs_per_group) {
         int cus = 0;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const ExtShape& d = c->shape;
-        qext::PlanKnobs sk{d.bw > 1 ? d.bw / 2 : 1, d.n_e, 0, d.threads, d.padded};
+        // (inputs are checked against the default plan's alignment, which
+        // the latency plan's must divide)
+        auto small_plan = [&](uint32_t bw, ExtShape* ss) {
+            const qext::PlanKnobs sk{bw, d.n_e, 0, d.threads, d.padded};
+            return qext::plan_shape(m_bits, d.n_e, taps.data(), (uint32_t)taps.size(), sk, ss) &&
+                   ss->padded == d.padded && ss->qw == d.qw && d.align % ss->align == 0;
+        };
+        auto one_round = [](const ExtShape& ss) {
+            return (uint64_t)ss.np * ss.groups <= ss.threads;
+        };
+        uint32_t bw = d.bw > 1 ? d.bw / 2 : 1;
         ExtShape ss;
-        if (cus > 0 && qext::plan_shape(m_bits, d.n_e, taps.data(), (uint32_t)taps.size(), sk, &ss) &&
-            ss.padded == d.padded && ss.qw == d.qw && d.align % ss.align == 0) {
-            // (inputs are checked against the default plan's alignment, which
-            // the latency plan's divides)
+        if (cus > 0 && small_plan(bw, &ss)) {
+            while (bw > 1 && one_round(ss)) {
+                ExtShape s2;
+                if (!small_plan(bw / 2, &s2) || !one_round(s2)) break;
+                ss = s2;
+                bw /= 2;
+            }
             c->small = ss;
             c->has_small = true;
             c->cus = (uint32_t)cus;

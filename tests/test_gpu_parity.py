@@ -198,7 +198,8 @@ def test_latency_plan_equals_default_plan(dev, m, n_e):
     """A launch with fewer work-groups than CUs takes the context's latency
     plan (ext_describe's small_launch); its bytes equal the default plan's
     (a context with the base fixed at its default size has no latency plan)
-    and the oracle's."""
+    and the oracle's.  The plan's base is half the default's, or smaller
+    while a pair's n_e * 3^levels items fit in one round of the lanes."""
     import json
 
     import torch
@@ -217,6 +218,13 @@ def test_latency_plan_equals_default_plan(dev, m, n_e):
             plan["small_launch"]["below_workgroups"]
         small = gpu_extract(dev, x, y, n, m, ex=ex)
         base = plan["base_bits"]
+        sl = plan["small_launch"]
+        assert sl["element_groups"] == n_e and sl["base_bits"] <= max(32, base // 2)
+        fits = lambda levels: n_e * 3 ** levels <= plan["threads"]  # noqa: E731
+        if sl["base_bits"] < base // 2:
+            assert fits(sl["karatsuba_levels"])
+        if sl["base_bits"] > 32 and fits(sl["karatsuba_levels"]):
+            assert not fits(sl["karatsuba_levels"] + 1)
     with binding.Extractor(n, m, device_memory=True, stream=st, base_bits=base) as ex:
         assert "small_launch" not in json.loads(ex.describe())
         default = gpu_extract(dev, x, y, n, m, ex=ex)
