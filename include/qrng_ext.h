@@ -558,12 +558,13 @@ int ext_serve_simulate(const ext_sim_config *cfg, ext_sim_result *res, uint64_t 
 
 /* Write a one-line JSON description of the context's launch plan (base
  * product size, Karatsuba levels, work-group shape) into buf (1024 bytes
- * suffice).  A word-level context planned without fixed knobs also has a
- * latency plan ("small_launch": one element per lane item, half the base
- * size, or smaller while a pair's n_e * 3^levels items fit in one
- * work-group's lanes) that plain and streaming launches take when the
- * default plan would give fewer work-groups than the GPU has compute
- * units. */
+ * suffice).  A word-level context planned without fixed knobs also has
+ * latency plans (one element per lane item; half the base size, and smaller
+ * ones while a pair's n_e * 3^levels items fit in one work-group's lanes)
+ * that plain and streaming launches take when the default plan would give
+ * fewer work-groups than the GPU has compute units: the smallest base whose
+ * launch stays within two work-groups per compute unit, else the half-size
+ * one.  "small_launch" describes the smallest and lists every base. */
 int ext_describe(const ext_ctx *c, char *buf, size_t cap);
 
 /* Diagnostic: the device's measured issue rate of the extraction kernel's

@@ -143,11 +143,14 @@ struct ext_ctx {
     uint32_t b = 8;
     std::vector<uint32_t> taps;  // non-leading nonzero exponents, decreasing
     ExtShape shape{};
-    // latency plan for launches that would leave CUs idle: one element per
-    // lane item and one more Karatsuba level, so a lane's chain is one short
-    // base product (word-level kernel only; same outputs)
-    ExtShape small{};
-    bool has_small = false;
+    // latency plans for launches that would leave CUs idle: one element per
+    // lane item and one or more Karatsuba levels beyond the default, so a
+    // lane's chain is one short base product (word-level kernel only; same
+    // outputs); small[0] has half the default base, each next one half the
+    // base before it
+    static constexpr uint32_t kMaxSmall = 4;
+    ExtShape small[kMaxSmall]{};
+    uint32_t n_small = 0;
     uint32_t cus = 0;
     bool bitslice = false;  // plain/streaming launches take the bit-sliced kernel
     uint32_t kernel = EXT_KERNEL_AUTO;  // ext_params.kernel, for streams of other shapes
@@ -242,13 +245,21 @@ int launch(ext_ctx* c, const ExtShape& shape, bool bitslice, const void* x, cons
 }
 
 int launch(ext_ctx* c, const void* x, const void* y, void* out, uint64_t n_pairs) {
-    if (!c->bitslice && c->has_small) {
-        // fewer work-groups than CUs: the latency plan spreads the same pairs
-        // over more of them, each lane one base product
+    if (!c->bitslice && c->n_small) {
+        // fewer work-groups than CUs: a latency plan spreads the same pairs
+        // over more of them, each lane one base product; the smallest base
+        // whose launch stays within two work-groups per CU (smaller bases do
+        // more work in all, which a fuller GPU would pay for), else the
+        // half-size base
         const uint64_t wgs = (n_pairs + c->shape.ppw - 1) / c->shape.ppw;
-        const uint64_t wgs_small = (n_pairs + c->small.ppw - 1) / c->small.ppw;
-        if (wgs < c->cus && wgs_small > wgs)
-            return launch(c, c->small, false, x, y, out, n_pairs);
+        if (wgs < c->cus) {
+            for (uint32_t i = c->n_small; i-- > 0;) {
+                const ExtShape& sm = c->small[i];
+                const uint64_t w = (n_pairs + sm.ppw - 1) / sm.ppw;
+                if (w > wgs && (w <= 2ull * c->cus || i == 0))
+                    return launch(c, sm, false, x, y, out, n_pairs);
+            }
+        }
     }
     return launch(c, c->shape, c->bitslice, x, y, out, n_pairs);
 }
@@ -489,14 +500,16 @@ int ext_create(uint64_t n_bits, uint32_t m_bits, const ext_params* p, ext_ctx** 
         uint32_t bw = d.bw > 1 ? d.bw / 2 : 1;
         ExtShape ss;
         if (cus > 0 && small_plan(bw, &ss)) {
-            while (bw > 1 && one_round(ss)) {
+            c->small[0] = ss;
+            c->n_small = 1;
+            while (bw > 1 && c->n_small < ext_ctx::kMaxSmall && one_round(ss)) {
                 ExtShape s2;
                 if (!small_plan(bw / 2, &s2) || !one_round(s2)) break;
-                ss = s2;
                 bw /= 2;
+                if (s2.bw == ss.bw) continue;  // the base target rounded to the same size
+                ss = s2;
+                c->small[c->n_small++] = ss;
             }
-            c->small = ss;
-            c->has_small = true;
             c->cus = (uint32_t)cus;
         }
     }
@@ -530,12 +543,21 @@ int ext_describe(const ext_ctx* c, char* buf, size_t cap) {
                  qext::kThreads, qext::bitslice_lds_words(s) * 4, ec, levels, piece, subs);
         return EXT_OK;
     }
-    char small[160] = "";
-    if (c->has_small)
+    // small_launch: the smallest-base latency plan, and the bases of all of them
+    char small[256] = "";
+    if (c->n_small) {
+        const ExtShape& sm = c->small[c->n_small - 1];
+        char bases[64] = "";
+        size_t used = 0;
+        for (uint32_t i = 0; i < c->n_small && used < sizeof bases; ++i)
+            used += (size_t)snprintf(bases + used, sizeof bases - used, "%s%u", i ? ", " : "",
+                                     c->small[i].bw * 32);
         snprintf(small, sizeof small,
                  ", \"small_launch\": {\"below_workgroups\": %u, \"base_bits\": %u, "
-                 "\"karatsuba_levels\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u}",
-                 c->cus, c->small.bw * 32, c->small.levels, c->small.ppw, c->small.groups);
+                 "\"karatsuba_levels\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "
+                 "\"bases\": [%s], \"smallest_within_workgroups\": %u}",
+                 c->cus, sm.bw * 32, sm.levels, sm.ppw, sm.groups, bases, 2u * c->cus);
+    }
     snprintf(buf, cap,
              "{\"n\": %llu, \"m\": %u, \"n_e\": %u, \"base_bits\": %u, \"karatsuba_levels\": %u, "
              "\"subproducts\": %u, \"pairs_per_workgroup\": %u, \"element_groups\": %u, "

@@ -232,6 +232,41 @@ def test_latency_plan_equals_default_plan(dev, m, n_e):
     assert np.array_equal(small, oracle.ext_blocks(x, y, n, m))
 
 
+@pytest.mark.parametrize("pairs", [512, 3000, 20000])
+def test_latency_plans_by_launch_size(dev, pairs):
+    """n = 1024, m = 256: the default plan packs 256 pairs per work-group, so
+    launches up to 65279 pairs are below one work-group per CU (256 on
+    MI355X) and take a latency plan: the 32-bit base while its launch stays
+    within two work-groups per CU (512 pairs: 256 work-groups), the 64-bit
+    one at 3000 pairs (429), the half-size 128-bit one at 20000 (953).
+    Every launch size gives the default plan's bytes, and sampled pairs the
+    oracle's."""
+    import json
+
+    import torch
+
+    n, m = 1024, 256
+    rng = np.random.Generator(np.random.PCG64(7100 + pairs))
+    x = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    y = rng.integers(0, 256, pairs * n // 8, dtype=np.uint8)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    with binding.Extractor(n, m, device_memory=True, stream=st) as ex:
+        plan = json.loads(ex.describe())
+        say("pairs=%d: %s" % (pairs, plan))
+        assert plan["small_launch"]["bases"] == [128, 64, 32]
+        assert plan["small_launch"]["smallest_within_workgroups"] == \
+            2 * plan["small_launch"]["below_workgroups"]
+        got = gpu_extract(dev, x, y, n, m, ex=ex)
+    with binding.Extractor(n, m, device_memory=True, stream=st, base_bits=256) as ex:
+        assert "small_launch" not in json.loads(ex.describe())
+        default = gpu_extract(dev, x, y, n, m, ex=ex)
+    assert np.array_equal(got, default)
+    idx = np.unique(np.concatenate([[0, pairs - 1], rng.integers(0, pairs, 30)])).astype(np.uint64)
+    want = oracle.ext_sampled(x, y, idx, n, m)
+    qb = m // 8
+    assert np.array_equal(np.concatenate([got[int(i) * qb:(int(i) + 1) * qb] for i in idx]), want)
+
+
 # degrees that are not multiples of 32: elements sit at byte (not word)
 # offsets, are re-laid out in zero-padded 32-bit slots, and outputs are
 # q/8 bytes per pair at byte offsets; and multiples of 32 whose word count
